@@ -518,7 +518,7 @@ static void band_solve(const band_chol *c, double *x) {
 /* the problem object                                                 */
 /* ------------------------------------------------------------------ */
 typedef struct {
-    int m, n1;            /* elements per side, interior nodes per side (m-1) */
+    int m, n1;            /* n1 interior nodes per side; m = n1 + 1 */
     long n;
     double *S;            /* Q1 operator by offset, radius 1 */
     double *Sfact;        /* dense Cholesky at the coarsest level, else NULL */
@@ -609,10 +609,15 @@ static int build_blocks(or_problem *P) {
 
 /*
  * V-cycle hierarchy for the degree-1 coarse problem (Section 3.2): level 0 is
- * A_{plow} itself; a coarser level exists while the element count is even and
- * larger than 2; its operator is the Galerkin product P^T A P with P the
- * bilinear (trilinear) interpolation of interior nodes; the coarsest level is
- * solved by a dense Cholesky factorisation.
+ * A_{plow} itself.  The paper fixes only "standard" h -> 2h coarsening and
+ * analyses three grids; the reading used here, which needs no assumption on
+ * m, is: the coarse nodes of a level are its odd-indexed interior nodes
+ * (0-based) in every direction, P is linear interpolation between them (the
+ * boundary value being zero), the coarse operator is the Galerkin product
+ * P^T A P, and coarsening continues down to one node per direction, which is
+ * solved exactly.  For m a power of two this is standard full coarsening of
+ * the uniform mesh (and P^T A P equals rediscretisation for kappa = 1); for
+ * other m the last coarse cell next to the boundary is narrower.
  */
 static double interp_weight(int i_fine, int I_coarse) {
     /* fine interior node i sits at grid node i+1, coarse node I at fine grid
@@ -625,8 +630,8 @@ static double interp_weight(int i_fine, int I_coarse) {
 
 static int build_levels(or_problem *P) {
     int d = P->d;
-    int nl = 1, mm = P->m;
-    while (mm % 2 == 0 && mm > 2) { mm /= 2; nl++; }
+    int nl = 1, nn = P->m - 1;
+    while (nn > 1) { nn /= 2; nl++; }
     P->nlev = nl;
     P->lev = calloc(nl, sizeof(or_level));
     long W3 = ipow(3, d);
@@ -636,7 +641,7 @@ static int build_levels(or_problem *P) {
     int ix[OR_MAXD], IX[OR_MAXD], a[OR_MAXD], jx[OR_MAXD], o[OR_MAXD], JX[OR_MAXD], bb[OR_MAXD], oc[OR_MAXD];
     for (int l = 1; l < nl; l++) {
         or_level *F = &P->lev[l - 1], *C = &P->lev[l];
-        C->m = F->m / 2; C->n1 = C->m - 1; C->n = ipow(C->n1, d);
+        C->n1 = F->n1 / 2; C->m = C->n1 + 1; C->n = ipow(C->n1, d);
         C->S = calloc(C->n * W3, sizeof(double));
         /* A_c(I,J) = sum_{i,j} P(i,I) A_f(i,j) P(j,J) */
         for (long I = 0; I < C->n; I++) {

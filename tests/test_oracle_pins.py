@@ -359,35 +359,37 @@ def test_galerkin_equals_rediscretisation_and_vcycle_rate():
 
 
 def _interp_1d(nf):
-    """Dense bilinear-interpolation factor from (nf-1)/2 coarse to nf fine
-    interior nodes of a uniform 1-D grid (coarse node I at fine node 2I+1)."""
-    nc = (nf - 1) // 2
+    """Dense linear-interpolation factor from the odd-indexed fine interior
+    nodes (coarse node I = fine node 2I+1) to all nf fine interior nodes."""
+    nc = nf // 2
     Pm = np.zeros((nf, nc))
     for I in range(nc):
         Pm[2 * I + 1, I] = 1.0
         Pm[2 * I, I] = 0.5
-        Pm[2 * I + 2, I] = 0.5
+        if 2 * I + 2 < nf:
+            Pm[2 * I + 2, I] = 0.5
     return Pm
 
 
-@pytest.mark.parametrize("kappa_seed", [None, 5])
-def test_vcycle_matches_dense_brute_force(kappa_seed):
+@pytest.mark.parametrize("kappa_seed,m", [(None, 16), (5, 16), (5, 15), (None, 13)])
+def test_vcycle_matches_dense_brute_force(kappa_seed, m):
     """Dense re-implementation of the V(nu1,nu2) definition (red then black
-    points updated simultaneously from the half-step start, bilinear P,
-    Galerkin P^T A P, exact solve at m=2) agrees with the oracle."""
-    d, m = 2, 16
+    points updated simultaneously from the half-step start, linear P onto the
+    odd-indexed nodes, Galerkin P^T A P, exact solve at one node per
+    direction) agrees with the oracle, also for odd m."""
+    d = 2
     kap = None if kappa_seed is None else synth.kappa_grf(d, m, 1.0, 0.2, seed=kappa_seed)
     P = O.Problem(d, 2, m, kappa=kap, vcycle=True)
     A0 = O.offsets_to_dense(O.assemble(d, 1, m, kappa=kap), d, m - 1, 1)
     levels = [A0]
     Ps = []
-    mm = m
-    while mm % 2 == 0 and mm > 2:
-        P1 = _interp_1d(mm - 1)
+    nn = m - 1
+    while nn > 1:
+        P1 = _interp_1d(nn)
         Pk = np.kron(P1, P1)
         Ps.append(Pk)
         levels.append(Pk.T @ levels[-1] @ Pk)
-        mm //= 2
+        nn //= 2
 
     def red_black(A, e, f, n1):
         par = np.array([(i % n1 + i // n1) % 2 for i in range(n1 * n1)])
