@@ -1,0 +1,487 @@
+// api.hip -- the extern "C" entry points of include/iga2l.h and the two-level
+// cycle driver (Algorithm 1 of arXiv:2009.01499 in correction form: FP64
+// residual, a correction cycle in working precision from zero, FP64 update).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <type_traits>
+
+#include "internal.h"
+
+struct iga2l_problem {
+    iga2l::Problem P;
+};
+
+namespace iga2l {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+void DevBuf::alloc(size_t nbytes) {
+    free();
+    if (nbytes == 0) nbytes = 8;
+    hipError_t e = hipMalloc(&ptr, nbytes);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        throw Error{IGA2L_ENOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed"};
+    }
+    bytes = nbytes;
+}
+
+void DevBuf::free() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+namespace {
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        f();
+        g_last_error.clear();
+        return IGA2L_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return IGA2L_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return IGA2L_EDEVICE;
+    }
+}
+
+iga2l_opts effective_opts(const iga2l_opts *o) {
+    iga2l_opts r;
+    iga2l_default_opts(&r);
+    if (o) r = *o;
+    return r;
+}
+
+void check_opts(const Problem &P, const iga2l_opts &o) {
+    IGA2L_REQUIRE(o.ordering == IGA2L_LEX || o.ordering == IGA2L_COLOUR, IGA2L_EINVAL, "unknown ordering");
+    IGA2L_REQUIRE(o.coarse == IGA2L_COARSE_DIRECT || o.coarse == IGA2L_COARSE_VCYCLE, IGA2L_EINVAL,
+                  "unknown coarse solver");
+    IGA2L_REQUIRE(o.precision == IGA2L_FP64 || o.precision == IGA2L_MIXED_FP32, IGA2L_EINVAL, "unknown precision");
+    IGA2L_REQUIRE(o.nu1 >= 0 && o.nu2 >= 0 && o.nu1 + o.nu2 <= 64, IGA2L_EINVAL, "bad V-cycle smoothing counts");
+    IGA2L_REQUIRE(o.max_cycles >= 0, IGA2L_EINVAL, "max_cycles must be >= 0");
+    IGA2L_REQUIRE(o.tol >= 0.0 && std::isfinite(o.tol), IGA2L_EINVAL, "tol must be finite and >= 0");
+    IGA2L_REQUIRE(o.fine_post_sweeps >= 0 && o.fine_post_sweeps <= 16, IGA2L_EINVAL, "bad post-sweep count");
+    if (P.blocks_ready && o.ordering == IGA2L_COLOUR) {
+        const int s = o.colour_period ? o.colour_period : P.bw;
+        IGA2L_REQUIRE(s >= P.bw, IGA2L_EINVAL, "colour period must be >= block width");
+    }
+    IGA2L_REQUIRE(!(o.ordering == IGA2L_LEX && o.precision != IGA2L_FP64), IGA2L_EUNSUPPORTED,
+                  "the lexicographic ordering runs in FP64 only");
+}
+
+void set_device(const Problem &P) { IGA2L_HIP(hipSetDevice(P.device)); }
+
+// one Schwarz sweep on A e = rhs in working precision (COLOUR ordering).
+// e_zero: e is zero on entry (its buffer content is ignored).  Returns the
+// buffer index (0/1 of P.ework) holding the result; start = buffer holding e.
+template <class T>
+int sweep_colour(const Problem &P, int s_period, const T *rhs, int start, bool e_zero, hipStream_t s) {
+    const int S = s_period;
+    const int ncz = (P.dim == 3) ? S : 1;
+    int cur = start;
+    bool zero = e_zero;
+    for (int cz = 0; cz < ncz; ++cz)
+        for (int cy = 0; cy < S; ++cy)
+            for (int cx = 0; cx < S; ++cx) {
+                launch_colour_step<T>(P, cx, cy, cz, S, P.ework[cur].as<T>(), P.ework[1 - cur].as<T>(), rhs, zero, s);
+                cur = 1 - cur;
+                zero = false;
+            }
+    return cur;
+}
+
+template <class T>
+void coarse_solve(Problem &P, const iga2l_opts &o, const T *dc, T *ec, hipStream_t s) {
+    if (o.coarse == IGA2L_COARSE_VCYCLE) {
+        launch_vcycle<T>(P, dc, ec, o.nu1, o.nu2, s);
+        return;
+    }
+    IGA2L_REQUIRE(P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up (iga2l_setup_blocks)");
+    if constexpr (std::is_same<T, double>::value) {
+        launch_dst_solve(P, dc, ec, s);
+    } else {
+        launch_convert(dc, P.dc64.ptr, P.coarse.n, false, s);
+        launch_dst_solve(P, P.dc64.as<double>(), P.ec64.as<double>(), s);
+        launch_convert(P.ec64.ptr, ec, P.coarse.n, true, s);
+    }
+}
+
+// One correction cycle: expects r64 = b - A u and the scalars of
+// launch_norm_finalize; performs u += sigma * cycle(0; r64 / sigma).
+template <class T>
+void correction_cycle(Problem &P, const iga2l_opts &o, double *u, hipStream_t s) {
+    const T *rhs;
+    if constexpr (std::is_same<T, double>::value) {
+        rhs = P.r64.as<double>();
+    } else {
+        launch_cast_scale<T>(P, P.r64.as<double>(), P.rhs_w.as<T>(), s);
+        rhs = P.rhs_w.as<T>();
+    }
+    int cur = 0;
+    if (o.ordering == IGA2L_COLOUR) {
+        const int S = o.colour_period ? o.colour_period : P.bw;
+        cur = sweep_colour<T>(P, S, rhs, 0, true, s);
+    } else {
+        // lexicographic: FP64 only, in place on a zeroed correction
+        IGA2L_HIP(hipMemsetAsync(P.ework[0].ptr, 0, sizeof(double) * size_t(P.fine.n), s));
+        for (size_t st = 0; st + 1 < P.lex_off.size(); ++st)
+            launch_lex_step(P, int(st), P.ework[0].as<double>(), P.r64.as<double>(), s);
+        cur = 0;
+    }
+    T *e = P.ework[cur].as<T>();
+    launch_defect<T>(P, e, rhs, P.dfine.as<T>(), s);
+    launch_restrict<T>(P, P.dfine.as<T>(), P.dc.as<T>(), s);
+    coarse_solve<T>(P, o, P.dc.as<T>(), P.ec.as<T>(), s);
+    const bool scaled = !std::is_same<T, double>::value;
+    if (o.fine_post_sweeps == 0) {
+        launch_prolong_update<T>(P, P.ec.as<T>(), e, u, scaled, s);
+        return;
+    }
+    launch_prolong_add<T>(P, P.ec.as<T>(), e, s);
+    for (int k = 0; k < o.fine_post_sweeps; ++k) {
+        if (o.ordering == IGA2L_COLOUR) {
+            const int S = o.colour_period ? o.colour_period : P.bw;
+            cur = sweep_colour<T>(P, S, rhs, cur, false, s);
+        } else {
+            for (size_t st = 0; st + 1 < P.lex_off.size(); ++st)
+                launch_lex_step(P, int(st), P.ework[0].as<double>(), P.r64.as<double>(), s);
+        }
+    }
+    // u += sigma * e: prolongation of a zero coarse vector adds nothing
+    IGA2L_HIP(hipMemsetAsync(P.ctmp.ptr, 0, sizeof(double) * size_t(P.coarse.n), s));
+    launch_prolong_update<T>(P, P.ctmp.as<T>(), P.ework[cur].as<T>(), u, scaled, s);
+}
+
+double residual_norm(Problem &P, const double *u, const double *b, bool fp32, hipStream_t s) {
+    launch_residual64(P, u, b, P.r64.as<double>(), true, s);
+    launch_norm_finalize(P, fp32, s);
+    double nrm = 0.0;
+    IGA2L_HIP(hipMemcpyAsync(&nrm, P.scal.as<double>() + kScalNorm, sizeof(double), hipMemcpyDeviceToHost, s));
+    IGA2L_HIP(hipStreamSynchronize(s));
+    return nrm;
+}
+
+void solve_impl(Problem &P, const double *b, double *u, const iga2l_opts &o, iga2l_info *info, hipStream_t s) {
+    IGA2L_REQUIRE(P.blocks_ready, IGA2L_EINVAL, "iga2l_setup_blocks must run before iga2l_solve");
+    IGA2L_REQUIRE(b && u, IGA2L_EINVAL, "null vector");
+    const bool fp32 = o.precision == IGA2L_MIXED_FP32;
+    IGA2L_REQUIRE(!fp32 || P.fp32_ready, IGA2L_EINVAL, "FP32 data not set up (setup_blocks with MIXED_FP32)");
+    IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_VCYCLE || P.vcycle_ready, IGA2L_EINVAL, "V-cycle not set up");
+    IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_DIRECT || P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");
+    auto t0 = std::chrono::steady_clock::now();
+    double r0 = residual_norm(P, u, b, fp32, s);
+    IGA2L_REQUIRE(std::isfinite(r0), IGA2L_ENUMERIC, "initial residual is not finite");
+    double rk = r0;
+    int k = 0;
+    int status = IGA2L_OK;
+    while (rk > o.tol * r0 && k < o.max_cycles) {
+        if (fp32) correction_cycle<float>(P, o, u, s);
+        else correction_cycle<double>(P, o, u, s);
+        ++k;
+        rk = residual_norm(P, u, b, fp32, s);
+        if (info && info->relres_history && k <= info->history_cap) info->relres_history[k - 1] = r0 > 0 ? rk / r0 : 0.0;
+        if (!std::isfinite(rk) || (r0 > 0 && rk > 1e3 * r0)) {
+            status = IGA2L_ENUMERIC;
+            break;
+        }
+    }
+    if (status == IGA2L_OK && rk > o.tol * r0) status = IGA2L_ENOTCONV;
+    auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->iters = k;
+        info->status = status;
+        info->r0 = r0;
+        info->relres = r0 > 0 ? rk / r0 : 0.0;
+        info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (status == IGA2L_ENUMERIC) throw Error{IGA2L_ENUMERIC, "residual diverged or became non-finite"};
+    if (status == IGA2L_ENOTCONV) throw Error{IGA2L_ENOTCONV, "max_cycles reached before the tolerance"};
+}
+
+bool knots_open_uniform(const double *t, int nt, int p, int &m) {
+    m = nt - 2 * p - 1;
+    if (m < 2) return false;
+    for (int i = 0; i < nt; ++i) {
+        double expect = (i <= p) ? 0.0 : (i >= nt - p - 1 ? 1.0 : double(i - p) / m);
+        if (!std::isfinite(t[i]) || std::fabs(t[i] - expect) > 1e-12) return false;
+    }
+    return true;
+}
+
+}  // namespace
+}  // namespace iga2l
+
+using namespace iga2l;
+
+extern "C" {
+
+void iga2l_default_opts(iga2l_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-10;
+    o->max_cycles = 100;
+    o->ordering = IGA2L_COLOUR;
+    o->colour_period = 0;
+    o->coarse = IGA2L_COARSE_VCYCLE;
+    o->nu1 = 1;
+    o->nu2 = 1;
+    o->precision = IGA2L_FP64;
+    o->fine_post_sweeps = 0;
+}
+
+const char *iga2l_last_error(void) { return g_last_error.c_str(); }
+
+int iga2l_assemble(int dim, const double *const *knots, const int *nknots, int p, const double *kappa, int device,
+                   iga2l_problem **out) {
+    return guarded([&] {
+        IGA2L_REQUIRE(out, IGA2L_EINVAL, "out is NULL");
+        *out = nullptr;
+        IGA2L_REQUIRE(dim == 2 || dim == 3, IGA2L_EINVAL, "dim must be 2 or 3");
+        IGA2L_REQUIRE(p >= 1 && p <= kMaxP, IGA2L_EINVAL, "p must be in 1..8");
+        IGA2L_REQUIRE(dim == 2 || p <= 4, IGA2L_EUNSUPPORTED, "3-D problems support p <= 4");
+        IGA2L_REQUIRE(knots && nknots, IGA2L_EINVAL, "knots is NULL");
+        int m = 0;
+        for (int k = 0; k < dim; ++k) {
+            IGA2L_REQUIRE(knots[k], IGA2L_EINVAL, "knot vector is NULL");
+            IGA2L_REQUIRE(nknots[k] == nknots[0], IGA2L_EUNSUPPORTED, "all directions must use the same knots");
+            int mk = 0;
+            IGA2L_REQUIRE(knots_open_uniform(knots[k], nknots[k], p, mk), IGA2L_EINVAL,
+                          "knots must be the open uniform vector (p+1 zeros, i/m, p+1 ones) with m >= 2");
+            m = mk;
+        }
+        auto *h = new iga2l_problem();
+        try {
+            Problem &P = h->P;
+            P.device = device;
+            P.dim = dim;
+            P.p = p;
+            P.m = m;
+            int64_t ne = 1;
+            for (int k = 0; k < dim; ++k) ne *= m;
+            if (kappa) {
+                P.kappa_one = false;
+                P.kappa.assign(kappa, kappa + ne);
+                for (double v : P.kappa)
+                    IGA2L_REQUIRE(std::isfinite(v) && v > 0.0, IGA2L_EINVAL, "kappa must be finite and > 0");
+            }
+            set_device(P);
+            host_assemble(P);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *opts) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob, IGA2L_EINVAL, "problem is NULL");
+        Problem &P = prob->P;
+        set_device(P);
+        iga2l_opts o = effective_opts(opts);
+        int bw = block_width;
+        if (bw == 0) bw = (P.p <= 4) ? 3 : (P.p <= 6 ? 5 : 7);
+        IGA2L_REQUIRE(bw >= 1 && bw <= 7 && (bw & 1), IGA2L_EINVAL, "block width must be odd, 1..7");
+        IGA2L_REQUIRE(P.dim == 2 || bw <= 3, IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3");
+        hipStream_t s = nullptr;
+        if (!P.blocks_ready || P.bw != bw) {
+            P.blocks_ready = false;
+            P.fp32_ready = false;
+            P.bw = bw;
+            P.bd = 1;
+            for (int k = 0; k < P.dim; ++k) P.bd *= bw;
+            std::vector<int> cls1;
+            std::vector<int64_t> reps;
+            host_block_classes(P, cls1, reps);
+            P.cls_d.alloc(cls1.size() * sizeof(int));
+            IGA2L_HIP(hipMemcpy(P.cls_d.ptr, cls1.data(), cls1.size() * sizeof(int), hipMemcpyHostToDevice));
+            P.Inv64.alloc(size_t(P.nslots) * P.bd * P.bd * sizeof(double));
+            launch_block_inverse(P, reps, s);
+            host_lex_schedule(P);
+            P.blocks_ready = true;
+        }
+        check_opts(P, o);
+        if (o.precision == IGA2L_MIXED_FP32 && !P.fp32_ready) {
+            P.A.v32.alloc(size_t(P.A.Wh) * P.A.npad * sizeof(float));
+            launch_convert(P.A.v64.ptr, P.A.v32.ptr, int64_t(P.A.Wh) * P.A.npad, true, s);
+            P.Inv32.alloc(size_t(P.nslots) * P.bd * P.bd * sizeof(float));
+            launch_convert(P.Inv64.ptr, P.Inv32.ptr, P.nslots * P.bd * P.bd, true, s);
+            P.R1d32.alloc(P.R1.size() * sizeof(float));
+            launch_convert(P.R1d64.ptr, P.R1d32.ptr, int64_t(P.R1.size()), true, s);
+            P.dc64.alloc(size_t(P.coarse.n) * sizeof(double));
+            P.ec64.alloc(size_t(P.coarse.n) * sizeof(double));
+            IGA2L_HIP(hipStreamSynchronize(s));
+            P.fp32_ready = true;
+        }
+        if (o.coarse == IGA2L_COARSE_VCYCLE && !P.vcycle_ready) host_build_levels(P);
+        if (o.coarse == IGA2L_COARSE_DIRECT && !P.direct_ready) {
+            IGA2L_REQUIRE(P.kappa_one, IGA2L_EUNSUPPORTED,
+                          "the exact coarse solve needs kappa = 1; use the V-cycle for variable kappa");
+            host_build_dst(P);
+        }
+        IGA2L_HIP(hipDeviceSynchronize());
+    });
+}
+
+int iga2l_sizes(const iga2l_problem *prob, int64_t *n_fine, int64_t *n_coarse, int64_t *n_elem) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob, IGA2L_EINVAL, "problem is NULL");
+        if (n_fine) *n_fine = prob->P.fine.n;
+        if (n_coarse) *n_coarse = prob->P.coarse.n;
+        if (n_elem) *n_elem = prob->P.ne;
+    });
+}
+
+int iga2l_residual(const iga2l_problem *prob, const double *u, const double *b, double *r, void *stream) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob && u && b && r, IGA2L_EINVAL, "null argument");
+        IGA2L_REQUIRE(r != u, IGA2L_EINVAL, "r may not alias u");
+        set_device(prob->P);
+        launch_residual64(prob->P, u, b, r, false, static_cast<hipStream_t>(stream));
+        IGA2L_HIP(hipGetLastError());
+    });
+}
+
+int iga2l_smooth(const iga2l_problem *prob, double *u, const double *b, int nsweeps, const iga2l_opts *opts,
+                 void *stream) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob && u && b, IGA2L_EINVAL, "null argument");
+        IGA2L_REQUIRE(nsweeps >= 0, IGA2L_EINVAL, "nsweeps must be >= 0");
+        Problem &P = const_cast<Problem &>(prob->P);
+        IGA2L_REQUIRE(P.blocks_ready, IGA2L_EINVAL, "iga2l_setup_blocks must run first");
+        iga2l_opts o = effective_opts(opts);
+        o.precision = IGA2L_FP64;
+        check_opts(P, o);
+        set_device(P);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const size_t bytes = sizeof(double) * size_t(P.fine.n);
+        for (int k = 0; k < nsweeps; ++k) {
+            if (o.ordering == IGA2L_LEX) {
+                for (size_t st = 0; st + 1 < P.lex_off.size(); ++st) launch_lex_step(P, int(st), u, b, s);
+            } else {
+                const int S = o.colour_period ? o.colour_period : P.bw;
+                IGA2L_HIP(hipMemcpyAsync(P.ework[0].ptr, u, bytes, hipMemcpyDeviceToDevice, s));
+                const int cur = sweep_colour<double>(P, S, b, 0, false, s);
+                IGA2L_HIP(hipMemcpyAsync(u, P.ework[cur].ptr, bytes, hipMemcpyDeviceToDevice, s));
+            }
+        }
+        IGA2L_HIP(hipGetLastError());
+    });
+}
+
+int iga2l_restrict(const iga2l_problem *prob, const double *r_fine, double *d_coarse, void *stream) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob && r_fine && d_coarse, IGA2L_EINVAL, "null argument");
+        set_device(prob->P);
+        launch_restrict<double>(prob->P, r_fine, d_coarse, static_cast<hipStream_t>(stream));
+        IGA2L_HIP(hipGetLastError());
+    });
+}
+
+int iga2l_prolong(const iga2l_problem *prob, const double *e_coarse, double *u_fine, void *stream) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob && e_coarse && u_fine, IGA2L_EINVAL, "null argument");
+        set_device(prob->P);
+        launch_prolong_add<double>(prob->P, e_coarse, u_fine, static_cast<hipStream_t>(stream));
+        IGA2L_HIP(hipGetLastError());
+    });
+}
+
+int iga2l_coarse_solve(const iga2l_problem *prob, const double *d_coarse, double *e_coarse, const iga2l_opts *opts,
+                       void *stream) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob && d_coarse && e_coarse, IGA2L_EINVAL, "null argument");
+        IGA2L_REQUIRE(d_coarse != e_coarse, IGA2L_EINVAL, "e_coarse may not alias d_coarse");
+        Problem &P = const_cast<Problem &>(prob->P);
+        iga2l_opts o = effective_opts(opts);
+        check_opts(P, o);
+        set_device(P);
+        coarse_solve<double>(P, o, d_coarse, e_coarse, static_cast<hipStream_t>(stream));
+        IGA2L_HIP(hipGetLastError());
+    });
+}
+
+int iga2l_solve(const iga2l_problem *prob, const double *b, double *u, const iga2l_opts *opts, iga2l_info *info,
+                void *stream) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob, IGA2L_EINVAL, "problem is NULL");
+        Problem &P = const_cast<Problem &>(prob->P);
+        iga2l_opts o = effective_opts(opts);
+        check_opts(P, o);
+        set_device(P);
+        solve_impl(P, b, u, o, info, static_cast<hipStream_t>(stream));
+    });
+}
+
+int iga2l_solve_batch(iga2l_problem *const *probs, int nprob, const double *const *b, double *const *u,
+                      const iga2l_opts *opts, iga2l_info *infos, void *stream) {
+    return guarded([&] {
+        IGA2L_REQUIRE(nprob >= 0 && (nprob == 0 || (probs && b && u)), IGA2L_EINVAL, "null argument");
+        iga2l_opts o = effective_opts(opts);
+        int worst = IGA2L_OK;
+        std::string msg;
+        for (int k = 0; k < nprob; ++k) {
+            IGA2L_REQUIRE(probs[k], IGA2L_EINVAL, "problem is NULL");
+            Problem &P = probs[k]->P;
+            check_opts(P, o);
+            set_device(P);
+            try {
+                solve_impl(P, b[k], u[k], o, infos ? &infos[k] : nullptr, static_cast<hipStream_t>(stream));
+            } catch (const Error &e) {
+                if (e.code == IGA2L_ENOTCONV || e.code == IGA2L_ENUMERIC) {
+                    if (worst == IGA2L_OK || e.code == IGA2L_ENUMERIC) {
+                        worst = e.code;
+                        msg = "problem " + std::to_string(k) + ": " + e.msg;
+                    }
+                } else {
+                    throw;
+                }
+            }
+        }
+        if (worst != IGA2L_OK) throw Error{worst, msg};
+    });
+}
+
+int iga2l_solve_backward(const iga2l_problem *prob, const double *u, const double *grad_u, double *lambda,
+                         double *grad_kappa, const iga2l_opts *opts, iga2l_info *info, void *stream) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob && u && grad_u && lambda, IGA2L_EINVAL, "null argument");
+        Problem &P = const_cast<Problem &>(prob->P);
+        iga2l_opts o = effective_opts(opts);
+        check_opts(P, o);
+        set_device(P);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        IGA2L_HIP(hipMemsetAsync(lambda, 0, sizeof(double) * size_t(P.fine.n), s));
+        // A is symmetric: the adjoint system A lambda = dL/du uses the same solver
+        solve_impl(P, grad_u, lambda, o, info, s);
+        if (grad_kappa) {
+            launch_grad_kappa(P, u, lambda, grad_kappa, s);
+            IGA2L_HIP(hipGetLastError());
+            IGA2L_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+void iga2l_destroy(iga2l_problem *prob) {
+    if (!prob) return;
+    (void)hipSetDevice(prob->P.device);
+    (void)hipDeviceSynchronize();
+    delete prob;
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+// internal.h -- data structures shared by the host set-up code, the kernels
+// and the C-ABI layer of the gfx950 two-level solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/iga2l.h"
+
+namespace iga2l {
+
+constexpr int kMaxDim = 3;
+constexpr int kMaxP = 8;
+
+// -------------------------------------------------------------- errors --
+void set_error(const std::string &msg);
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define IGA2L_HIP(call)                                                                \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::iga2l::Error{IGA2L_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define IGA2L_REQUIRE(cond, code, msg)                                                 \
+    do {                                                                               \
+        if (!(cond)) throw ::iga2l::Error{(code), (msg)};                              \
+    } while (0)
+
+// --------------------------------------------------------- device buffer --
+// Owning device allocation; freed with the problem.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    void alloc(size_t nbytes);
+    void free();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+    ~DevBuf() { free(); }
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : ptr(o.ptr), bytes(o.bytes) {
+        o.ptr = nullptr;
+        o.bytes = 0;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            free();
+            ptr = o.ptr;
+            bytes = o.bytes;
+            o.ptr = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
+};
+
+// ---------------------------------------------------------- grid shapes --
+// A tensor grid of n1 points per direction in dim directions, x fastest.
+struct Grid {
+    int dim = 2;
+    int n1 = 0;
+    int64_t n = 0;
+};
+
+// Banded operator with radius q stored in symmetric "upper-diagonal" form:
+// for each offset o in [-q,q]^d whose lexicographic (z,y,x) sign is >= 0
+// (Wh = ((2q+1)^d + 1) / 2 of them, the centre first) an array of the entries
+// A[i][i+o] over the padded grid (n1 + 2q per direction, zero padding), so
+// that A[i][i-o] = A[i-o][i] is read at the shifted padded position.
+struct SymDia {
+    int q = 0;
+    int W = 0, Wh = 0;
+    int pitch[kMaxDim] = {1, 0, 0};  // padded strides
+    int64_t npad = 0;                // padded length of one diagonal
+    DevBuf v64, v32;                 // [Wh][npad]
+};
+
+// One level of the degree-1 V-cycle hierarchy: full 3^d stencil by offset,
+// stored [3^d][n] (structure of arrays).
+struct Level {
+    Grid g;
+    DevBuf S64, S32;
+    DevBuf e[2], rhs, res;       // working vectors, sized for FP64 (FP32 reuses them)
+    double coarsest_diag = 0.0;  // n == 1 only
+};
+
+struct Problem {
+    int device = 0;
+    int dim = 2, p = 3, m = 0;
+    Grid fine, coarse;      // fine: n1 = m+p-2; coarse: n1 = m-1 (degree 1)
+    int64_t ne = 0;
+    bool kappa_one = true;
+    std::vector<double> kappa;
+
+    // host copies of the 1-D factors (per direction identical)
+    std::vector<double> K1, M1;   // [n1][2p+1], interior rows, offset j-i+p
+    std::vector<double> R1;       // [n1c][p+2], coarse row I, fine column I-1+a
+    std::vector<std::vector<double>> Ke, Me;  // element matrices [m][(p+1)^2]
+
+    SymDia A;                     // fine stiffness
+    DevBuf R1d64, R1d32;          // restriction factor on the device
+    DevBuf Ke_d, Me_d;            // 1-D element matrices (FP64) for the gradient kernel
+    DevBuf kappa_d;
+
+    // Schwarz blocks
+    int bw = 0, bd = 0;           // block width, b^d
+    int ncls1 = 0;                // classes per direction (1-D block classes)
+    bool shared_inverses = false; // kappa = 1: one inverse per class, else one per DOF
+    DevBuf cls_d;                 // [n1] int: 1-D class of a block centre
+    DevBuf Inv64, Inv32;          // [nslots][bd][bd]
+    int64_t nslots = 0;
+    bool blocks_ready = false;
+    bool fp32_ready = false;
+    // lexicographic schedule: hyperplane steps
+    std::vector<int> lex_off;     // host [nsteps+1]
+    DevBuf lex_blocks;            // int [n]
+
+    // coarse
+    std::vector<Level> levels;    // V-cycle hierarchy, level 0 = A_1 on the same knots
+    bool vcycle_ready = false;
+    DevBuf dst_S, dst_mu;         // DST-I matrix [n1c][n1c], eigenvalues [n_c]
+    bool direct_ready = false;
+
+    // workspaces
+    DevBuf r64;                   // fine residual FP64
+    DevBuf ework[2];              // fine correction ping-pong (FP64-sized)
+    DevBuf rhs_w;                 // fine right-hand side in working precision
+    DevBuf dfine;                 // fine defect in working precision
+    DevBuf dc, ec, ctmp;          // coarse vectors (FP64-sized)
+    DevBuf dc64, ec64;            // FP64 coarse vectors of the exact solve in mixed mode
+    DevBuf partial;               // per-workgroup partial sums (FP64)
+    DevBuf scal;                  // device scalars (see kScal*)
+    DevBuf lam_tmp;               // adjoint workspace
+    int npartial = 0;
+
+    // tuning knobs (numerics-neutral)
+    int tile_bx = 4, tile_by = 4, tile_bz = 1;   // Schwarz tile in blocks
+};
+
+// device scalar slots in Problem::scal (doubles)
+enum { kScalNorm = 0, kScalSigma = 1, kScalInvSigma = 2, kScalCount = 8 };
+
+// ------------------------------------------------------------ host set-up --
+void host_assemble(Problem &P);                 // 1-D factors, DIA, transfers, kappa
+void host_build_levels(Problem &P);             // V-cycle hierarchy (Galerkin)
+void host_build_dst(Problem &P);                // exact coarse solver (kappa = 1)
+void host_block_classes(Problem &P, std::vector<int> &cls1, std::vector<int64_t> &reps);
+void host_lex_schedule(Problem &P);
+
+// ------------------------------------------------------------ launchers --
+// fine level
+void launch_block_inverse(Problem &P, const std::vector<int64_t> &reps, hipStream_t s);
+void launch_residual64(const Problem &P, const double *u, const double *b, double *r, bool partial_norm,
+                       hipStream_t s);
+template <class T>
+void launch_defect(const Problem &P, const T *e, const T *rhs, T *d, hipStream_t s);
+void launch_norm_finalize(const Problem &P, bool scale_fp32, hipStream_t s);
+int64_t residual_workgroups(const Problem &P);   // partial sums written by the FP64 residual
+template <class T>
+void launch_colour_step(const Problem &P, int cx, int cy, int cz, int s_period, const T *x_src, T *x_dst,
+                        const T *rhs, bool x_zero, hipStream_t s);
+void launch_lex_step(const Problem &P, int step, double *u, const double *b, hipStream_t s);
+template <class T>
+void launch_cast_scale(const Problem &P, const double *r64, T *rhs, hipStream_t s);
+// transfers
+template <class T>
+void launch_restrict(const Problem &P, const T *df, T *dc, hipStream_t s);
+template <class T>
+void launch_prolong_add(const Problem &P, const T *ec, T *uf, hipStream_t s);
+template <class T>
+void launch_prolong_update(const Problem &P, const T *ec, const T *e, double *u, bool scaled, hipStream_t s);
+// coarse
+template <class T>
+void launch_vcycle(Problem &P, const T *rhs, T *e, int nu1, int nu2, hipStream_t s);
+void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s);
+void launch_convert(const void *src, void *dst, int64_t n, bool to_fp32, hipStream_t s);
+// gradient
+void launch_grad_kappa(const Problem &P, const double *u, const double *lam, double *g, hipStream_t s);
+
+}  // namespace iga2l

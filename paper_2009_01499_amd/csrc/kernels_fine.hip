@@ -1,0 +1,604 @@
+// kernels_fine.hip -- fine-level kernels of the two-level solver on gfx950:
+// the wide-band residual (symmetric padded-diagonal operator, LDS-staged halo
+// of width p), the coloured overlapping multiplicative Schwarz step, the
+// lexicographic (hyperplane) Schwarz step, the batched inversion of the
+// Schwarz block matrices and the deterministic residual norm.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace iga2l {
+
+namespace {
+
+constexpr int kWave = 64;
+
+__host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
+
+// ------------------------------------------------------------------------
+// Operator entry A[i][i+o] from the symmetric padded-diagonal form.
+// padi = padded position of row i; w = offset index of o (x fastest, each
+// component shifted by P); delta = padded shift of o.
+template <int D, int P, class T>
+__device__ __forceinline__ T dia_entry(const T *__restrict__ val, int64_t npad, int64_t padi, int w, int64_t delta) {
+    constexpr int W = cpow(2 * P + 1, D);
+    constexpr int c0 = (W - 1) / 2;
+    if (w >= c0) return val[int64_t(w - c0) * npad + padi];
+    return val[int64_t(c0 - w) * npad + padi + delta];
+}
+
+// ------------------------------------------------------------------------
+// Residual r = b - A x over tiles of TX x TY (x TZ) points; x staged in LDS
+// with a halo of width P (zeros outside the grid).  NORM: per-workgroup
+// partial sums of r^2 (fixed reduction order) for the FP64 outer residual.
+template <int D, int P, class T, bool NORM>
+__global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
+                                                  int n1, int TX, int TY, int TZ, const T *__restrict__ x,
+                                                  const T *__restrict__ b, T *__restrict__ r,
+                                                  double *__restrict__ partial) {
+    extern __shared__ unsigned char smem_raw[];
+    T *xs = reinterpret_cast<T *>(smem_raw);
+    const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
+    const int gx0 = blockIdx.x * TX, gy0 = blockIdx.y * TY, gz0 = (D == 3) ? blockIdx.z * TZ : 0;
+    const int nh = HX * HY * HZ;
+    for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+        int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        int gx = gx0 + hx - P, gy = gy0 + hy - P, gz = (D == 3) ? gz0 + hz - P : 0;
+        bool in = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
+        xs[h] = in ? x[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int tx = t % TX, ty = (t / TX) % TY, tz = (D == 3) ? t / (TX * TY) : 0;
+    const int gx = gx0 + tx, gy = gy0 + ty, gz = gz0 + tz;
+    const bool active = t < TX * TY * ((D == 3) ? TZ : 1) && gx < n1 && gy < n1 && (D == 2 || gz < n1);
+    double rr = 0.0;
+    if (active) {
+        const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+        const int64_t padi = int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
+        const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
+        T acc = T(0);
+        if constexpr (D == 2) {
+#pragma unroll
+            for (int oy = -P; oy <= P; ++oy)
+#pragma unroll
+                for (int ox = -P; ox <= P; ++ox) {
+                    const int w = (oy + P) * (2 * P + 1) + (ox + P);
+                    const T a = dia_entry<D, P, T>(val, npad, padi, w, int64_t(ox) + int64_t(oy) * pitch1);
+                    acc += a * xs[lc + oy * HX + ox];
+                }
+        } else {
+#pragma unroll
+            for (int oz = -P; oz <= P; ++oz)
+#pragma unroll
+                for (int oy = -P; oy <= P; ++oy)
+#pragma unroll
+                    for (int ox = -P; ox <= P; ++ox) {
+                        const int w = ((oz + P) * (2 * P + 1) + (oy + P)) * (2 * P + 1) + (ox + P);
+                        const T a = dia_entry<D, P, T>(val, npad, padi, w,
+                                                       int64_t(ox) + int64_t(oy) * pitch1 + int64_t(oz) * pitch2);
+                        acc += a * xs[lc + (oz * HY + oy) * HX + ox];
+                    }
+        }
+        const T res = b[gi] - acc;
+        r[gi] = res;
+        rr = double(res) * double(res);
+    }
+    if constexpr (NORM) {
+        __shared__ double red[256 / kWave];
+        for (int off = kWave / 2; off > 0; off >>= 1) rr += __shfl_down(rr, off, kWave);
+        if ((threadIdx.x % kWave) == 0) red[threadIdx.x / kWave] = rr;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int k = 0; k < int(blockDim.x / kWave); ++k) s += red[k];
+            partial[(int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// One colour of the coloured multiplicative Schwarz sweep.  The blocks of the
+// colour have centres c with c_k = col_k (mod B) when the colour period equals
+// the block width B, so they tile the grid.  Each workgroup owns a tile of
+// whole blocks (tile origin shifted by col - hb), reads the colour-start
+// iterate x_src over the tile plus a halo of width P, computes the residual
+// of every tile point, applies the block inverses and writes x_src + delta
+// for every point it owns into x_dst.  Reading x_src and writing x_dst keeps
+// all corrections of the colour based on the colour-start iterate.
+// For a colour period s > B the same kernel runs with the tile spacing s; the
+// points between blocks are copied unchanged.
+template <int D, int P, int B, class T>
+__global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
+                                                 int n1, const T *__restrict__ inv, const int *__restrict__ cls,
+                                                 int ncls1, const T *__restrict__ x_src, T *__restrict__ x_dst,
+                                                 const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz,
+                                                 int S, int NBX, int NBY, int NBZ) {
+    constexpr int BD = cpow(B, D);
+    constexpr int HB = (B - 1) / 2;
+    extern __shared__ unsigned char smem_raw[];
+    // tile = NBX x NBY (x NBZ) cells of S points; each cell holds one block in
+    // its first B x B points
+    const int TX = NBX * S, TY = NBY * S, TZ = (D == 3) ? NBZ * S : 1;
+    const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
+    T *xs = reinterpret_cast<T *>(smem_raw);
+    T *rs = xs + HX * HY * HZ;
+    const int gx0 = ox + blockIdx.x * TX, gy0 = oy + blockIdx.y * TY, gz0 = (D == 3) ? oz + blockIdx.z * TZ : 0;
+    const int nh = HX * HY * HZ;
+    if (!x_zero) {
+        for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+            int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+            int gx = gx0 + hx - P, gy = gy0 + hy - P, gz = (D == 3) ? gz0 + hz - P : 0;
+            bool in = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
+            xs[h] = in ? x_src[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
+        }
+        __syncthreads();
+    }
+    const int t = threadIdx.x;
+    const int ntile = TX * TY * TZ;
+    const int tx = t % TX, ty = (t / TX) % TY, tz = (D == 3) ? t / (TX * TY) : 0;
+    const int gx = gx0 + tx, gy = gy0 + ty, gz = gz0 + tz;
+    const bool mine = t < ntile && gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
+    const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
+    // position inside the cell; points outside the block part are not in any block of this colour
+    const int cx = tx % S, cy = ty % S, cz = (D == 3) ? tz % S : 0;
+    const bool in_block = cx < B && cy < B && (D == 2 || cz < B);
+    T res = T(0);
+    int64_t gi = 0;
+    if (mine) {
+        gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+        if (in_block) {
+            if (x_zero) {
+                res = rhs[gi];
+            } else {
+                const int64_t padi =
+                    int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
+                T acc = T(0);
+                if constexpr (D == 2) {
+#pragma unroll
+                    for (int qy = -P; qy <= P; ++qy)
+#pragma unroll
+                        for (int qx = -P; qx <= P; ++qx) {
+                            const int w = (qy + P) * (2 * P + 1) + (qx + P);
+                            acc += dia_entry<D, P, T>(val, npad, padi, w, int64_t(qx) + int64_t(qy) * pitch1) *
+                                   xs[lc + qy * HX + qx];
+                        }
+                } else {
+#pragma unroll
+                    for (int qz = -P; qz <= P; ++qz)
+#pragma unroll
+                        for (int qy = -P; qy <= P; ++qy)
+#pragma unroll
+                            for (int qx = -P; qx <= P; ++qx) {
+                                const int w = ((qz + P) * (2 * P + 1) + (qy + P)) * (2 * P + 1) + (qx + P);
+                                acc += dia_entry<D, P, T>(val, npad, padi, w,
+                                                          int64_t(qx) + int64_t(qy) * pitch1 + int64_t(qz) * pitch2) *
+                                       xs[lc + (qz * HY + qy) * HX + qx];
+                            }
+                }
+                res = rhs[gi] - acc;
+            }
+        }
+    }
+    if (t < ntile) rs[t] = res;
+    __syncthreads();
+    if (!mine) return;
+    T xi = x_zero ? T(0) : xs[lc];
+    T delta = T(0);
+    if (in_block) {
+        // block centre and its inverse slot
+        const int bx = tx / S, by = ty / S, bz = (D == 3) ? tz / S : 0;
+        const int ccx = gx0 + bx * S + HB, ccy = gy0 + by * S + HB, ccz = (D == 3) ? gz0 + bz * S + HB : 0;
+        const bool covered = ccx >= 0 && ccx < n1 && ccy >= 0 && ccy < n1 && (D == 2 || (ccz >= 0 && ccz < n1));
+        if (covered) {
+            int64_t slot = cls[ccx] + int64_t(ncls1) * cls[ccy];
+            if (D == 3) slot += int64_t(ncls1) * ncls1 * cls[ccz];
+            const int loc = cx + B * cy + ((D == 3) ? B * B * cz : 0);
+            const T *row = inv + (slot * BD + loc) * BD;
+            const int base = ((bz * S) * TY + by * S) * TX + bx * S;
+#pragma unroll
+            for (int l = 0; l < BD; ++l) {
+                const int lx = l % B, ly = (l / B) % B, lz = (D == 3) ? l / (B * B) : 0;
+                delta += row[l] * rs[base + (lz * TY + ly) * TX + lx];
+            }
+        }
+    }
+    x_dst[gi] = xi + delta;
+}
+
+// ------------------------------------------------------------------------
+// One step of the lexicographic Schwarz sweep: every block of the step (they
+// do not interact) computes its residual from u, applies its inverse and
+// updates u in place.  One workgroup per block, one thread per block point.
+template <int D, int P, int B>
+__global__ void __launch_bounds__(128) k_lex_step(const double *__restrict__ val, int64_t npad, int pitch1,
+                                                  int pitch2, int n1, const double *__restrict__ inv,
+                                                  const int *__restrict__ cls, int ncls1,
+                                                  const int *__restrict__ blocks, int first, double *u,
+                                                  const double *__restrict__ b) {
+    constexpr int BD = cpow(B, D);
+    constexpr int HB = (B - 1) / 2;
+    __shared__ double rs[BD];
+    const int j = blocks[first + blockIdx.x];
+    const int jx = j % n1, jy = (j / n1) % n1, jz = (D == 3) ? j / (n1 * n1) : 0;
+    const int l = threadIdx.x;
+    int gx = 0, gy = 0, gz = 0;
+    bool in = false;
+    if (l < BD) {
+        gx = jx + l % B - HB;
+        gy = jy + (l / B) % B - HB;
+        gz = (D == 3) ? jz + l / (B * B) - HB : 0;
+        in = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
+        double r = 0.0;
+        if (in) {
+            const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+            const int64_t padi = int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
+            double acc = 0.0;
+            for (int qz = ((D == 3) ? -P : 0); qz <= ((D == 3) ? P : 0); ++qz)
+                for (int qy = -P; qy <= P; ++qy)
+                    for (int qx = -P; qx <= P; ++qx) {
+                        const int hx = gx + qx, hy = gy + qy, hz = gz + qz;
+                        if (hx < 0 || hx >= n1 || hy < 0 || hy >= n1 || (D == 3 && (hz < 0 || hz >= n1))) continue;
+                        const int w = ((D == 3) ? (qz + P) * (2 * P + 1) * (2 * P + 1) : 0) + (qy + P) * (2 * P + 1) + (qx + P);
+                        acc += dia_entry<D, P, double>(val, npad, padi, w,
+                                                       int64_t(qx) + int64_t(qy) * pitch1 + int64_t(qz) * pitch2) *
+                               u[(int64_t(hz) * n1 + hy) * n1 + hx];
+                    }
+            r = b[gi] - acc;
+        }
+        rs[l] = r;
+    }
+    __syncthreads();
+    if (l < BD && in) {
+        int64_t slot = cls[jx] + int64_t(ncls1) * cls[jy];
+        if (D == 3) slot += int64_t(ncls1) * ncls1 * cls[jz];
+        const double *row = inv + (slot * BD + l) * BD;
+        double delta = 0.0;
+        for (int k = 0; k < BD; ++k) delta += row[k] * rs[k];
+        u[(int64_t(gz) * n1 + gy) * n1 + gx] += delta;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Inverse of every block matrix A^{B_j} = V_j A V_j^T (one per slot) by
+// in-place Gauss-Jordan elimination without pivoting (the block matrices are
+// symmetric positive definite).  Block members outside the grid get identity
+// rows/columns during the elimination and zero rows/columns in the result.
+template <int D, int B>
+__global__ void __launch_bounds__(kWave) k_block_inverse(const double *__restrict__ val, int64_t npad, int pitch1,
+                                                         int pitch2, int n1, int P, const int64_t *__restrict__ reps,
+                                                         double *__restrict__ inv, int *__restrict__ err) {
+    constexpr int BD = cpow(B, D);
+    constexpr int HB = (B - 1) / 2;
+    __shared__ double a[BD * BD];
+    __shared__ double col[BD];
+    __shared__ int member_in[BD];
+    __shared__ int64_t member_pad[BD];
+    __shared__ int mx[BD], my[BD], mz[BD];
+    const int64_t j = reps[blockIdx.x];
+    const int jx = int(j % n1), jy = int((j / n1) % n1), jz = (D == 3) ? int(j / (int64_t(n1) * n1)) : 0;
+    const int W1 = 2 * P + 1;
+    const int W = (D == 3) ? W1 * W1 * W1 : W1 * W1;
+    const int c0 = (W - 1) / 2;
+    for (int l = threadIdx.x; l < BD; l += blockDim.x) {
+        int gx = jx + l % B - HB, gy = jy + (l / B) % B - HB, gz = (D == 3) ? jz + l / (B * B) - HB : 0;
+        mx[l] = gx;
+        my[l] = gy;
+        mz[l] = gz;
+        member_in[l] = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
+        member_pad[l] = int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < BD * BD; e += blockDim.x) {
+        const int r = e / BD, c = e % BD;
+        double v = (r == c) ? 1.0 : 0.0;
+        if (member_in[r] && member_in[c]) {
+            const int qx = mx[c] - mx[r], qy = my[c] - my[r], qz = mz[c] - mz[r];
+            if (qx >= -P && qx <= P && qy >= -P && qy <= P && qz >= -P && qz <= P) {
+                const int w = ((D == 3) ? (qz + P) * W1 * W1 : 0) + (qy + P) * W1 + (qx + P);
+                if (w >= c0) v = val[int64_t(w - c0) * npad + member_pad[r]];
+                else v = val[int64_t(c0 - w) * npad + member_pad[c]];
+            } else {
+                v = 0.0;
+            }
+        }
+        a[e] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < BD; ++k) {
+        const double piv = a[k * BD + k];
+        if (threadIdx.x == 0 && !(piv > 0.0)) atomicOr(err, 1);
+        for (int i = threadIdx.x; i < BD; i += blockDim.x) col[i] = a[i * BD + k];
+        __syncthreads();
+        for (int c = threadIdx.x; c < BD; c += blockDim.x) a[k * BD + c] = ((c == k) ? 1.0 : a[k * BD + c]) / piv;
+        __syncthreads();
+        for (int e = threadIdx.x; e < BD * BD; e += blockDim.x) {
+            const int r = e / BD, c = e % BD;
+            if (r == k) continue;
+            a[e] = ((c == k) ? 0.0 : a[e]) - col[r] * a[k * BD + c];
+        }
+        __syncthreads();
+    }
+    double *out = inv + int64_t(blockIdx.x) * BD * BD;
+    for (int e = threadIdx.x; e < BD * BD; e += blockDim.x) {
+        const int r = e / BD, c = e % BD;
+        out[e] = (member_in[r] && member_in[c]) ? a[e] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Fixed-order reduction of the per-workgroup partial sums into ||r||_2 and
+// the scaling used by the FP32 correction cycle.
+__global__ void __launch_bounds__(256) k_norm_finalize(const double *__restrict__ partial, int np, double *scal,
+                                                       int scale_fp32) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(red[0]);
+        const double sigma = (scale_fp32 && nrm > 0.0) ? nrm : 1.0;
+        scal[kScalNorm] = nrm;
+        scal[kScalSigma] = sigma;
+        scal[kScalInvSigma] = 1.0 / sigma;
+    }
+}
+
+template <class T>
+__global__ void k_cast_scale(const double *__restrict__ r64, T *__restrict__ out, const double *__restrict__ scal,
+                             int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = T(r64[i] * scal[kScalInvSigma]);
+}
+
+// ------------------------------------------------------------ dispatch --
+template <int D, int P>
+struct TileShape;
+template <int P>
+struct TileShape<2, P> {
+    static constexpr int TX = 64, TY = 4, TZ = 1;
+};
+template <int P>
+struct TileShape<3, P> {
+    static constexpr int TX = 16, TY = 8, TZ = 2;
+};
+
+template <int D, int P, class T, bool NORM>
+void residual_launch(const Problem &Pb, const T *val, const T *x, const T *b, T *r, double *partial, int &nblocks,
+                     hipStream_t s) {
+    using TS = TileShape<D, P>;
+    const int n1 = Pb.fine.n1;
+    dim3 grid((n1 + TS::TX - 1) / TS::TX, (n1 + TS::TY - 1) / TS::TY, D == 3 ? (n1 + TS::TZ - 1) / TS::TZ : 1);
+    const size_t shm = size_t(TS::TX + 2 * P) * (TS::TY + 2 * P) * (D == 3 ? TS::TZ + 2 * P : 1) * sizeof(T);
+    nblocks = int(grid.x * grid.y * grid.z);
+    hipLaunchKernelGGL((k_residual<D, P, T, NORM>), grid, dim3(TS::TX * TS::TY * TS::TZ), shm, s, val, Pb.A.npad,
+                       Pb.A.pitch[1], Pb.A.pitch[2], n1, TS::TX, TS::TY, TS::TZ, x, b, r, partial);
+}
+
+#define IGA2L_DISPATCH_P2(F, ...)                                   \
+    switch (Pb.p) {                                                 \
+        case 1: F<2, 1>(__VA_ARGS__); break;                        \
+        case 2: F<2, 2>(__VA_ARGS__); break;                        \
+        case 3: F<2, 3>(__VA_ARGS__); break;                        \
+        case 4: F<2, 4>(__VA_ARGS__); break;                        \
+        case 5: F<2, 5>(__VA_ARGS__); break;                        \
+        case 6: F<2, 6>(__VA_ARGS__); break;                        \
+        case 7: F<2, 7>(__VA_ARGS__); break;                        \
+        case 8: F<2, 8>(__VA_ARGS__); break;                        \
+        default: throw Error{IGA2L_EUNSUPPORTED, "degree out of range"}; \
+    }
+#define IGA2L_DISPATCH_P3(F, ...)                                   \
+    switch (Pb.p) {                                                 \
+        case 1: F<3, 1>(__VA_ARGS__); break;                        \
+        case 2: F<3, 2>(__VA_ARGS__); break;                        \
+        case 3: F<3, 3>(__VA_ARGS__); break;                        \
+        case 4: F<3, 4>(__VA_ARGS__); break;                        \
+        default: throw Error{IGA2L_EUNSUPPORTED, "3-D degree out of range"}; \
+    }
+
+template <int D, int P>
+void res64_dp(const Problem &Pb, const double *u, const double *b, double *r, bool norm, hipStream_t s) {
+    int nb = 0;
+    if (norm) {
+        IGA2L_REQUIRE(residual_workgroups(Pb) <= Pb.npartial, IGA2L_EUNSUPPORTED,
+                      "grid too large for the norm workspace");
+        residual_launch<D, P, double, true>(Pb, Pb.A.v64.as<double>(), u, b, r, Pb.partial.as<double>(), nb, s);
+    } else {
+        residual_launch<D, P, double, false>(Pb, Pb.A.v64.as<double>(), u, b, r, nullptr, nb, s);
+    }
+}
+
+template <int D, int P, class T>
+void defect_dp(const Problem &Pb, const T *e, const T *rhs, T *d, hipStream_t s) {
+    int nb = 0;
+    const T *val = std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.A.v64.ptr)
+                                                  : reinterpret_cast<const T *>(Pb.A.v32.ptr);
+    residual_launch<D, P, T, false>(Pb, val, e, rhs, d, nullptr, nb, s);
+}
+
+template <int D, int P, int B, class T>
+void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs,
+                   bool x_zero, hipStream_t s) {
+    const int n1 = Pb.fine.n1;
+    constexpr int HB = (B - 1) / 2;
+    int nbx = Pb.tile_bx, nby = Pb.tile_by, nbz = (D == 3) ? Pb.tile_bz : 1;
+    // keep the tile within one workgroup of at most 1024 threads
+    while (nbx * S * nby * S * ((D == 3) ? nbz * S : 1) > 1024) {
+        if (nby > 1) --nby;
+        else if (nbx > 1) --nbx;
+        else if (nbz > 1) --nbz;
+        else break;
+    }
+    const int TX = nbx * S, TY = nby * S, TZ = (D == 3) ? nbz * S : 1;
+    IGA2L_REQUIRE(TX * TY * TZ <= 1024, IGA2L_EUNSUPPORTED, "colour period too large for one workgroup");
+    // tile origins: aligned with the colour's blocks and at or before index 0
+    int ox = cx - HB, oy = cy - HB, oz = (D == 3) ? cz - HB : 0;
+    if (ox > 0) ox -= S;
+    if (oy > 0) oy -= S;
+    if (oz > 0) oz -= S;
+    dim3 grid((n1 - ox + TX - 1) / TX, (n1 - oy + TY - 1) / TY, D == 3 ? (n1 - oz + TZ - 1) / TZ : 1);
+    const int threads = ((TX * TY * TZ + kWave - 1) / kWave) * kWave;
+    const size_t shm = (size_t(TX + 2 * Pb.p) * (TY + 2 * Pb.p) * (D == 3 ? TZ + 2 * Pb.p : 1) + size_t(TX) * TY * TZ) *
+                       sizeof(T);
+    const T *val = std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.A.v64.ptr)
+                                                  : reinterpret_cast<const T *>(Pb.A.v32.ptr);
+    const T *inv = std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.Inv64.ptr)
+                                                  : reinterpret_cast<const T *>(Pb.Inv32.ptr);
+    hipLaunchKernelGGL((k_colour<D, P, B, T>), grid, dim3(threads), shm, s, val, Pb.A.npad, Pb.A.pitch[1],
+                       Pb.A.pitch[2], n1, inv, Pb.cls_d.as<int>(), Pb.ncls1, x_src, x_dst, rhs, x_zero ? 1 : 0, ox,
+                       oy, oz, S, nbx, nby, nbz);
+}
+
+template <int D, int P, class T>
+void colour_dp(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs, bool x_zero,
+               hipStream_t s) {
+    switch (Pb.bw) {
+        case 1: colour_launch<D, P, 1, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s); break;
+        case 3: colour_launch<D, P, 3, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s); break;
+        case 5:
+            if constexpr (D == 2) colour_launch<D, P, 5, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s);
+            else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
+            break;
+        case 7:
+            if constexpr (D == 2) colour_launch<D, P, 7, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s);
+            else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
+            break;
+        default: throw Error{IGA2L_EUNSUPPORTED, "block width must be 1, 3, 5 or 7"};
+    }
+}
+
+template <int D, int P, int B>
+void lex_launch(const Problem &Pb, int step, double *u, const double *b, hipStream_t s) {
+    const int first = Pb.lex_off[step], cnt = Pb.lex_off[step + 1] - first;
+    constexpr int BD = cpow(B, D);
+    const int threads = BD <= 64 ? 64 : 128;
+    hipLaunchKernelGGL((k_lex_step<D, P, B>), dim3(cnt), dim3(threads), 0, s, Pb.A.v64.as<double>(), Pb.A.npad,
+                       Pb.A.pitch[1], Pb.A.pitch[2], Pb.fine.n1, Pb.Inv64.as<double>(), Pb.cls_d.as<int>(), Pb.ncls1,
+                       Pb.lex_blocks.as<int>(), first, u, b);
+}
+
+template <int D, int P>
+void lex_dp(const Problem &Pb, int step, double *u, const double *b, hipStream_t s) {
+    switch (Pb.bw) {
+        case 1: lex_launch<D, P, 1>(Pb, step, u, b, s); break;
+        case 3: lex_launch<D, P, 3>(Pb, step, u, b, s); break;
+        case 5:
+            if constexpr (D == 2) lex_launch<D, P, 5>(Pb, step, u, b, s);
+            else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
+            break;
+        case 7:
+            if constexpr (D == 2) lex_launch<D, P, 7>(Pb, step, u, b, s);
+            else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
+            break;
+        default: throw Error{IGA2L_EUNSUPPORTED, "block width must be 1, 3, 5 or 7"};
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers --
+void launch_residual64(const Problem &Pb, const double *u, const double *b, double *r, bool partial_norm,
+                       hipStream_t s) {
+    if (Pb.dim == 2) {
+        IGA2L_DISPATCH_P2(res64_dp, Pb, u, b, r, partial_norm, s);
+    } else {
+        IGA2L_DISPATCH_P3(res64_dp, Pb, u, b, r, partial_norm, s);
+    }
+}
+
+template <class T>
+void launch_defect(const Problem &Pb, const T *e, const T *rhs, T *d, hipStream_t s) {
+    if (Pb.dim == 2) {
+        IGA2L_DISPATCH_P2(defect_dp, Pb, e, rhs, d, s);
+    } else {
+        IGA2L_DISPATCH_P3(defect_dp, Pb, e, rhs, d, s);
+    }
+}
+template void launch_defect<double>(const Problem &, const double *, const double *, double *, hipStream_t);
+template void launch_defect<float>(const Problem &, const float *, const float *, float *, hipStream_t);
+
+// number of workgroups of the FP64 residual launch (one partial sum each)
+int64_t residual_workgroups(const Problem &Pb) {
+    const int64_t n1 = Pb.fine.n1;
+    if (Pb.dim == 2) return ((n1 + TileShape<2, 1>::TX - 1) / TileShape<2, 1>::TX) * ((n1 + TileShape<2, 1>::TY - 1) / TileShape<2, 1>::TY);
+    return ((n1 + TileShape<3, 1>::TX - 1) / TileShape<3, 1>::TX) * ((n1 + TileShape<3, 1>::TY - 1) / TileShape<3, 1>::TY) *
+           ((n1 + TileShape<3, 1>::TZ - 1) / TileShape<3, 1>::TZ);
+}
+
+void launch_norm_finalize(const Problem &Pb, bool scale_fp32, hipStream_t s) {
+    const int64_t nb = residual_workgroups(Pb);
+    IGA2L_REQUIRE(nb <= Pb.npartial, IGA2L_EUNSUPPORTED, "grid too large for the norm workspace");
+    hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, Pb.partial.as<double>(), int(nb),
+                       Pb.scal.as<double>(), scale_fp32 ? 1 : 0);
+}
+
+template <class T>
+void launch_colour_step(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs,
+                        bool x_zero, hipStream_t s) {
+    if (Pb.dim == 2) {
+        IGA2L_DISPATCH_P2(colour_dp, Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s);
+    } else {
+        IGA2L_DISPATCH_P3(colour_dp, Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s);
+    }
+}
+template void launch_colour_step<double>(const Problem &, int, int, int, int, const double *, double *,
+                                         const double *, bool, hipStream_t);
+template void launch_colour_step<float>(const Problem &, int, int, int, int, const float *, float *, const float *,
+                                        bool, hipStream_t);
+
+void launch_lex_step(const Problem &Pb, int step, double *u, const double *b, hipStream_t s) {
+    if (Pb.dim == 2) {
+        IGA2L_DISPATCH_P2(lex_dp, Pb, step, u, b, s);
+    } else {
+        IGA2L_DISPATCH_P3(lex_dp, Pb, step, u, b, s);
+    }
+}
+
+template <class T>
+void launch_cast_scale(const Problem &Pb, const double *r64, T *rhs, hipStream_t s) {
+    const int64_t n = Pb.fine.n;
+    hipLaunchKernelGGL((k_cast_scale<T>), dim3((n + 255) / 256), dim3(256), 0, s, r64, rhs, Pb.scal.as<double>(), n);
+}
+template void launch_cast_scale<float>(const Problem &, const double *, float *, hipStream_t);
+template void launch_cast_scale<double>(const Problem &, const double *, double *, hipStream_t);
+
+void launch_block_inverse(Problem &Pb, const std::vector<int64_t> &reps, hipStream_t s) {
+    DevBuf reps_d;
+    reps_d.alloc(reps.size() * sizeof(int64_t));
+    IGA2L_HIP(hipMemcpyAsync(reps_d.ptr, reps.data(), reps.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DevBuf err;
+    err.alloc(sizeof(int));
+    IGA2L_HIP(hipMemsetAsync(err.ptr, 0, sizeof(int), s));
+    const unsigned nblk = unsigned(reps.size());
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nblk), dim3(kWave), 0, s, Pb.A.v64.as<double>(), Pb.A.npad, Pb.A.pitch[1],
+                           Pb.A.pitch[2], Pb.fine.n1, Pb.p, reps_d.as<int64_t>(), Pb.Inv64.as<double>(), err.as<int>());
+    };
+    if (Pb.dim == 2) {
+        switch (Pb.bw) {
+            case 1: go(k_block_inverse<2, 1>); break;
+            case 3: go(k_block_inverse<2, 3>); break;
+            case 5: go(k_block_inverse<2, 5>); break;
+            case 7: go(k_block_inverse<2, 7>); break;
+            default: throw Error{IGA2L_EUNSUPPORTED, "block width must be 1, 3, 5 or 7"};
+        }
+    } else {
+        switch (Pb.bw) {
+            case 1: go(k_block_inverse<3, 1>); break;
+            case 3: go(k_block_inverse<3, 3>); break;
+            default: throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
+        }
+    }
+    IGA2L_HIP(hipGetLastError());
+    int herr = 0;
+    IGA2L_HIP(hipMemcpyAsync(&herr, err.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    IGA2L_HIP(hipStreamSynchronize(s));
+    IGA2L_REQUIRE(herr == 0, IGA2L_ENUMERIC, "a Schwarz block matrix is not positive definite");
+}
+
+}  // namespace iga2l

@@ -1,0 +1,523 @@
+// setup_host.cpp -- host-side set-up of the gfx950 two-level solver: B-spline
+// evaluation, 1-D element matrices, assembly of the fine operator in
+// symmetric padded-diagonal form, the restriction factor, the degree-1 V-cycle
+// hierarchy, the DST tables of the exact coarse solver, Schwarz block classes
+// and the lexicographic hyperplane schedule.  Runs once per problem; every
+// per-cycle operation runs in the HIP kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace iga2l {
+
+namespace {
+
+int64_t ipow(int64_t b, int e) {
+    int64_t r = 1;
+    while (e-- > 0) r *= b;
+    return r;
+}
+
+// Gauss-Legendre rule on [-1,1], nodes by Newton iteration on P_q.
+void gauss_rule(int q, double *x, double *w) {
+    for (int i = 0; i < q; ++i) {
+        double z = std::cos(M_PI * (4.0 * i + 3.0) / (4.0 * q + 2.0));
+        double p0 = 1.0, p1 = z, dp = 1.0;
+        for (int it = 0; it < 64; ++it) {
+            p0 = 1.0;
+            p1 = z;
+            for (int k = 2; k <= q; ++k) {
+                double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (q == 1) { p1 = z; p0 = 1.0; }
+            dp = q * (z * p1 - p0) / (z * z - 1.0);
+            double step = p1 / dp;
+            z -= step;
+            if (std::fabs(step) < 1e-17) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Values and first derivatives of the p+1 B-splines of degree p that are live
+// on knot span s (t[s] <= x < t[s+1]): out index a <-> function s-p+a.
+// The triangle of lower-degree values is built stage by stage with the
+// Cox-de Boor step restricted to live functions.
+void live_values(const std::vector<double> &t, int p, int s, double x, double *val, double *der) {
+    double stage[kMaxP + 1], next[kMaxP + 1], prev_stage[kMaxP + 1];
+    stage[0] = 1.0;  // degree 0: only N_s is live
+    for (int a = 0; a <= p; ++a) prev_stage[a] = 0.0;
+    for (int k = 1; k <= p; ++k) {
+        // stage holds N^{k-1}_{s-k+1+b}, b = 0..k-1; next gets N^k_{s-k+a}, a = 0..k
+        for (int a = 0; a <= k; ++a) {
+            int i = s - k + a;
+            double lo = (a >= 1) ? stage[a - 1] : 0.0;      // N^{k-1}_i
+            double hi = (a <= k - 1) ? stage[a] : 0.0;      // N^{k-1}_{i+1}
+            double d1 = t[i + k] - t[i], d2 = t[i + k + 1] - t[i + 1];
+            double v = 0.0;
+            if (d1 > 0.0) v += (x - t[i]) / d1 * lo;
+            if (d2 > 0.0) v += (t[i + k + 1] - x) / d2 * hi;
+            next[a] = v;
+        }
+        if (k == p) {
+            for (int b = 0; b < k; ++b) prev_stage[b] = stage[b];
+        }
+        for (int a = 0; a <= k; ++a) stage[a] = next[a];
+    }
+    for (int a = 0; a <= p; ++a) val[a] = stage[a];
+    if (der) {
+        if (p == 0) {
+            der[0] = 0.0;
+            return;
+        }
+        for (int a = 0; a <= p; ++a) {
+            int i = s - p + a;
+            double lo = (a >= 1) ? prev_stage[a - 1] : 0.0;
+            double hi = (a <= p - 1) ? prev_stage[a] : 0.0;
+            double d1 = t[i + p] - t[i], d2 = t[i + p + 1] - t[i + 1];
+            double v = 0.0;
+            if (d1 > 0.0) v += p / d1 * lo;
+            if (d2 > 0.0) v -= p / d2 * hi;
+            der[a] = v;
+        }
+    }
+}
+
+std::vector<double> open_uniform_knots(int p, int m) {
+    std::vector<double> t(2 * p + m + 1);
+    for (int i = 0; i < (int)t.size(); ++i) t[i] = std::min(1.0, std::max(0.0, double(i - p) / m));
+    return t;
+}
+
+// 1-D element stiffness/mass matrices of degree p on all m elements,
+// [(p+1) x (p+1)] row-major each; Gauss rule with p+1 points (exact).
+void element_matrices(int p, int m, std::vector<std::vector<double>> &Ke, std::vector<std::vector<double>> &Me) {
+    auto t = open_uniform_knots(p, m);
+    double gx[kMaxP + 4], gw[kMaxP + 4];
+    int q = p + 1;
+    gauss_rule(q, gx, gw);
+    double h = 1.0 / m;
+    Ke.assign(m, std::vector<double>((p + 1) * (p + 1), 0.0));
+    Me.assign(m, std::vector<double>((p + 1) * (p + 1), 0.0));
+    double v[kMaxP + 1], dv[kMaxP + 1];
+    for (int e = 0; e < m; ++e) {
+        for (int k = 0; k < q; ++k) {
+            double x = (e + 0.5 * (gx[k] + 1.0)) * h, wq = 0.5 * h * gw[k];
+            live_values(t, p, p + e, x, v, dv);
+            for (int a = 0; a <= p; ++a)
+                for (int b = 0; b <= p; ++b) {
+                    Ke[e][a * (p + 1) + b] += wq * dv[a] * dv[b];
+                    Me[e][a * (p + 1) + b] += wq * v[a] * v[b];
+                }
+        }
+    }
+}
+
+// linear index <-> multi-index over a box of extent n in each of dim directions
+inline void split(int64_t idx, int dim, int64_t n, int *out) {
+    for (int k = 0; k < dim; ++k) {
+        out[k] = int(idx % n);
+        idx /= n;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ assembly --
+void host_assemble(Problem &P) {
+    const int p = P.p, m = P.m, d = P.dim;
+    const int n1 = m + p - 2, n1c = m - 1;
+    P.fine = Grid{d, n1, ipow(n1, d)};
+    P.coarse = Grid{d, n1c, ipow(n1c, d)};
+    P.ne = ipow(m, d);
+
+    element_matrices(p, m, P.Ke, P.Me);
+
+    // interior 1-D factors K1, M1: entry (i, i+o) at [i][o+p]
+    const int w1 = 2 * p + 1;
+    P.K1.assign(size_t(n1) * w1, 0.0);
+    P.M1.assign(size_t(n1) * w1, 0.0);
+    for (int e = 0; e < m; ++e)
+        for (int a = 0; a <= p; ++a)
+            for (int b = 0; b <= p; ++b) {
+                int i = e + a - 1, j = e + b - 1;
+                if (i < 0 || i >= n1 || j < 0 || j >= n1) continue;
+                P.K1[size_t(i) * w1 + (j - i + p)] += P.Ke[e][a * (p + 1) + b];
+                P.M1[size_t(i) * w1 + (j - i + p)] += P.Me[e][a * (p + 1) + b];
+            }
+
+    // restriction factor: R1 = D1^{-1} Mmix1 with D1 the row sums of the
+    // Dirichlet-reduced degree-1 mass matrix (row-sum lumping)
+    {
+        auto tf = open_uniform_knots(p, m), tc = open_uniform_knots(1, m);
+        double gx[kMaxP + 4], gw[kMaxP + 4];
+        int q = p + 1;
+        gauss_rule(q, gx, gw);
+        double h = 1.0 / m;
+        std::vector<double> mix(size_t(n1c) * (p + 2), 0.0), lump(n1c, 0.0);
+        double v[kMaxP + 1], vc[2];
+        for (int e = 0; e < m; ++e)
+            for (int k = 0; k < q; ++k) {
+                double x = (e + 0.5 * (gx[k] + 1.0)) * h, wq = 0.5 * h * gw[k];
+                live_values(tf, p, p + e, x, v, nullptr);
+                live_values(tc, 1, 1 + e, x, vc, nullptr);
+                for (int c = 0; c < 2; ++c) {
+                    int I = e + c - 1;
+                    if (I < 0 || I >= n1c) continue;
+                    for (int c2 = 0; c2 < 2; ++c2) {
+                        int J = e + c2 - 1;
+                        if (J < 0 || J >= n1c) continue;
+                        lump[I] += wq * vc[c] * vc[c2];
+                    }
+                    for (int a = 0; a <= p; ++a) {
+                        int j = e + a - 1;
+                        if (j < 0 || j >= n1) continue;
+                        mix[size_t(I) * (p + 2) + (j - I + 1)] += wq * vc[c] * v[a];
+                    }
+                }
+            }
+        P.R1.assign(mix.size(), 0.0);
+        for (int I = 0; I < n1c; ++I)
+            for (int a = 0; a < p + 2; ++a) P.R1[size_t(I) * (p + 2) + a] = mix[size_t(I) * (p + 2) + a] / lump[I];
+    }
+
+    // fine operator in symmetric padded-diagonal form
+    SymDia &A = P.A;
+    A.q = p;
+    A.W = int(ipow(w1, d));
+    A.Wh = (A.W + 1) / 2;
+    const int np1 = n1 + 2 * p;
+    A.pitch[0] = 1;
+    A.pitch[1] = np1;
+    A.pitch[2] = np1 * np1;
+    A.npad = ipow(np1, d);
+    std::vector<double> val(size_t(A.Wh) * A.npad, 0.0);
+    const int c0 = (A.W - 1) / 2;
+    const int nl = p + 1;
+    const int64_t nloc = ipow(nl, d);
+    int e[kMaxDim] = {0, 0, 0}, a[kMaxDim] = {0, 0, 0}, b[kMaxDim] = {0, 0, 0};
+    for (int64_t el = 0; el < P.ne; ++el) {
+        split(el, d, m, e);
+        const double kap = P.kappa_one ? 1.0 : P.kappa[el];
+        for (int64_t la = 0; la < nloc; ++la) {
+            split(la, d, nl, a);
+            bool in = true;
+            int64_t padi = 0;
+            for (int k = 0; k < d; ++k) {
+                int ik = e[k] + a[k] - 1;
+                if (ik < 0 || ik >= n1) in = false;
+                padi += int64_t(ik + p) * A.pitch[k];
+            }
+            if (!in) continue;
+            for (int64_t lb = 0; lb < nloc; ++lb) {
+                split(lb, d, nl, b);
+                bool inb = true;
+                int widx = 0;
+                for (int k = d - 1; k >= 0; --k) {
+                    int jk = e[k] + b[k] - 1;
+                    if (jk < 0 || jk >= n1) inb = false;
+                    widx = widx * w1 + (b[k] - a[k] + p);
+                }
+                if (!inb || widx < c0) continue;  // lower half implied by symmetry
+                double term = 0.0;
+                for (int c = 0; c < d; ++c) {
+                    double prod = 1.0;
+                    for (int k = 0; k < d; ++k) {
+                        const auto &Mk = (k == c) ? P.Ke[e[k]] : P.Me[e[k]];
+                        prod *= Mk[a[k] * nl + b[k]];
+                    }
+                    term += prod;
+                }
+                val[size_t(widx - c0) * A.npad + padi] += kap * term;
+            }
+        }
+    }
+    A.v64.alloc(val.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(A.v64.ptr, val.data(), val.size() * sizeof(double), hipMemcpyHostToDevice));
+
+    P.R1d64.alloc(P.R1.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.R1d64.ptr, P.R1.data(), P.R1.size() * sizeof(double), hipMemcpyHostToDevice));
+
+    // 1-D element matrices for the gradient kernel: [m][2][(p+1)^2] (K then M)
+    std::vector<double> km(size_t(m) * 2 * nl * nl);
+    for (int el = 0; el < m; ++el)
+        for (int k = 0; k < nl * nl; ++k) {
+            km[(size_t(el) * 2 + 0) * nl * nl + k] = P.Ke[el][k];
+            km[(size_t(el) * 2 + 1) * nl * nl + k] = P.Me[el][k];
+        }
+    P.Ke_d.alloc(km.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.Ke_d.ptr, km.data(), km.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<double> kap(P.ne, 1.0);
+    if (!P.kappa_one) kap = P.kappa;
+    P.kappa_d.alloc(kap.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.kappa_d.ptr, kap.data(), kap.size() * sizeof(double), hipMemcpyHostToDevice));
+
+    // workspaces sized by the fine grid
+    const size_t nf = size_t(P.fine.n), nc = size_t(P.coarse.n);
+    P.r64.alloc(nf * sizeof(double));
+    P.ework[0].alloc(nf * sizeof(double));
+    P.ework[1].alloc(nf * sizeof(double));
+    P.rhs_w.alloc(nf * sizeof(double));
+    P.dfine.alloc(nf * sizeof(double));
+    P.lam_tmp.alloc(nf * sizeof(double));
+    P.dc.alloc(nc * sizeof(double));
+    P.ec.alloc(nc * sizeof(double));
+    P.ctmp.alloc(nc * sizeof(double));
+    P.npartial = int(residual_workgroups(P));
+    P.partial.alloc(size_t(P.npartial) * sizeof(double));
+    P.scal.alloc(kScalCount * sizeof(double));
+    IGA2L_HIP(hipMemset(P.scal.ptr, 0, kScalCount * sizeof(double)));
+}
+
+// ---------------------------------------------------- V-cycle hierarchy --
+// Level 0: the degree-1 stiffness on the same knots and kappa, full 3^d
+// stencil.  Coarser levels: coarse nodes are the odd-indexed interior nodes
+// (0-based) of the finer level, P = linear interpolation, A_c = P^T A P,
+// down to a single node per direction.
+void host_build_levels(Problem &P) {
+    const int d = P.dim, m = P.m;
+    const int W3 = int(ipow(3, d));
+    std::vector<std::vector<double>> ops;
+    std::vector<int> sizes;
+    {
+        // degree-1 element matrices: K = (1/h)[1 -1; -1 1], M = (h/6)[2 1; 1 2]
+        std::vector<std::vector<double>> Kc, Mc;
+        element_matrices(1, m, Kc, Mc);
+        int n1 = m - 1;
+        std::vector<double> S(size_t(W3) * ipow(n1, d), 0.0);
+        int e[kMaxDim] = {0, 0, 0}, a[kMaxDim] = {0, 0, 0}, b[kMaxDim] = {0, 0, 0};
+        const int64_t n = ipow(n1, d);
+        for (int64_t el = 0; el < P.ne; ++el) {
+            split(el, d, m, e);
+            double kap = P.kappa_one ? 1.0 : P.kappa[el];
+            for (int la = 0; la < (1 << d); ++la) {
+                for (int k = 0; k < d; ++k) a[k] = (la >> k) & 1;
+                int64_t row = 0;
+                bool in = true;
+                for (int k = d - 1; k >= 0; --k) {
+                    int ik = e[k] + a[k] - 1;
+                    if (ik < 0 || ik >= n1) in = false;
+                    row = row * n1 + ik;
+                }
+                if (!in) continue;
+                for (int lb = 0; lb < (1 << d); ++lb) {
+                    for (int k = 0; k < d; ++k) b[k] = (lb >> k) & 1;
+                    bool inb = true;
+                    int w = 0;
+                    for (int k = d - 1; k >= 0; --k) {
+                        int jk = e[k] + b[k] - 1;
+                        if (jk < 0 || jk >= n1) inb = false;
+                        w = w * 3 + (b[k] - a[k] + 1);
+                    }
+                    if (!inb) continue;
+                    double term = 0.0;
+                    for (int c = 0; c < d; ++c) {
+                        double prod = 1.0;
+                        for (int k = 0; k < d; ++k) prod *= ((k == c) ? Kc[e[k]] : Mc[e[k]])[a[k] * 2 + b[k]];
+                        term += prod;
+                    }
+                    S[size_t(w) * n + row] += kap * term;
+                }
+            }
+        }
+        ops.push_back(std::move(S));
+        sizes.push_back(n1);
+    }
+    while (sizes.back() > 1) {
+        const int nf1 = sizes.back(), nc1 = nf1 / 2;
+        const int64_t nf = ipow(nf1, d), nc = ipow(nc1, d);
+        const std::vector<double> &Sf = ops.back();
+        std::vector<double> Sc(size_t(W3) * nc, 0.0);
+        // parents of a fine 1-D index: odd i -> (i-1)/2 weight 1; even i -> i/2-1, i/2 weight 1/2
+        auto parents = [nc1](int i, int *I, double *w) {
+            int cnt = 0;
+            if (i & 1) {
+                I[cnt] = (i - 1) / 2; w[cnt++] = 1.0;
+            } else {
+                if (i / 2 - 1 >= 0) { I[cnt] = i / 2 - 1; w[cnt++] = 0.5; }
+                if (i / 2 < nc1) { I[cnt] = i / 2; w[cnt++] = 0.5; }
+            }
+            return cnt;
+        };
+        int ix[kMaxDim] = {0, 0, 0}, o[kMaxDim] = {0, 0, 0}, jx[kMaxDim] = {0, 0, 0};
+        int PI[kMaxDim][2], PJ[kMaxDim][2], npi[kMaxDim], npj[kMaxDim];
+        double WI[kMaxDim][2], WJ[kMaxDim][2];
+        for (int64_t i = 0; i < nf; ++i) {
+            split(i, d, nf1, ix);
+            for (int k = 0; k < d; ++k) npi[k] = parents(ix[k], PI[k], WI[k]);
+            for (int w = 0; w < W3; ++w) {
+                double aij = Sf[size_t(w) * nf + i];
+                if (aij == 0.0) continue;
+                split(w, d, 3, o);
+                bool in = true;
+                for (int k = 0; k < d; ++k) {
+                    jx[k] = ix[k] + o[k] - 1;
+                    if (jx[k] < 0 || jx[k] >= nf1) in = false;
+                }
+                if (!in) continue;
+                for (int k = 0; k < d; ++k) npj[k] = parents(jx[k], PJ[k], WJ[k]);
+                // all combinations of parents per direction
+                int ci[kMaxDim] = {0, 0, 0};
+                int64_t combos_i = 1;
+                for (int k = 0; k < d; ++k) combos_i *= npi[k];
+                for (int64_t ca = 0; ca < combos_i; ++ca) {
+                    int64_t t = ca;
+                    double wi = 1.0;
+                    int64_t I = 0;
+                    for (int k = 0; k < d; ++k) { ci[k] = int(t % npi[k]); t /= npi[k]; wi *= WI[k][ci[k]]; }
+                    for (int k = d - 1; k >= 0; --k) I = I * nc1 + PI[k][ci[k]];
+                    int64_t combos_j = 1;
+                    for (int k = 0; k < d; ++k) combos_j *= npj[k];
+                    for (int64_t cb = 0; cb < combos_j; ++cb) {
+                        int64_t tt = cb;
+                        double wj = 1.0;
+                        int wc = 0;
+                        int cj[kMaxDim];
+                        for (int k = 0; k < d; ++k) { cj[k] = int(tt % npj[k]); tt /= npj[k]; wj *= WJ[k][cj[k]]; }
+                        for (int k = d - 1; k >= 0; --k) wc = wc * 3 + (PJ[k][cj[k]] - PI[k][ci[k]] + 1);
+                        Sc[size_t(wc) * nc + I] += wi * aij * wj;
+                    }
+                }
+            }
+        }
+        ops.push_back(std::move(Sc));
+        sizes.push_back(nc1);
+    }
+    P.levels.clear();
+    P.levels.resize(ops.size());
+    for (size_t l = 0; l < ops.size(); ++l) {
+        Level &L = P.levels[l];
+        L.g = Grid{d, sizes[l], ipow(sizes[l], d)};
+        const auto &S = ops[l];
+        L.S64.alloc(S.size() * sizeof(double));
+        IGA2L_HIP(hipMemcpy(L.S64.ptr, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+        std::vector<float> s32(S.begin(), S.end());
+        L.S32.alloc(s32.size() * sizeof(float));
+        IGA2L_HIP(hipMemcpy(L.S32.ptr, s32.data(), s32.size() * sizeof(float), hipMemcpyHostToDevice));
+        const size_t nb = size_t(L.g.n) * sizeof(double);
+        L.e[0].alloc(nb);
+        L.e[1].alloc(nb);
+        L.rhs.alloc(nb);
+        L.res.alloc(nb);
+        if (L.g.n == 1) L.coarsest_diag = S[(W3 - 1) / 2];
+    }
+    P.vcycle_ready = true;
+}
+
+// ------------------------------------------------------- exact coarse --
+// For kappa = 1 the degree-1 operator on the uniform mesh is a sum of
+// Kronecker products of (1/h) tridiag(-1,2,-1) and (h/6) tridiag(1,4,1), all
+// diagonalised by the orthonormal DST-I matrix S_ik = sqrt(2/m) sin((i+1)(k+1)pi/m).
+void host_build_dst(Problem &P) {
+    const int m = P.m, n1 = m - 1, d = P.dim;
+    const double h = 1.0 / m;
+    std::vector<double> S(size_t(n1) * n1), lk(n1), lm(n1);
+    for (int i = 0; i < n1; ++i)
+        for (int k = 0; k < n1; ++k) S[size_t(i) * n1 + k] = std::sqrt(2.0 / m) * std::sin((i + 1.0) * (k + 1.0) * M_PI / m);
+    for (int k = 0; k < n1; ++k) {
+        double th = (k + 1.0) * M_PI / m;
+        lk[k] = (2.0 / h) * (1.0 - std::cos(th));
+        lm[k] = (h / 3.0) * (2.0 + std::cos(th));
+    }
+    const int64_t n = ipow(n1, d);
+    std::vector<double> mu(n);
+    int ix[kMaxDim] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        split(i, d, n1, ix);
+        double s = 0.0;
+        for (int c = 0; c < d; ++c) {
+            double prod = 1.0;
+            for (int k = 0; k < d; ++k) prod *= (k == c) ? lk[ix[k]] : lm[ix[k]];
+            s += prod;
+        }
+        mu[i] = s;
+    }
+    P.dst_S.alloc(S.size() * sizeof(double));
+    P.dst_mu.alloc(mu.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.dst_S.ptr, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+    IGA2L_HIP(hipMemcpy(P.dst_mu.ptr, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice));
+    P.direct_ready = true;
+}
+
+// ------------------------------------------------------- block classes --
+// A block matrix depends only on the 1-D position class of its centre in each
+// direction when kappa = 1 (the operator is a sum of Kronecker products of
+// 1-D factors).  Centres within L = p-1+hb of either end form individual
+// classes; all others share the uniform interior class.  With a variable
+// coefficient every DOF is its own class.  reps gets one representative
+// centre (linear DOF index) per inverse slot; slot = sum_k cls[j_k] ncls^k.
+void host_block_classes(Problem &P, std::vector<int> &cls1, std::vector<int64_t> &reps) {
+    const int n1 = P.fine.n1, d = P.dim, hb = (P.bw - 1) / 2;
+    const int L = P.p - 1 + hb;
+    std::vector<int> rep1;
+    cls1.assign(n1, 0);
+    if (P.kappa_one && n1 >= 2 * L + 2) {
+        P.shared_inverses = true;
+        P.ncls1 = 2 * L + 1;
+        for (int j = 0; j < n1; ++j) {
+            if (j < L) cls1[j] = j;
+            else if (j > n1 - 1 - L) cls1[j] = L + 1 + (j - (n1 - L));
+            else cls1[j] = L;
+        }
+        rep1.resize(P.ncls1);
+        for (int j = n1 - 1; j >= 0; --j) rep1[cls1[j]] = j;
+    } else {
+        P.shared_inverses = false;
+        P.ncls1 = n1;
+        rep1.resize(n1);
+        for (int j = 0; j < n1; ++j) cls1[j] = rep1[j] = j;
+    }
+    P.nslots = ipow(P.ncls1, d);
+    reps.resize(P.nslots);
+    int c[kMaxDim] = {0, 0, 0};
+    for (int64_t s = 0; s < P.nslots; ++s) {
+        split(s, d, P.ncls1, c);
+        int64_t j = 0;
+        for (int k = d - 1; k >= 0; --k) j = j * n1 + rep1[c[k]];
+        reps[s] = j;
+    }
+}
+
+// ------------------------------------------------- lexicographic schedule --
+// Block j runs at step t(j) = j_x + S j_y + S^2 j_z with S = bw + p: two blocks
+// that interact (centres closer than bw + p in every direction) are then
+// ordered as in the lexicographic sequence, and blocks of one step never
+// interact, so each step may run all its blocks at once.
+void host_lex_schedule(Problem &P) {
+    const int n1 = P.fine.n1, d = P.dim;
+    const int64_t S = P.bw + P.p;
+    const int64_t n = P.fine.n;
+    std::vector<int64_t> tj(n);
+    int64_t tmax = 0;
+    int ix[kMaxDim] = {0, 0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+        split(j, d, n1, ix);
+        int64_t t = 0;
+        for (int k = d - 1; k >= 0; --k) t = t * S + ix[k];
+        tj[j] = t;
+        tmax = std::max(tmax, t);
+    }
+    std::vector<int> count(tmax + 2, 0);
+    for (int64_t j = 0; j < n; ++j) count[tj[j] + 1]++;
+    // compress empty steps away
+    std::vector<int> off;
+    off.push_back(0);
+    std::vector<int64_t> order(n);
+    std::vector<int> start(tmax + 2, 0);
+    for (int64_t t = 0; t <= tmax; ++t) start[t + 1] = start[t] + count[t + 1];
+    std::vector<int> fill(start.begin(), start.end());
+    for (int64_t j = 0; j < n; ++j) order[fill[tj[j]]++] = j;
+    for (int64_t t = 0; t <= tmax; ++t)
+        if (count[t + 1] > 0) off.push_back(start[t + 1]);
+    P.lex_off = off;
+    std::vector<int> blocks(order.begin(), order.end());
+    P.lex_blocks.alloc(blocks.size() * sizeof(int));
+    IGA2L_HIP(hipMemcpy(P.lex_blocks.ptr, blocks.data(), blocks.size() * sizeof(int), hipMemcpyHostToDevice));
+}
+
+}  // namespace iga2l
