@@ -1,0 +1,201 @@
+"""Benchmark of the two-level isogeometric solver on one MI355X.
+
+Workload (headline): 2-D Poisson on the unit square, tensor B-splines of
+degree p=3 with maximal smoothness on 256x256 elements (66049 fine DOFs),
+homogeneous Dirichlet, load vector b ~ N(0,1) (seed 0).  Two-level method:
+one coloured overlapping multiplicative Schwarz sweep with 3x3 blocks, lumped
+L2 restriction to p=1 on the same knots, one V(2,2) red-black Gauss-Seidel
+cycle on the coarse level, prolongation by the transpose.  A step is one full
+solve from u=0 to a 1e-10 residual reduction; the inputs are resident on the
+GPU before the timed region.
+
+value   = fine DOF/s per two-level cycle of the mixed-precision solver
+          (FP32 smoother/defect/transfers/V-cycle, FP64 residual and update):
+          n_fine * cycles / solve time.
+Also reported: time-to-1e-10 for mixed and FP64, their ratio, the error of
+both against the CPU oracle's converged solution, the roofline of the
+dominant kernel (HIP-event timed inside this script) and the CPU oracle on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+FP64_PEAK_TFS = 78.6        # MI355X FP64 vector, published
+FP32_PEAK_TFS = 157.3       # MI355X FP32 vector, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--m", type=int, default=256)
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg (profiling runs)")
+    ap.add_argument("--no-roofline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(d, p, m, b, nu, cycles_gpu):
+    """The CPU oracle (plain serial C, -O2, 1 thread) on a bounded sample of the
+    same workload: set-up, then the same coloured cycles from u=0, stopped
+    after ~15 s of cycles.  Returns (record, converged oracle solution or None)."""
+    import oracle as O
+    t0 = time.perf_counter()
+    orc = O.Problem(d, p, m, vcycle=True, coarse_direct=False)
+    t_setup = time.perf_counter() - t0
+    u = np.zeros(orc.n)
+    r0 = np.linalg.norm(orc.residual(u, b))
+    ncyc, t_cyc, rel = 0, 0.0, 1.0
+    while rel > 1e-10 and t_cyc < 15.0 and ncyc < 60:
+        t1 = time.perf_counter()
+        u = orc.cycle(u, b, coarse=O.VCYCLE, cnu1=nu[0], cnu2=nu[1])
+        t_cyc += time.perf_counter() - t1
+        ncyc += 1
+        rel = np.linalg.norm(orc.residual(u, b)) / r0
+    rec = {"value": orc.n * ncyc / t_cyc, "unit": "fine DOF/s per two-level cycle", "cores": 1, "kind": "oracle",
+           "sample": f"{ncyc} FP64 cycles of the same 2-D p={p} {m}x{m} coloured/V(2,2) solve from u=0 "
+                     f"(relres {rel:.1e}); set-up {t_setup:.1f}s excluded",
+           "seconds_per_cycle": t_cyc / ncyc, "host_cpu": _cpu_model(), "nproc": os.cpu_count()}
+    return rec, (u if rel <= 1e-10 else None)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def event_time(torch, fn, reps):
+    """Average duration (ms) of fn() over reps calls, with HIP events on the
+    current stream (the stream the library launches on)."""
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2009_01499_amd as G
+    import synth
+
+    d, p, m = 2, args.p, args.m
+    nu = (2, 2)
+    b_np = synth.rhs_normal(d, p, m, seed=0)
+    dev = torch.device("cuda:0")
+    b = torch.tensor(b_np, device=dev)
+    t0 = time.perf_counter()
+    prob = G.Problem(d, p, m, device=0)
+    prob.setup(0, G.Opts(coarse=G.COARSE_VCYCLE, precision=G.MIXED_FP32))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    n = prob.n
+    o_mixed = G.Opts(coarse=G.COARSE_VCYCLE, nu1=nu[0], nu2=nu[1], precision=G.MIXED_FP32, tol=1e-10)
+    o_fp64 = G.Opts(coarse=G.COARSE_VCYCLE, nu1=nu[0], nu2=nu[1], precision=G.FP64, tol=1e-10)
+    u = torch.zeros_like(b)
+
+    def solve(opts):
+        u.zero_()
+        _, info = prob.solve(b, u, opts)
+        return info
+
+    for _ in range(args.warmup):
+        solve(o_mixed)
+        solve(o_fp64)
+    # ---- timed region: K mixed-precision solves
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles = 0
+    for _ in range(args.steps):
+        cycles += solve(o_mixed).iters
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    u_mixed = u.cpu().numpy().copy()
+    # ---- the same for FP64 (comparison)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles64 = 0
+    for _ in range(args.steps):
+        cycles64 += solve(o_fp64).iters
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t0
+    u_fp64 = u.cpu().numpy().copy()
+
+    ms_step = 1e3 * t_mixed / args.steps
+    value = n * cycles / t_mixed
+    out = {
+        "metric": "fine DOF/s per two-level cycle (mixed precision), with time-to-1e-10 vs FP64",
+        "value": value, "unit": "fine DOF/s per cycle",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"2D Poisson p={p} {m}x{m} elements ({n} DOFs), coloured 3x3 Schwarz, "
+                               f"p=1 coarse V({nu[0]},{nu[1]}) RB-GS, tol 1e-10, b~N(0,1) seed 0",
+                   "dim": d, "p": p, "m": m, "n_fine": n, "block_width": 3, "ordering": "colour s=b"},
+        "time_to_tol_ms": {"mixed": ms_step, "fp64": 1e3 * t_fp64 / args.steps},
+        "cycles": {"mixed": cycles / args.steps, "fp64": cycles64 / args.steps},
+        "fp64_value": n * cycles64 / t_fp64,
+        "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
+        "setup_s": t_setup,
+    }
+    # ---- roofline of the dominant kernel, HIP-event timed
+    if not args.no_roofline:
+        sweep_opts = G.Opts()
+        uu = torch.zeros_like(b)
+        ncol = 9
+        ms_sweep = event_time(torch, lambda: prob.smooth(uu, b, 1, sweep_opts), 50)
+        ms_col = ms_sweep / ncol
+        # algorithmic bytes per colour launch (FP64 smoother on the symmetric
+        # padded-diagonal operator): x, rhs read, x' write (24 B) + 25 upper
+        # diagonals (200 B) per DOF; the shared block inverses are cache-resident
+        bytes_per_dof = 24 + 8 * ((2 * p + 1) ** 2 + 1) // 2
+        achieved = bytes_per_dof * n / (ms_col * 1e-3) / 1e9
+        out["roofline"] = {"kernel": "k_colour<2,3,3,double> (one colour of the Schwarz sweep)",
+                           "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "avg_launch_us": ms_col * 1e3, "algorithmic_bytes_per_launch": bytes_per_dof * n}
+        r = torch.empty_like(b)
+        ms_res = event_time(torch, lambda: prob.residual(uu, b, r), 100)
+        ach_res = bytes_per_dof * n / (ms_res * 1e-3) / 1e9
+        out["roofline_residual"] = {"kernel": "k_residual<2,3,double>", "achieved": ach_res, "unit": "GB/s",
+                                    "frac": ach_res / HBM_PEAK_GBS, "avg_launch_us": ms_res * 1e3}
+    # ---- CPU oracle leg
+    if not args.no_cpu_baseline:
+        rec, u_orc = cpu_baseline(d, p, m, b_np, nu, out["cycles"]["mixed"])
+        out["cpu_baseline"] = rec
+        if u_orc is not None:
+            nrm = np.linalg.norm(u_orc)
+            out["error_vs_oracle"] = {"mixed": float(np.linalg.norm(u_mixed - u_orc) / nrm),
+                                      "fp64": float(np.linalg.norm(u_fp64 - u_orc) / nrm)}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -375,9 +375,23 @@ int iga2l_smooth(const iga2l_problem *prob, double *u, const double *b, int nswe
                 for (size_t st = 0; st + 1 < P.lex_off.size(); ++st) launch_lex_step(P, int(st), u, b, s);
             } else {
                 const int S = o.colour_period ? o.colour_period : P.bw;
-                IGA2L_HIP(hipMemcpyAsync(P.ework[0].ptr, u, bytes, hipMemcpyDeviceToDevice, s));
-                const int cur = sweep_colour<double>(P, S, b, 0, false, s);
-                IGA2L_HIP(hipMemcpyAsync(u, P.ework[cur].ptr, bytes, hipMemcpyDeviceToDevice, s));
+                const int ncol = (P.dim == 3) ? S * S * S : S * S;
+                if (ncol == 1) {
+                    IGA2L_HIP(hipMemcpyAsync(P.ework[0].ptr, u, bytes, hipMemcpyDeviceToDevice, s));
+                    launch_colour_step<double>(P, 0, 0, 0, S, P.ework[0].as<double>(), u, b, false, s);
+                    continue;
+                }
+                // u -> w0 -> w1 -> w0 ... -> u: one kernel per colour, each reading the
+                // colour-start iterate and writing the next one
+                const double *src = u;
+                int c = 0;
+                for (int cz = 0; cz < ((P.dim == 3) ? S : 1); ++cz)
+                    for (int cy = 0; cy < S; ++cy)
+                        for (int cx = 0; cx < S; ++cx, ++c) {
+                            double *dst = (c == ncol - 1) ? u : P.ework[c & 1].as<double>();
+                            launch_colour_step<double>(P, cx, cy, cz, S, src, dst, b, false, s);
+                            src = dst;
+                        }
             }
         }
         IGA2L_HIP(hipGetLastError());
