@@ -85,12 +85,24 @@ struct SymDia {
 };
 
 // One level of the degree-1 V-cycle hierarchy: full 3^d stencil by offset,
-// stored [3^d][n] (structure of arrays).
+// stored [3^d][n] (structure of arrays), and the reciprocal diagonal.
 struct Level {
     Grid g;
-    DevBuf S64, S32;
+    DevBuf S64, S32, invd64, invd32;
     DevBuf e[2], rhs, res;       // working vectors, sized for FP64 (FP32 reuses them)
-    double coarsest_diag = 0.0;  // n == 1 only
+    bool cst = false;            // translation-invariant stencil (interior row everywhere)
+};
+
+// Level descriptor handed to the V-cycle kernels (by value or in a device array).
+template <class T>
+struct LevelDev {
+    int n1;
+    int cst;          // 1: use c[] / cinv instead of S / invd
+    int64_t n;
+    const T *S;       // [3^d][n]
+    const T *invd;    // [n]
+    T c[27];          // interior stencil (cst only)
+    T cinv;           // 1 / centre coefficient (cst only)
 };
 
 struct Problem {
@@ -126,6 +138,10 @@ struct Problem {
 
     // coarse
     std::vector<Level> levels;    // V-cycle hierarchy, level 0 = A_1 on the same knots
+    std::vector<LevelDev<double>> levhost64;
+    std::vector<LevelDev<float>> levhost32;
+    DevBuf levdev64, levdev32;    // the same descriptors on the device
+    size_t vc_bottom64 = 0, vc_bottom32 = 0;  // first level run by the one-workgroup kernel
     bool vcycle_ready = false;
     DevBuf dst_S, dst_mu;         // DST-I matrix [n1c][n1c], eigenvalues [n_c]
     bool direct_ready = false;
@@ -182,6 +198,8 @@ void launch_prolong_update(const Problem &P, const T *ec, const T *e, double *u,
 template <class T>
 void launch_vcycle(Problem &P, const T *rhs, T *e, int nu1, int nu2, hipStream_t s);
 void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s);
+int64_t vcycle_bottom_lds(const Problem &P, size_t lb);   // LDS elements of the one-workgroup tail
+bool vcycle_bottom_fits(const Problem &P, size_t lb);
 void launch_convert(const void *src, void *dst, int64_t n, bool to_fp32, hipStream_t s);
 // gradient
 void launch_grad_kappa(const Problem &P, const double *u, const double *lam, double *g, hipStream_t s);

@@ -1,9 +1,9 @@
 // kernels_coarse.hip -- transfer, coarse-level and auxiliary kernels of the
 // two-level solver on gfx950: restriction by the lumped L2 projection and its
-// adjoint prolongation (tensor products of the 1-D factor R1), the degree-1
-// h-multigrid V-cycle (red-black Gauss-Seidel, linear interpolation, Galerkin
-// operators), the exact coarse solve for kappa = 1 by DST-I diagonalisation,
-// precision conversions and the element-wise kappa-gradient of the adjoint.
+// adjoint prolongation (tensor products of the 1-D factor R1), the exact
+// coarse solve for kappa = 1 by DST-I diagonalisation, precision conversions
+// and the element-wise kappa-gradient of the adjoint.  The V-cycle lives in
+// kernels_vcycle.hip.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -94,126 +94,6 @@ __global__ void k_prolong_update(const T *__restrict__ R1, int p, int n1f, int n
     u[i] += scaled ? scal[kScalSigma] * double(corr) : double(corr);
 }
 
-// --------------------------------------------------------------- V-cycle --
-// Red-black half step on a level: points of the given colour (parity of the
-// index sum) are updated from e_src, the others copied; e_dst != e_src.
-template <int D, class T>
-__global__ void k_rb_half(const T *__restrict__ S, int n1, int colour, const T *__restrict__ e_src,
-                          const T *__restrict__ rhs, T *__restrict__ e_dst, int zero_src) {
-    const int64_t n = (D == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int ix = int(i % n1), iy = int((i / n1) % n1), iz = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
-    const T ei = zero_src ? T(0) : e_src[i];
-    if (((ix + iy + iz) & 1) != colour) {
-        e_dst[i] = ei;
-        return;
-    }
-    constexpr int W3 = (D == 3) ? 27 : 9;
-    constexpr int c0 = (W3 - 1) / 2;
-    T acc = T(0);
-    if (!zero_src) {
-        int w = 0;
-        for (int oz = ((D == 3) ? -1 : 0); oz <= ((D == 3) ? 1 : 0); ++oz)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int ox = -1; ox <= 1; ++ox, ++w) {
-                    const int jx = ix + ox, jy = iy + oy, jz = iz + oz;
-                    if (jx < 0 || jx >= n1 || jy < 0 || jy >= n1 || (D == 3 && (jz < 0 || jz >= n1))) continue;
-                    acc += S[int64_t(w) * n + i] * e_src[(int64_t(jz) * n1 + jy) * n1 + jx];
-                }
-    }
-    e_dst[i] = ei + (rhs[i] - acc) / S[int64_t(c0) * n + i];
-}
-
-// rc = P^T (rhs - S e) with P the linear interpolation onto odd fine indices
-template <int D, class T>
-__global__ void k_res_restrict(const T *__restrict__ S, int n1f, const T *__restrict__ e, const T *__restrict__ rhs,
-                               int n1c, T *__restrict__ rc) {
-    const int64_t nc = (D == 3) ? int64_t(n1c) * n1c * n1c : int64_t(n1c) * n1c;
-    const int64_t nf = (D == 3) ? int64_t(n1f) * n1f * n1f : int64_t(n1f) * n1f;
-    const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= nc) return;
-    const int Ix = int(I % n1c), Iy = int((I / n1c) % n1c), Iz = (D == 3) ? int(I / (int64_t(n1c) * n1c)) : 0;
-    T acc = T(0);
-    for (int az = ((D == 3) ? -1 : 0); az <= ((D == 3) ? 1 : 0); ++az) {
-        const int iz = (D == 3) ? 2 * Iz + 1 + az : 0;
-        if (D == 3 && iz >= n1f) continue;
-        const T wz = (D == 3) ? (az == 0 ? T(1) : T(0.5)) : T(1);
-        for (int ay = -1; ay <= 1; ++ay) {
-            const int iy = 2 * Iy + 1 + ay;
-            if (iy >= n1f) continue;
-            const T wy = (ay == 0 ? T(1) : T(0.5)) * wz;
-            for (int ax = -1; ax <= 1; ++ax) {
-                const int ix = 2 * Ix + 1 + ax;
-                if (ix >= n1f) continue;
-                const T wxy = (ax == 0 ? T(1) : T(0.5)) * wy;
-                const int64_t i = (int64_t(iz) * n1f + iy) * n1f + ix;
-                T s = T(0);
-                int w = 0;
-                for (int oz = ((D == 3) ? -1 : 0); oz <= ((D == 3) ? 1 : 0); ++oz)
-                    for (int oy = -1; oy <= 1; ++oy)
-                        for (int ox = -1; ox <= 1; ++ox, ++w) {
-                            const int jx = ix + ox, jy = iy + oy, jz = iz + oz;
-                            if (jx < 0 || jx >= n1f || jy < 0 || jy >= n1f || (D == 3 && (jz < 0 || jz >= n1f)))
-                                continue;
-                            s += S[int64_t(w) * nf + i] * e[(int64_t(jz) * n1f + jy) * n1f + jx];
-                        }
-                acc += wxy * (rhs[i] - s);
-            }
-        }
-    }
-    rc[I] = acc;
-}
-
-// e += P e_c
-template <int D, class T>
-__global__ void k_interp_add(const T *__restrict__ ec, int n1c, T *__restrict__ e, int n1f) {
-    const int64_t nf = (D == 3) ? int64_t(n1f) * n1f * n1f : int64_t(n1f) * n1f;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= nf) return;
-    const int ix = int(i % n1f), iy = int((i / n1f) % n1f), iz = (D == 3) ? int(i / (int64_t(n1f) * n1f)) : 0;
-    int Ix[2], Iy[2], Iz[2];
-    T wx[2], wy[2], wz[2];
-    int nx = 0, ny = 0, nz = 0;
-    auto parents = [n1c](int v, int *I, T *w) {
-        int c = 0;
-        if (v & 1) {
-            I[c] = (v - 1) / 2; w[c++] = T(1);
-        } else {
-            if (v / 2 - 1 >= 0) { I[c] = v / 2 - 1; w[c++] = T(0.5); }
-            if (v / 2 < n1c) { I[c] = v / 2; w[c++] = T(0.5); }
-        }
-        return c;
-    };
-    nx = parents(ix, Ix, wx);
-    ny = parents(iy, Iy, wy);
-    if (D == 3) nz = parents(iz, Iz, wz);
-    else { nz = 1; Iz[0] = 0; wz[0] = T(1); }
-    T acc = T(0);
-    for (int c = 0; c < nz; ++c)
-        for (int b = 0; b < ny; ++b)
-            for (int a = 0; a < nx; ++a)
-                acc += wz[c] * wy[b] * wx[a] * ec[(int64_t(Iz[c]) * n1c + Iy[b]) * n1c + Ix[a]];
-    e[i] += acc;
-}
-
-template <class T>
-__global__ void k_coarsest(const T *__restrict__ rhs, T *__restrict__ e, double diag) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) e[0] = rhs[0] / T(diag);
-}
-
-template <class T>
-__global__ void k_fill_zero(T *__restrict__ x, int64_t n) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = T(0);
-}
-
-template <class T>
-__global__ void k_copy(const T *__restrict__ a, T *__restrict__ b, int64_t n) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = a[i];
-}
-
 // ----------------------------------------------------------------- DST --
 // out[.., k, ..] = sum_i S[k][i] in[.., i, ..] along one axis (S symmetric);
 // with mu != nullptr the result is divided by mu (diagonal solve).
@@ -287,69 +167,6 @@ const T *R1_of(const Problem &P) {
                                           : reinterpret_cast<const T *>(P.R1d32.ptr);
 }
 
-template <class T>
-const T *S_of(const Level &L) {
-    return std::is_same<T, double>::value ? reinterpret_cast<const T *>(L.S64.ptr)
-                                          : reinterpret_cast<const T *>(L.S32.ptr);
-}
-
-template <class T>
-void fill_zero(T *x, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL((k_fill_zero<T>), dim3(nblocks(n, 256)), dim3(256), 0, s, x, n);
-}
-
-// one V(nu1,nu2) cycle from zero on level l; result in e_out
-template <class T>
-void vcycle_level(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, hipStream_t s) {
-    Level &L = P.levels[l];
-    const int64_t n = L.g.n;
-    const int d = P.dim;
-    if (l + 1 == P.levels.size()) {
-        hipLaunchKernelGGL((k_coarsest<T>), dim3(1), dim3(64), 0, s, rhs, e_out, L.coarsest_diag);
-        return;
-    }
-    Level &C = P.levels[l + 1];
-    T *buf[2] = {L.e[0].as<T>(), L.e[1].as<T>()};
-    int cur = 0;
-    bool zero = true;
-    auto half = [&](int colour) {
-        if (d == 2)
-            hipLaunchKernelGGL((k_rb_half<2, T>), dim3(nblocks(n, 256)), dim3(256), 0, s, S_of<T>(L), L.g.n1, colour,
-                               buf[cur], rhs, buf[1 - cur], zero ? 1 : 0);
-        else
-            hipLaunchKernelGGL((k_rb_half<3, T>), dim3(nblocks(n, 256)), dim3(256), 0, s, S_of<T>(L), L.g.n1, colour,
-                               buf[cur], rhs, buf[1 - cur], zero ? 1 : 0);
-        cur = 1 - cur;
-        zero = false;
-    };
-    for (int k = 0; k < nu1; ++k) {
-        half(0);
-        half(1);
-    }
-    if (zero) {
-        fill_zero(buf[cur], n, s);
-        zero = false;
-    }
-    T *rc = C.rhs.as<T>();
-    T *ecl = C.res.as<T>();
-    if (d == 2)
-        hipLaunchKernelGGL((k_res_restrict<2, T>), dim3(nblocks(C.g.n, 256)), dim3(256), 0, s, S_of<T>(L), L.g.n1,
-                           buf[cur], rhs, C.g.n1, rc);
-    else
-        hipLaunchKernelGGL((k_res_restrict<3, T>), dim3(nblocks(C.g.n, 256)), dim3(256), 0, s, S_of<T>(L), L.g.n1,
-                           buf[cur], rhs, C.g.n1, rc);
-    vcycle_level<T>(P, l + 1, rc, ecl, nu1, nu2, s);
-    if (d == 2)
-        hipLaunchKernelGGL((k_interp_add<2, T>), dim3(nblocks(n, 256)), dim3(256), 0, s, ecl, C.g.n1, buf[cur], L.g.n1);
-    else
-        hipLaunchKernelGGL((k_interp_add<3, T>), dim3(nblocks(n, 256)), dim3(256), 0, s, ecl, C.g.n1, buf[cur], L.g.n1);
-    for (int k = 0; k < nu2; ++k) {
-        half(0);
-        half(1);
-    }
-    hipLaunchKernelGGL((k_copy<T>), dim3(nblocks(n, 256)), dim3(256), 0, s, buf[cur], e_out, n);
-}
-
 }  // namespace
 
 // ------------------------------------------------------------ launchers --
@@ -393,14 +210,6 @@ template void launch_prolong_update<double>(const Problem &, const double *, con
                                             hipStream_t);
 template void launch_prolong_update<float>(const Problem &, const float *, const float *, double *, bool,
                                            hipStream_t);
-
-template <class T>
-void launch_vcycle(Problem &P, const T *rhs, T *e, int nu1, int nu2, hipStream_t s) {
-    IGA2L_REQUIRE(P.vcycle_ready, IGA2L_EINVAL, "V-cycle hierarchy not set up");
-    vcycle_level<T>(P, 0, rhs, e, nu1, nu2, s);
-}
-template void launch_vcycle<double>(Problem &, const double *, double *, int, int, hipStream_t);
-template void launch_vcycle<float>(Problem &, const float *, float *, int, int, hipStream_t);
 
 void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s) {
     IGA2L_REQUIRE(P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");

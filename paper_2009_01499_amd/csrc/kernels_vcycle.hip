@@ -1,0 +1,503 @@
+// kernels_vcycle.hip -- the degree-1 h-multigrid V(nu1,nu2) cycle of the
+// coarse level (red-black Gauss-Seidel, linear interpolation onto the
+// odd-indexed nodes, Galerkin operators, exact solve on one node per direction).
+//
+// Fine levels of the hierarchy run one kernel per full red-black step (tiles
+// with a halo of 2: the red half step is recomputed on the tile's halo ring so
+// that the black half step needs no grid-wide barrier) and one tiled
+// residual-restriction kernel; the prolongation is fused into the load of the
+// first post-smoothing step.  All levels whose vectors fit in the LDS of one
+// workgroup run inside a single-workgroup kernel.  A red (black) half step
+// updates every red (black) point from the iterate at the start of the half
+// step.  Levels whose operator is translation invariant (kappa = 1) use the
+// interior stencil as constants instead of loading coefficients.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "internal.h"
+
+namespace iga2l {
+
+namespace {
+
+inline unsigned nblk(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+
+template <int D>
+struct VT;  // tile shapes of the multi-workgroup kernels
+template <>
+struct VT<2> {
+    static constexpr int TX = 32, TY = 8, TZ = 1;   // red-black step tile
+    static constexpr int CX = 16, CY = 16, CZ = 1;  // residual-restriction coarse tile
+};
+template <>
+struct VT<3> {
+    static constexpr int TX = 16, TY = 8, TZ = 4;
+    static constexpr int CX = 8, CY = 8, CZ = 4;
+};
+
+template <int D>
+__device__ __forceinline__ int w_of(int ox, int oy, int oz) {
+    return (D == 3) ? ((oz + 1) * 3 + (oy + 1)) * 3 + (ox + 1) : (oy + 1) * 3 + (ox + 1);
+}
+
+// Stencil coefficient A[i][i+o] of a level.
+template <int D, class T>
+__device__ __forceinline__ T coef(const LevelDev<T> &L, int64_t i, int w) {
+    return L.cst ? L.c[w] : L.S[int64_t(w) * L.n + i];
+}
+template <int D, class T>
+__device__ __forceinline__ T inv_diag(const LevelDev<T> &L, int64_t i) {
+    return L.cst ? L.cinv : L.invd[i];
+}
+
+// parents of a fine index v in 1-D (coarse node I sits at fine index 2I+1)
+template <class T>
+__device__ __forceinline__ int parents(int v, int n1c, int *I, T *w) {
+    int c = 0;
+    if (v & 1) {
+        I[c] = (v - 1) >> 1;
+        w[c++] = T(1);
+    } else {
+        if ((v >> 1) - 1 >= 0) { I[c] = (v >> 1) - 1; w[c++] = T(0.5); }
+        if ((v >> 1) < n1c) { I[c] = v >> 1; w[c++] = T(0.5); }
+    }
+    return c;
+}
+
+// (P ec)[i] for a fine index (ix,iy,iz), ec on the coarse grid n1c
+template <int D, class T>
+__device__ __forceinline__ T interp_value(const T *__restrict__ ec, int n1c, int ix, int iy, int iz) {
+    int Ix[2], Iy[2], Iz[2];
+    T wx[2], wy[2], wz[2];
+    const int nx = parents<T>(ix, n1c, Ix, wx), ny = parents<T>(iy, n1c, Iy, wy);
+    int nz = 1;
+    Iz[0] = 0;
+    wz[0] = T(1);
+    if (D == 3) nz = parents<T>(iz, n1c, Iz, wz);
+    T acc = T(0);
+    for (int c = 0; c < nz; ++c)
+        for (int b = 0; b < ny; ++b)
+            for (int a = 0; a < nx; ++a)
+                acc += wz[c] * wy[b] * wx[a] * ec[(int64_t(Iz[c]) * n1c + Iy[b]) * n1c + Ix[a]];
+    return acc;
+}
+
+// --------------------------------------------------------------------------
+// One full red-black step on a level:  e_dst = S_black S_red (e_in)  with
+// e_in = (zero_src ? 0 : e_src) + (ec ? P ec : 0).
+template <int D, class T>
+__global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restrict__ e_src, int zero_src,
+                                                 const T *__restrict__ ec, int n1c, const T *__restrict__ rhs,
+                                                 T *__restrict__ e_dst) {
+    constexpr int TX = VT<D>::TX, TY = VT<D>::TY, TZ = VT<D>::TZ;
+    constexpr int HX = TX + 4, HY = TY + 4, HZ = (D == 3) ? TZ + 4 : 1;
+    constexpr int NH = HX * HY * HZ;
+    __shared__ T e0[NH];
+    __shared__ T e1[NH];
+    const int n1 = L.n1;
+    const int gx0 = blockIdx.x * TX, gy0 = blockIdx.y * TY, gz0 = (D == 3) ? blockIdx.z * TZ : 0;
+    const int zoff = (D == 3) ? 2 : 0;
+    auto inside = [n1](int x, int y, int z) {
+        return x >= 0 && x < n1 && y >= 0 && y < n1 && (D == 2 || (z >= 0 && z < n1));
+    };
+    // load the step-start iterate over the tile plus a halo of 2
+    for (int h = threadIdx.x; h < NH; h += blockDim.x) {
+        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        const int gx = gx0 + hx - 2, gy = gy0 + hy - 2, gz = gz0 + hz - zoff;
+        T v = T(0);
+        if (inside(gx, gy, gz)) {
+            const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+            if (!zero_src) v = e_src[gi];
+            if (ec) v += interp_value<D, T>(ec, n1c, gx, gy, gz);
+        }
+        e0[h] = v;
+        e1[h] = v;
+    }
+    __syncthreads();
+    // red half step on the tile and its halo ring of width 1
+    for (int h = threadIdx.x; h < NH; h += blockDim.x) {
+        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        if (hx < 1 || hx > HX - 2 || hy < 1 || hy > HY - 2) continue;
+        if (D == 3 && (hz < 1 || hz > HZ - 2)) continue;
+        const int gx = gx0 + hx - 2, gy = gy0 + hy - 2, gz = gz0 + hz - zoff;
+        if (!inside(gx, gy, gz) || ((gx + gy + gz) & 1) != 0) continue;
+        const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+        T acc = T(0);
+        for (int oz = ((D == 3) ? -1 : 0); oz <= ((D == 3) ? 1 : 0); ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox)
+                    acc += coef<D, T>(L, gi, w_of<D>(ox, oy, oz)) * e0[h + (oz * HY + oy) * HX + ox];
+        e1[h] = e0[h] + (rhs[gi] - acc) * inv_diag<D, T>(L, gi);
+    }
+    __syncthreads();
+    // black half step on the tile; write the result
+    const int ntile = TX * TY * ((D == 3) ? TZ : 1);
+    for (int t = threadIdx.x; t < ntile; t += blockDim.x) {
+        const int tx = t % TX, ty = (t / TX) % TY, tz = (D == 3) ? t / (TX * TY) : 0;
+        const int gx = gx0 + tx, gy = gy0 + ty, gz = gz0 + tz;
+        if (!inside(gx, gy, gz)) continue;
+        const int h = ((tz + zoff) * HY + (ty + 2)) * HX + (tx + 2);
+        const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+        T v = e1[h];
+        if ((gx + gy + gz) & 1) {
+            T acc = T(0);
+            for (int oz = ((D == 3) ? -1 : 0); oz <= ((D == 3) ? 1 : 0); ++oz)
+                for (int oy = -1; oy <= 1; ++oy)
+                    for (int ox = -1; ox <= 1; ++ox)
+                        acc += coef<D, T>(L, gi, w_of<D>(ox, oy, oz)) * e1[h + (oz * HY + oy) * HX + ox];
+            v = e1[h] + (rhs[gi] - acc) * inv_diag<D, T>(L, gi);
+        }
+        e_dst[gi] = v;
+    }
+}
+
+// e_dst = e_src + P ec (used only when no post-smoothing step follows)
+template <int D, class T>
+__global__ void k_interp_add2(const T *__restrict__ e_src, int zero_src, const T *__restrict__ ec, int n1c, int n1,
+                              T *__restrict__ e_dst) {
+    const int64_t n = (D == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ix = int(i % n1), iy = int((i / n1) % n1), iz = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
+    e_dst[i] = (zero_src ? T(0) : e_src[i]) + interp_value<D, T>(ec, n1c, ix, iy, iz);
+}
+
+// rc = P^T (rhs - A e) over tiles of coarse points; the fine residuals of the
+// tile's fine region are computed once into LDS.  zero_e: e = 0 (rc = P^T rhs).
+template <int D, class T>
+__global__ void __launch_bounds__(256) k_res_restrict_tiled(LevelDev<T> L, const T *__restrict__ e, int zero_e,
+                                                            const T *__restrict__ rhs, int n1c,
+                                                            T *__restrict__ rc) {
+    constexpr int CX = VT<D>::CX, CY = VT<D>::CY, CZ = VT<D>::CZ;
+    constexpr int FX = 2 * CX + 1, FY = 2 * CY + 1, FZ = (D == 3) ? 2 * CZ + 1 : 1;  // fine region
+    constexpr int EX = FX + 2, EY = FY + 2, EZ = (D == 3) ? FZ + 2 : 1;              // + halo 1
+    __shared__ T es[EX * EY * EZ];
+    __shared__ T rs[FX * FY * FZ];
+    const int n1 = L.n1;
+    const int I0 = blockIdx.x * CX, J0 = blockIdx.y * CY, K0 = (D == 3) ? blockIdx.z * CZ : 0;
+    const int fx0 = 2 * I0, fy0 = 2 * J0, fz0 = 2 * K0;  // fine region origin (fine index of child 2I)
+    const int ez = (D == 3) ? 1 : 0;
+    auto inside = [n1](int x, int y, int z) {
+        return x >= 0 && x < n1 && y >= 0 && y < n1 && (D == 2 || (z >= 0 && z < n1));
+    };
+    if (!zero_e) {
+        for (int h = threadIdx.x; h < EX * EY * EZ; h += blockDim.x) {
+            const int hx = h % EX, hy = (h / EX) % EY, hz = h / (EX * EY);
+            const int gx = fx0 + hx - 1, gy = fy0 + hy - 1, gz = fz0 + hz - ez;
+            es[h] = inside(gx, gy, gz) ? e[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
+        }
+        __syncthreads();
+    }
+    for (int f = threadIdx.x; f < FX * FY * FZ; f += blockDim.x) {
+        const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
+        const int gx = fx0 + fx, gy = fy0 + fy, gz = fz0 + fz;
+        T r = T(0);
+        if (inside(gx, gy, gz)) {
+            const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+            r = rhs[gi];
+            if (!zero_e) {
+                const int h = ((fz + ez) * EY + (fy + 1)) * EX + (fx + 1);
+                T acc = T(0);
+                for (int oz = ((D == 3) ? -1 : 0); oz <= ((D == 3) ? 1 : 0); ++oz)
+                    for (int oy = -1; oy <= 1; ++oy)
+                        for (int ox = -1; ox <= 1; ++ox)
+                            acc += coef<D, T>(L, gi, w_of<D>(ox, oy, oz)) * es[h + (oz * EY + oy) * EX + ox];
+                r -= acc;
+            }
+        }
+        rs[f] = r;
+    }
+    __syncthreads();
+    const int nct = CX * CY * ((D == 3) ? CZ : 1);
+    for (int c = threadIdx.x; c < nct; c += blockDim.x) {
+        const int cx = c % CX, cy = (c / CX) % CY, cz = (D == 3) ? c / (CX * CY) : 0;
+        const int I = I0 + cx, J = J0 + cy, K = K0 + cz;
+        if (I >= n1c || J >= n1c || (D == 3 && K >= n1c)) continue;
+        T acc = T(0);
+        for (int az = ((D == 3) ? -1 : 0); az <= ((D == 3) ? 1 : 0); ++az)
+            for (int ay = -1; ay <= 1; ++ay)
+                for (int ax = -1; ax <= 1; ++ax) {
+                    const T w = (ax == 0 ? T(1) : T(0.5)) * (ay == 0 ? T(1) : T(0.5)) *
+                                ((D == 3 && az != 0) ? T(0.5) : T(1));
+                    const int fx = 2 * cx + 1 + ax, fy = 2 * cy + 1 + ay, fz = (D == 3) ? 2 * cz + 1 + az : 0;
+                    acc += w * rs[(fz * FY + fy) * FX + fx];
+                }
+        rc[(int64_t(K) * n1c + J) * n1c + I] = acc;
+    }
+}
+
+// --------------------------------------------------------------------------
+// The tail of the V-cycle (levels lb .. coarsest) in one workgroup.  Every
+// level's correction and right-hand side live in LDS on a zero-padded grid
+// ((n1+2)^D); the coarsest level has a single node and is solved exactly.
+constexpr int kBottomThreads = 1024;
+constexpr int kBottomMaxPts = 8;  // points per thread and half step
+
+template <int D, class T>
+struct BottomArgs {
+    int nlev;                        // levels handled, lb .. coarsest
+    const LevelDev<T> *levels;       // device array, first entry = level lb
+};
+
+template <int D>
+__device__ __forceinline__ int64_t padded_size(int n1) {
+    return (D == 3) ? int64_t(n1 + 2) * (n1 + 2) * (n1 + 2) : int64_t(n1 + 2) * (n1 + 2);
+}
+
+template <int D, class T>
+__global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, T> A, const T *__restrict__ rhs_top,
+                                                                  T *__restrict__ e_top, int nu1, int nu2) {
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    // LDS: for each level: e (padded), rhs (padded); then one residual scratch (padded, level lb)
+    __shared__ int64_t off_e[16], off_r[16], off_end;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int64_t acc = 0;
+        for (int l = 0; l < A.nlev; ++l) {
+            const int64_t ps = padded_size<D>(A.levels[l].n1);
+            off_e[l] = acc;
+            acc += ps;
+            off_r[l] = acc;
+            acc += ps;
+        }
+        off_end = acc;
+    }
+    __syncthreads();
+    const int64_t o = off_end;
+    T *scr = sm + o;
+    // zero everything (padding must be zero)
+    const int64_t total = o + padded_size<D>(A.levels[0].n1);
+    for (int64_t i = tid; i < total; i += blockDim.x) sm[i] = T(0);
+    __syncthreads();
+    // load the top right-hand side
+    {
+        const int n1 = A.levels[0].n1;
+        const int64_t n = A.levels[0].n;
+        for (int64_t i = tid; i < n; i += blockDim.x) {
+            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
+            sm[off_r[0] + ((D == 3) ? (int64_t(z + 1) * (n1 + 2) + (y + 1)) * (n1 + 2) + (x + 1)
+                                    : int64_t(y + 1) * (n1 + 2) + (x + 1))] = rhs_top[i];
+        }
+    }
+    __syncthreads();
+
+    auto pidx = [](int n1, int x, int y, int z) -> int64_t {
+        return (D == 3) ? (int64_t(z + 1) * (n1 + 2) + (y + 1)) * (n1 + 2) + (x + 1) : int64_t(y + 1) * (n1 + 2) + (x + 1);
+    };
+    // A e at an unpadded point i of level l (e in LDS)
+    auto apply = [&](int l, const T *e, int64_t i, int x, int y, int z) -> T {
+        const LevelDev<T> &L = A.levels[l];
+        const int n1 = L.n1;
+        const int64_t c = pidx(n1, x, y, z);
+        const int64_t sy = n1 + 2, sz = int64_t(n1 + 2) * (n1 + 2);
+        T acc = T(0);
+        for (int oz = ((D == 3) ? -1 : 0); oz <= ((D == 3) ? 1 : 0); ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox)
+                    acc += coef<D, T>(L, i, w_of<D>(ox, oy, oz)) * e[c + oz * sz + oy * sy + ox];
+        return acc;
+    };
+    // one half step of the given colour on level l
+    auto half = [&](int l, int colour) {
+        const LevelDev<T> &L = A.levels[l];
+        const int n1 = L.n1;
+        const int64_t n = L.n;
+        T *e = sm + off_e[l];
+        const T *r = sm + off_r[l];
+        T newv[kBottomMaxPts];
+        int64_t where[kBottomMaxPts];
+        int cnt = 0;
+        for (int64_t i = tid; i < n && cnt < kBottomMaxPts; i += blockDim.x) {
+            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
+            if (((x + y + z) & 1) != colour) continue;
+            const int64_t c = pidx(n1, x, y, z);
+            newv[cnt] = e[c] + (r[c] - apply(l, e, i, x, y, z)) * inv_diag<D, T>(L, i);
+            where[cnt++] = c;
+        }
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) e[where[k]] = newv[k];
+        __syncthreads();
+    };
+
+    const int last = A.nlev - 1;
+    // descend
+    for (int l = 0; l < last; ++l) {
+        for (int k = 0; k < nu1; ++k) {
+            half(l, 0);
+            half(l, 1);
+        }
+        // residual of level l into the scratch, then restriction into rhs of level l+1
+        const LevelDev<T> &L = A.levels[l];
+        const int n1 = L.n1;
+        const T *e = sm + off_e[l];
+        const T *r = sm + off_r[l];
+        for (int64_t i = tid; i < L.n; i += blockDim.x) {
+            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
+            const int64_t c = pidx(n1, x, y, z);
+            scr[c] = r[c] - apply(l, e, i, x, y, z);
+        }
+        __syncthreads();
+        const LevelDev<T> &C = A.levels[l + 1];
+        const int n1c = C.n1;
+        T *rc = sm + off_r[l + 1];
+        T *ecl = sm + off_e[l + 1];
+        for (int64_t I = tid; I < C.n; I += blockDim.x) {
+            const int X = int(I % n1c), Y = int((I / n1c) % n1c), Z = (D == 3) ? int(I / (int64_t(n1c) * n1c)) : 0;
+            T acc = T(0);
+            for (int az = ((D == 3) ? -1 : 0); az <= ((D == 3) ? 1 : 0); ++az)
+                for (int ay = -1; ay <= 1; ++ay)
+                    for (int ax = -1; ax <= 1; ++ax) {
+                        const T w = (ax == 0 ? T(1) : T(0.5)) * (ay == 0 ? T(1) : T(0.5)) *
+                                    ((D == 3 && az != 0) ? T(0.5) : T(1));
+                        const int fx = 2 * X + 1 + ax, fy = 2 * Y + 1 + ay, fz = (D == 3) ? 2 * Z + 1 + az : 0;
+                        // the scratch is shared by all levels: never read outside level l's points
+                        if (fx >= n1 || fy >= n1 || (D == 3 && fz >= n1)) continue;
+                        acc += w * scr[pidx(n1, fx, fy, fz)];
+                    }
+            rc[pidx(n1c, X, Y, Z)] = acc;
+            ecl[pidx(n1c, X, Y, Z)] = T(0);
+        }
+        __syncthreads();
+    }
+    // coarsest level: one node per direction
+    if (tid == 0) {
+        const LevelDev<T> &Z = A.levels[last];
+        const int64_t c = pidx(Z.n1, 0, 0, 0);
+        sm[off_e[last] + c] = sm[off_r[last] + c] * inv_diag<D, T>(Z, 0);
+    }
+    __syncthreads();
+    // ascend
+    for (int l = last - 1; l >= 0; --l) {
+        const LevelDev<T> &L = A.levels[l];
+        const LevelDev<T> &C = A.levels[l + 1];
+        const int n1 = L.n1, n1c = C.n1;
+        T *e = sm + off_e[l];
+        const T *ecl = sm + off_e[l + 1];
+        for (int64_t i = tid; i < L.n; i += blockDim.x) {
+            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
+            int Ix[2], Iy[2], Iz[2];
+            T wx[2], wy[2], wz[2];
+            const int nx = parents<T>(x, n1c, Ix, wx), ny = parents<T>(y, n1c, Iy, wy);
+            int nz = 1;
+            Iz[0] = 0;
+            wz[0] = T(1);
+            if (D == 3) nz = parents<T>(z, n1c, Iz, wz);
+            T acc = T(0);
+            for (int cc = 0; cc < nz; ++cc)
+                for (int bb = 0; bb < ny; ++bb)
+                    for (int aa = 0; aa < nx; ++aa) acc += wz[cc] * wy[bb] * wx[aa] * ecl[pidx(n1c, Ix[aa], Iy[bb], Iz[cc])];
+            e[pidx(n1, x, y, z)] += acc;
+        }
+        __syncthreads();
+        for (int k = 0; k < nu2; ++k) {
+            half(l, 0);
+            half(l, 1);
+        }
+    }
+    // write the result of level lb
+    {
+        const int n1 = A.levels[0].n1;
+        for (int64_t i = tid; i < A.levels[0].n; i += blockDim.x) {
+            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
+            e_top[i] = sm[off_e[0] + pidx(n1, x, y, z)];
+        }
+    }
+}
+
+template <class T>
+size_t bottom_level(const Problem &P) {
+    return std::is_same<T, double>::value ? P.vc_bottom64 : P.vc_bottom32;
+}
+
+template <class T>
+const LevelDev<T> *levdev(const Problem &P) {
+    return std::is_same<T, double>::value ? reinterpret_cast<const LevelDev<T> *>(P.levdev64.ptr)
+                                          : reinterpret_cast<const LevelDev<T> *>(P.levdev32.ptr);
+}
+
+template <class T>
+LevelDev<T> levhost(const Problem &P, size_t l) {
+    if constexpr (std::is_same<T, double>::value) return P.levhost64[l];
+    else return P.levhost32[l];
+}
+
+// V-cycle from zero on level l of the multi-workgroup part; result in e_out
+template <int D, class T>
+void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, hipStream_t s) {
+    const size_t lb = bottom_level<T>(P);
+    if (l == lb) {
+        const size_t nlev = P.levels.size() - lb;
+        BottomArgs<D, T> a{int(nlev), levdev<T>(P) + lb};
+        const size_t shm = size_t(vcycle_bottom_lds(P, lb)) * sizeof(T);
+        hipLaunchKernelGGL((k_vcycle_bottom<D, T>), dim3(1), dim3(kBottomThreads), shm, s, a, rhs, e_out, nu1, nu2);
+        return;
+    }
+    Level &L = P.levels[l];
+    Level &C = P.levels[l + 1];
+    const LevelDev<T> Ld = levhost<T>(P, l);
+    const int n1 = L.g.n1, n1c = C.g.n1;
+    using TS = VT<D>;
+    const dim3 sgrid(nblk(n1, TS::TX), nblk(n1, TS::TY), D == 3 ? nblk(n1, TS::TZ) : 1);
+    const dim3 rgrid(nblk(n1c, TS::CX), nblk(n1c, TS::CY), D == 3 ? nblk(n1c, TS::CZ) : 1);
+    T *buf[2] = {L.e[0].as<T>(), L.e[1].as<T>()};
+    int cur = 0;
+    bool zero = true;
+    for (int k = 0; k < nu1; ++k) {
+        hipLaunchKernelGGL((k_rb_step<D, T>), sgrid, dim3(256), 0, s, Ld, buf[cur], zero ? 1 : 0,
+                           static_cast<const T *>(nullptr), 0, rhs, buf[1 - cur]);
+        cur = 1 - cur;
+        zero = false;
+    }
+    T *rc = C.rhs.as<T>();
+    T *ecl = C.res.as<T>();
+    hipLaunchKernelGGL((k_res_restrict_tiled<D, T>), rgrid, dim3(256), 0, s, Ld, buf[cur], zero ? 1 : 0, rhs, n1c, rc);
+    vcycle_top<D, T>(P, l + 1, rc, ecl, nu1, nu2, s);
+    // post-smoothing; the first step loads e + P ec, the last one writes e_out
+    if (nu2 == 0) {
+        hipLaunchKernelGGL((k_interp_add2<D, T>), dim3(nblk(L.g.n, 256)), dim3(256), 0, s, buf[cur], zero ? 1 : 0,
+                           static_cast<const T *>(ecl), n1c, n1, e_out);
+        return;
+    }
+    for (int k = 0; k < nu2; ++k) {
+        T *dst = (k == nu2 - 1) ? e_out : buf[1 - cur];
+        hipLaunchKernelGGL((k_rb_step<D, T>), sgrid, dim3(256), 0, s, Ld, buf[cur], zero ? 1 : 0,
+                           (k == 0) ? static_cast<const T *>(ecl) : static_cast<const T *>(nullptr), n1c, rhs, dst);
+        cur = 1 - cur;
+        zero = false;
+    }
+}
+
+}  // namespace
+
+template <class T>
+void launch_vcycle(Problem &P, const T *rhs, T *e, int nu1, int nu2, hipStream_t s) {
+    IGA2L_REQUIRE(P.vcycle_ready, IGA2L_EINVAL, "V-cycle hierarchy not set up");
+    if (P.dim == 2) vcycle_top<2, T>(P, 0, rhs, e, nu1, nu2, s);
+    else vcycle_top<3, T>(P, 0, rhs, e, nu1, nu2, s);
+}
+template void launch_vcycle<double>(Problem &, const double *, double *, int, int, hipStream_t);
+template void launch_vcycle<float>(Problem &, const float *, float *, int, int, hipStream_t);
+
+// LDS (in elements) the bottom kernel needs for levels lb..coarsest
+int64_t vcycle_bottom_lds(const Problem &P, size_t lb) {
+    auto ps = [&](int n1) {
+        int64_t r = 1;
+        for (int k = 0; k < P.dim; ++k) r *= (n1 + 2);
+        return r;
+    };
+    int64_t tot = 0;
+    for (size_t l = lb; l < P.levels.size(); ++l) tot += 2 * ps(P.levels[l].g.n1);
+    return tot + ps(P.levels[lb].g.n1);
+}
+
+// points per thread of one half step in the bottom kernel
+bool vcycle_bottom_fits(const Problem &P, size_t lb) {
+    const int64_t n = P.levels[lb].g.n;
+    return (n + kBottomThreads - 1) / kBottomThreads <= kBottomMaxPts && P.levels.size() - lb <= 16;
+}
+
+}  // namespace iga2l

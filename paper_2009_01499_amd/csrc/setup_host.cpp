@@ -390,22 +390,95 @@ void host_build_levels(Problem &P) {
     }
     P.levels.clear();
     P.levels.resize(ops.size());
+    P.levhost64.assign(ops.size(), LevelDev<double>{});
+    P.levhost32.assign(ops.size(), LevelDev<float>{});
+    const int cw = (W3 - 1) / 2;
     for (size_t l = 0; l < ops.size(); ++l) {
         Level &L = P.levels[l];
         L.g = Grid{d, sizes[l], ipow(sizes[l], d)};
         const auto &S = ops[l];
+        const int64_t n = L.g.n;
+        const int n1 = L.g.n1;
         L.S64.alloc(S.size() * sizeof(double));
         IGA2L_HIP(hipMemcpy(L.S64.ptr, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
         std::vector<float> s32(S.begin(), S.end());
         L.S32.alloc(s32.size() * sizeof(float));
         IGA2L_HIP(hipMemcpy(L.S32.ptr, s32.data(), s32.size() * sizeof(float), hipMemcpyHostToDevice));
-        const size_t nb = size_t(L.g.n) * sizeof(double);
+        std::vector<double> inv(n);
+        std::vector<float> inv32(n);
+        for (int64_t i = 0; i < n; ++i) {
+            inv[i] = 1.0 / S[size_t(cw) * n + i];
+            inv32[i] = 1.0f / float(S[size_t(cw) * n + i]);
+        }
+        L.invd64.alloc(n * sizeof(double));
+        L.invd32.alloc(n * sizeof(float));
+        IGA2L_HIP(hipMemcpy(L.invd64.ptr, inv.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        IGA2L_HIP(hipMemcpy(L.invd32.ptr, inv32.data(), n * sizeof(float), hipMemcpyHostToDevice));
+        // translation invariance: every row carries the centre row's coefficients
+        // on all of its in-grid neighbours (rows are truncated at the boundary)
+        L.cst = false;
+        double ref[27] = {0};
+        if (n1 >= 3) {
+            int64_t ic = 0;
+            for (int k = d - 1; k >= 0; --k) ic = ic * n1 + n1 / 2;
+            double scale = 0.0;
+            for (int w = 0; w < W3; ++w) {
+                ref[w] = S[size_t(w) * n + ic];
+                scale = std::max(scale, std::fabs(ref[w]));
+            }
+            bool same = true;
+            int ix[kMaxDim] = {0, 0, 0}, o[kMaxDim] = {0, 0, 0};
+            for (int64_t i = 0; i < n && same; ++i) {
+                split(i, d, n1, ix);
+                for (int w = 0; w < W3 && same; ++w) {
+                    split(w, d, 3, o);
+                    bool in = true;
+                    for (int k = 0; k < d; ++k) {
+                        int j = ix[k] + o[k] - 1;
+                        if (j < 0 || j >= n1) in = false;
+                    }
+                    if (in && std::fabs(S[size_t(w) * n + i] - ref[w]) > 1e-14 * scale) same = false;
+                }
+            }
+            L.cst = same;
+        }
+        const size_t nb = size_t(n) * sizeof(double);
         L.e[0].alloc(nb);
         L.e[1].alloc(nb);
         L.rhs.alloc(nb);
         L.res.alloc(nb);
-        if (L.g.n == 1) L.coarsest_diag = S[(W3 - 1) / 2];
+        LevelDev<double> &h64 = P.levhost64[l];
+        LevelDev<float> &h32 = P.levhost32[l];
+        h64.n1 = h32.n1 = n1;
+        h64.n = h32.n = n;
+        h64.cst = h32.cst = L.cst ? 1 : 0;
+        h64.S = L.S64.as<double>();
+        h32.S = L.S32.as<float>();
+        h64.invd = L.invd64.as<double>();
+        h32.invd = L.invd32.as<float>();
+        for (int w = 0; w < 27; ++w) {
+            h64.c[w] = (w < W3) ? ref[w] : 0.0;
+            h32.c[w] = float(h64.c[w]);
+        }
+        h64.cinv = L.cst ? 1.0 / ref[cw] : 0.0;
+        h32.cinv = L.cst ? 1.0f / float(ref[cw]) : 0.0f;
     }
+    P.levdev64.alloc(P.levhost64.size() * sizeof(LevelDev<double>));
+    P.levdev32.alloc(P.levhost32.size() * sizeof(LevelDev<float>));
+    IGA2L_HIP(hipMemcpy(P.levdev64.ptr, P.levhost64.data(), P.levhost64.size() * sizeof(LevelDev<double>),
+                        hipMemcpyHostToDevice));
+    IGA2L_HIP(hipMemcpy(P.levdev32.ptr, P.levhost32.data(), P.levhost32.size() * sizeof(LevelDev<float>),
+                        hipMemcpyHostToDevice));
+    // the one-workgroup tail starts at the first level whose whole tail fits in
+    // 64 KiB of LDS (and whose half steps need at most the per-thread budget)
+    const int64_t lds_budget = 64 * 1024;
+    auto pick = [&](size_t elem) {
+        for (size_t lb = 0; lb < P.levels.size(); ++lb)
+            if (vcycle_bottom_fits(P, lb) && vcycle_bottom_lds(P, lb) * int64_t(elem) <= lds_budget) return lb;
+        return P.levels.size() - 1;
+    };
+    P.vc_bottom64 = pick(sizeof(double));
+    P.vc_bottom32 = pick(sizeof(float));
     P.vcycle_ready = true;
 }
 
