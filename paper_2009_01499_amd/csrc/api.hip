@@ -3,6 +3,7 @@
 // residual, a correction cycle in working precision from zero, FP64 update).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -114,14 +115,14 @@ void coarse_solve(Problem &P, const iga2l_opts &o, const T *dc, T *ec, hipStream
     if constexpr (std::is_same<T, double>::value) {
         launch_dst_solve(P, dc, ec, s);
     } else {
-        launch_convert(dc, P.dc64.ptr, P.coarse.n, false, s);
+        launch_convert(dc, P.dc64.ptr, P.coarse.n, false, s, P.skip);
         launch_dst_solve(P, P.dc64.as<double>(), P.ec64.as<double>(), s);
-        launch_convert(P.ec64.ptr, ec, P.coarse.n, true, s);
+        launch_convert(P.ec64.ptr, ec, P.coarse.n, true, s, P.skip);
     }
 }
 
-// One correction cycle: expects r64 = b - A u and the scalars of
-// launch_norm_finalize; performs u += sigma * cycle(0; r64 / sigma).
+// One correction cycle: expects r64 = b - A u and the scalars written by the
+// norm-carrying residual; performs u += sigma * cycle(0; r64 / sigma).
 template <class T>
 void correction_cycle(Problem &P, const iga2l_opts &o, double *u, hipStream_t s) {
     const T *rhs;
@@ -137,7 +138,7 @@ void correction_cycle(Problem &P, const iga2l_opts &o, double *u, hipStream_t s)
         cur = sweep_colour<T>(P, S, rhs, 0, true, s);
     } else {
         // lexicographic: FP64 only, in place on a zeroed correction
-        IGA2L_HIP(hipMemsetAsync(P.ework[0].ptr, 0, sizeof(double) * size_t(P.fine.n), s));
+        launch_fill_zero(P.ework[0].ptr, P.fine.n, false, s, P.skip);
         for (size_t st = 0; st + 1 < P.lex_off.size(); ++st)
             launch_lex_step(P, int(st), P.ework[0].as<double>(), P.r64.as<double>(), s);
         cur = 0;
@@ -162,19 +163,35 @@ void correction_cycle(Problem &P, const iga2l_opts &o, double *u, hipStream_t s)
         }
     }
     // u += sigma * e: prolongation of a zero coarse vector adds nothing
-    IGA2L_HIP(hipMemsetAsync(P.ctmp.ptr, 0, sizeof(double) * size_t(P.coarse.n), s));
+    launch_fill_zero(P.ctmp.ptr, P.coarse.n, !std::is_same<T, double>::value, s, P.skip);
     launch_prolong_update<T>(P, P.ctmp.as<T>(), P.ework[cur].as<T>(), u, scaled, s);
 }
 
-double residual_norm(Problem &P, const double *u, const double *b, bool fp32, hipStream_t s) {
-    launch_residual64(P, u, b, P.r64.as<double>(), true, s);
-    launch_norm_finalize(P, fp32, s);
-    double nrm = 0.0;
-    IGA2L_HIP(hipMemcpyAsync(&nrm, P.scal.as<double>() + kScalNorm, sizeof(double), hipMemcpyDeviceToHost, s));
-    IGA2L_HIP(hipStreamSynchronize(s));
-    return nrm;
+// Keeps P.skip pointing at the device stop flag while a solve enqueues work.
+struct SkipGuard {
+    Problem &P;
+    SkipGuard(Problem &p, const int *f) : P(p) { P.skip = f; }
+    ~SkipGuard() { P.skip = nullptr; }
+};
+
+void ensure_history(Problem &P, int cap) {
+    if (cap <= P.hist_cap) return;
+    DevBuf nb;
+    nb.alloc(status_bytes(cap));
+    IGA2L_HIP(hipMemset(nb.ptr, 0, status_bytes(cap)));
+    IGA2L_HIP(hipMemcpy(nb.ptr, P.scal.ptr, sizeof(double) * kScalCount, hipMemcpyDeviceToDevice));
+    P.scal = std::move(nb);
+    if (P.host_status) IGA2L_HIP(hipHostFree(P.host_status));
+    P.host_status = nullptr;
+    IGA2L_HIP(hipHostMalloc(&P.host_status, status_bytes(cap), hipHostMallocDefault));
+    P.hist_cap = cap;
 }
 
+// Solve loop.  The convergence test runs on the device (the norm-carrying
+// residual after each cycle records the history and raises a stop flag that
+// every kernel of later cycles obeys), so the host enqueues cycles in batches
+// and synchronises once per batch; the first batch has the length of the
+// previous solve.  Results are those of stopping exactly at the tolerance.
 void solve_impl(Problem &P, const double *b, double *u, const iga2l_opts &o, iga2l_info *info, hipStream_t s) {
     IGA2L_REQUIRE(P.blocks_ready, IGA2L_EINVAL, "iga2l_setup_blocks must run before iga2l_solve");
     IGA2L_REQUIRE(b && u, IGA2L_EINVAL, "null vector");
@@ -182,31 +199,47 @@ void solve_impl(Problem &P, const double *b, double *u, const iga2l_opts &o, iga
     IGA2L_REQUIRE(!fp32 || P.fp32_ready, IGA2L_EINVAL, "FP32 data not set up (setup_blocks with MIXED_FP32)");
     IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_VCYCLE || P.vcycle_ready, IGA2L_EINVAL, "V-cycle not set up");
     IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_DIRECT || P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");
+    ensure_history(P, std::max(o.max_cycles, 1));
     auto t0 = std::chrono::steady_clock::now();
-    double r0 = residual_norm(P, u, b, fp32, s);
-    IGA2L_REQUIRE(std::isfinite(r0), IGA2L_ENUMERIC, "initial residual is not finite");
-    double rk = r0;
-    int k = 0;
-    int status = IGA2L_OK;
-    while (rk > o.tol * r0 && k < o.max_cycles) {
-        if (fp32) correction_cycle<float>(P, o, u, s);
-        else correction_cycle<double>(P, o, u, s);
-        ++k;
-        rk = residual_norm(P, u, b, fp32, s);
-        if (info && info->relres_history && k <= info->history_cap) info->relres_history[k - 1] = r0 > 0 ? rk / r0 : 0.0;
-        if (!std::isfinite(rk) || (r0 > 0 && rk > 1e3 * r0)) {
-            status = IGA2L_ENUMERIC;
-            break;
+    launch_residual64(P, u, b, P.r64.as<double>(), true, fp32, false, s);
+    launch_solve_init(P, o.tol, o.max_cycles, s);
+    int issued = 0;
+    int batch = std::max(1, std::min(P.expected_cycles, o.max_cycles));
+    const double *hs = static_cast<const double *>(P.host_status);
+    const int *hf = reinterpret_cast<const int *>(hs + kScalCount);
+    {
+        SkipGuard guard(P, dev_flags(P));
+        while (true) {
+            for (int j = 0; j < batch && issued < o.max_cycles; ++j, ++issued) {
+                if (fp32) correction_cycle<float>(P, o, u, s);
+                else correction_cycle<double>(P, o, u, s);
+                launch_residual64(P, u, b, P.r64.as<double>(), true, fp32, true, s);
+            }
+            IGA2L_HIP(hipGetLastError());
+            IGA2L_HIP(hipMemcpyAsync(P.host_status, P.scal.ptr, status_bytes(std::min(issued, P.hist_cap)),
+                                     hipMemcpyDeviceToHost, s));
+            IGA2L_HIP(hipStreamSynchronize(s));
+            if (hf[kFlagDone] || issued >= o.max_cycles) break;
+            batch = 1;
         }
     }
-    if (status == IGA2L_OK && rk > o.tol * r0) status = IGA2L_ENOTCONV;
+    const int k = hf[kFlagIter];
+    const double r0 = hs[kScalR0];
+    const double rel = (k > 0) ? hs[kScalCount + kFlagCount / 2 + k - 1] : (r0 > 0 ? 1.0 : 0.0);
+    int status = IGA2L_OK;
+    if (hf[kFlagStatus] == 2) status = IGA2L_ENUMERIC;
+    else if (hf[kFlagStatus] == 1 || (!hf[kFlagDone] && rel > o.tol)) status = IGA2L_ENOTCONV;
+    if (k > 0) P.expected_cycles = k;
     auto t1 = std::chrono::steady_clock::now();
     if (info) {
         info->iters = k;
         info->status = status;
         info->r0 = r0;
-        info->relres = r0 > 0 ? rk / r0 : 0.0;
+        info->relres = rel;
         info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        if (info->relres_history)
+            for (int i = 0; i < std::min(k, info->history_cap); ++i)
+                info->relres_history[i] = hs[kScalCount + kFlagCount / 2 + i];
     }
     if (status == IGA2L_ENUMERIC) throw Error{IGA2L_ENUMERIC, "residual diverged or became non-finite"};
     if (status == IGA2L_ENOTCONV) throw Error{IGA2L_ENOTCONV, "max_cycles reached before the tolerance"};
@@ -352,7 +385,7 @@ int iga2l_residual(const iga2l_problem *prob, const double *u, const double *b, 
         IGA2L_REQUIRE(prob && u && b && r, IGA2L_EINVAL, "null argument");
         IGA2L_REQUIRE(r != u, IGA2L_EINVAL, "r may not alias u");
         set_device(prob->P);
-        launch_residual64(prob->P, u, b, r, false, static_cast<hipStream_t>(stream));
+        launch_residual64(prob->P, u, b, r, false, false, false, static_cast<hipStream_t>(stream));
         IGA2L_HIP(hipGetLastError());
     });
 }

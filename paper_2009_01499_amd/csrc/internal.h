@@ -154,16 +154,33 @@ struct Problem {
     DevBuf dc, ec, ctmp;          // coarse vectors (FP64-sized)
     DevBuf dc64, ec64;            // FP64 coarse vectors of the exact solve in mixed mode
     DevBuf partial;               // per-workgroup partial sums (FP64)
-    DevBuf scal;                  // device scalars (see kScal*)
+    int hist_cap = 0;             // cycles of history held after the flags in scal
+    const int *skip = nullptr;    // while a solve runs: flags (kernels return at once when set)
+    void *host_status = nullptr;  // pinned host copy of flags + hist
+    int expected_cycles = 8;      // cycles of the last solve: size of the first batch
+    DevBuf cs64, cs32;            // interior stencil of kappa = 1 rows, (2p+1)^d (empty otherwise)
+    int ulo = 1, uhi = 0;         // rows with all coordinates in [ulo, uhi] carry that stencil
+    DevBuf scal;                  // status block: kScalCount doubles, kFlagCount ints, hist_cap doubles
     DevBuf lam_tmp;               // adjoint workspace
     int npartial = 0;
+
+    ~Problem() {
+        if (host_status) (void)hipHostFree(host_status);
+    }
 
     // tuning knobs (numerics-neutral)
     int tile_bx = 4, tile_by = 4, tile_bz = 1;   // Schwarz tile in blocks
 };
 
 // device scalar slots in Problem::scal (doubles)
-enum { kScalNorm = 0, kScalSigma = 1, kScalInvSigma = 2, kScalCount = 8 };
+enum { kScalNorm = 0, kScalSigma = 1, kScalInvSigma = 2, kScalR0 = 3, kScalTol = 4, kScalMaxCycles = 5, kScalCount = 8 };
+// device int slots in Problem::flags: stop flag, cycles done, status (0 running/converged, 1 max cycles, 2 numeric)
+enum { kFlagDone = 0, kFlagIter = 1, kFlagStatus = 2, kFlagCount = 4 };
+
+// views into the status block
+inline int *dev_flags(const Problem &P) { return reinterpret_cast<int *>(P.scal.as<double>() + kScalCount); }
+inline double *dev_hist(const Problem &P) { return P.scal.as<double>() + kScalCount + kFlagCount / 2; }
+inline size_t status_bytes(int hist_cap) { return sizeof(double) * (kScalCount + kFlagCount / 2 + hist_cap); }
 
 // ------------------------------------------------------------ host set-up --
 void host_assemble(Problem &P);                 // 1-D factors, DIA, transfers, kappa
@@ -175,11 +192,13 @@ void host_lex_schedule(Problem &P);
 // ------------------------------------------------------------ launchers --
 // fine level
 void launch_block_inverse(Problem &P, const std::vector<int64_t> &reps, hipStream_t s);
-void launch_residual64(const Problem &P, const double *u, const double *b, double *r, bool partial_norm,
-                       hipStream_t s);
+// r = b - A u in FP64; with_norm: also ||r||_2 and the FP32 scaling into P.scal;
+// book: also the device-side convergence test after a cycle (P.flags, P.hist)
+void launch_residual64(const Problem &P, const double *u, const double *b, double *r, bool with_norm,
+                       bool scale_fp32, bool book, hipStream_t s);
 template <class T>
 void launch_defect(const Problem &P, const T *e, const T *rhs, T *d, hipStream_t s);
-void launch_norm_finalize(const Problem &P, bool scale_fp32, hipStream_t s);
+void launch_solve_init(const Problem &P, double tol, int max_cycles, hipStream_t s);
 int64_t residual_workgroups(const Problem &P);   // partial sums written by the FP64 residual
 template <class T>
 void launch_colour_step(const Problem &P, int cx, int cy, int cz, int s_period, const T *x_src, T *x_dst,
@@ -200,7 +219,8 @@ void launch_vcycle(Problem &P, const T *rhs, T *e, int nu1, int nu2, hipStream_t
 void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s);
 int64_t vcycle_bottom_lds(const Problem &P, size_t lb);   // LDS elements of the one-workgroup tail
 bool vcycle_bottom_fits(const Problem &P, size_t lb);
-void launch_convert(const void *src, void *dst, int64_t n, bool to_fp32, hipStream_t s);
+void launch_convert(const void *src, void *dst, int64_t n, bool to_fp32, hipStream_t s, const int *skip = nullptr);
+void launch_fill_zero(void *x, int64_t n_elems, bool fp32, hipStream_t s, const int *skip);
 // gradient
 void launch_grad_kappa(const Problem &P, const double *u, const double *lam, double *g, hipStream_t s);
 

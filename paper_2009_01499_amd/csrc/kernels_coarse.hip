@@ -20,7 +20,8 @@ inline unsigned nblocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 // d_c[I] = sum_a R1[Ix][ax] R1[Iy][ay] (R1[Iz][az]) d[I - 1 + a], a in [0,p+1]^D
 template <int D, class T>
 __global__ void k_restrict(const T *__restrict__ R1, int p, int n1f, int n1c, const T *__restrict__ df,
-                           T *__restrict__ dc) {
+                           T *__restrict__ dc, const int *__restrict__ skip) {
+    const int stop = skip ? *skip : 0;  // tested before the store (hides the load latency)
     const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nc = (D == 3) ? int64_t(n1c) * n1c * n1c : int64_t(n1c) * n1c;
     if (I >= nc) return;
@@ -44,6 +45,7 @@ __global__ void k_restrict(const T *__restrict__ R1, int p, int n1f, int n1c, co
             acc += ry * line;
         }
     }
+    if (stop) return;
     dc[I] = acc;
 }
 
@@ -73,7 +75,8 @@ __device__ __forceinline__ T prolong_value(const T *__restrict__ R1, int p, int 
 
 template <int D, class T>
 __global__ void k_prolong_add(const T *__restrict__ R1, int p, int n1f, int n1c, const T *__restrict__ ec,
-                              T *__restrict__ uf) {
+                              T *__restrict__ uf, const int *__restrict__ skip) {
+    if (skip && *skip) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nf = (D == 3) ? int64_t(n1f) * n1f * n1f : int64_t(n1f) * n1f;
     if (i >= nf) return;
@@ -85,12 +88,14 @@ __global__ void k_prolong_add(const T *__restrict__ R1, int p, int n1f, int n1c,
 template <int D, class T>
 __global__ void k_prolong_update(const T *__restrict__ R1, int p, int n1f, int n1c, const T *__restrict__ ec,
                                  const T *__restrict__ e, double *__restrict__ u, const double *__restrict__ scal,
-                                 int scaled) {
+                                 int scaled, const int *__restrict__ skip) {
+    const int stop = skip ? *skip : 0;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nf = (D == 3) ? int64_t(n1f) * n1f * n1f : int64_t(n1f) * n1f;
     if (i >= nf) return;
     const int ix = int(i % n1f), iy = int((i / n1f) % n1f), iz = (D == 3) ? int(i / (int64_t(n1f) * n1f)) : 0;
     const T corr = e[i] + prolong_value<D, T>(R1, p, n1f, n1c, ec, ix, iy, iz);
+    if (stop) return;
     u[i] += scaled ? scal[kScalSigma] * double(corr) : double(corr);
 }
 
@@ -98,7 +103,8 @@ __global__ void k_prolong_update(const T *__restrict__ R1, int p, int n1f, int n
 // out[.., k, ..] = sum_i S[k][i] in[.., i, ..] along one axis (S symmetric);
 // with mu != nullptr the result is divided by mu (diagonal solve).
 __global__ void k_dst_axis(const double *__restrict__ S, int n1, int dim, int axis, const double *__restrict__ in,
-                           double *__restrict__ out, const double *__restrict__ mu) {
+                           double *__restrict__ out, const double *__restrict__ mu, const int *__restrict__ skip) {
+    if (skip && *skip) return;
     const int64_t n = (dim == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= n) return;
@@ -112,8 +118,16 @@ __global__ void k_dst_axis(const double *__restrict__ S, int n1, int dim, int ax
     out[idx] = mu ? acc / mu[idx] : acc;
 }
 
+template <class T>
+__global__ void k_fill(T *__restrict__ x, int64_t n, const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = T(0);
+}
+
 template <class A, class B>
-__global__ void k_convert(const A *__restrict__ a, B *__restrict__ b, int64_t n) {
+__global__ void k_convert(const A *__restrict__ a, B *__restrict__ b, int64_t n, const int *__restrict__ skip) {
+    if (skip && *skip) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) b[i] = B(a[i]);
 }
@@ -175,10 +189,10 @@ void launch_restrict(const Problem &P, const T *df, T *dc, hipStream_t s) {
     const int64_t nc = P.coarse.n;
     if (P.dim == 2)
         hipLaunchKernelGGL((k_restrict<2, T>), dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
-                           P.coarse.n1, df, dc);
+                           P.coarse.n1, df, dc, P.skip);
     else
         hipLaunchKernelGGL((k_restrict<3, T>), dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
-                           P.coarse.n1, df, dc);
+                           P.coarse.n1, df, dc, P.skip);
 }
 template void launch_restrict<double>(const Problem &, const double *, double *, hipStream_t);
 template void launch_restrict<float>(const Problem &, const float *, float *, hipStream_t);
@@ -188,10 +202,10 @@ void launch_prolong_add(const Problem &P, const T *ec, T *uf, hipStream_t s) {
     const int64_t nf = P.fine.n;
     if (P.dim == 2)
         hipLaunchKernelGGL((k_prolong_add<2, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
-                           P.coarse.n1, ec, uf);
+                           P.coarse.n1, ec, uf, P.skip);
     else
         hipLaunchKernelGGL((k_prolong_add<3, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
-                           P.coarse.n1, ec, uf);
+                           P.coarse.n1, ec, uf, P.skip);
 }
 template void launch_prolong_add<double>(const Problem &, const double *, double *, hipStream_t);
 template void launch_prolong_add<float>(const Problem &, const float *, float *, hipStream_t);
@@ -201,10 +215,10 @@ void launch_prolong_update(const Problem &P, const T *ec, const T *e, double *u,
     const int64_t nf = P.fine.n;
     if (P.dim == 2)
         hipLaunchKernelGGL((k_prolong_update<2, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p,
-                           P.fine.n1, P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0);
+                           P.fine.n1, P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0, P.skip);
     else
         hipLaunchKernelGGL((k_prolong_update<3, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p,
-                           P.fine.n1, P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0);
+                           P.fine.n1, P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0, P.skip);
 }
 template void launch_prolong_update<double>(const Problem &, const double *, const double *, double *, bool,
                                             hipStream_t);
@@ -223,26 +237,35 @@ void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s) {
     int cur = 0;
     for (int ax = 0; ax < dim; ++ax) {
         hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, S, n1, dim, ax, src, bufs[cur],
-                           (ax == dim - 1) ? mu : nullptr);
+                           (ax == dim - 1) ? mu : nullptr, P.skip);
         src = bufs[cur];
         cur = 1 - cur;
     }
     for (int ax = 0; ax < dim; ++ax) {
         hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, S, n1, dim, ax, src, bufs[cur],
-                           nullptr);
+                           nullptr, P.skip);
         src = bufs[cur];
         cur = 1 - cur;
     }
     // 2*dim passes alternate t1, e, t1, e, ...: an even count, so the last one wrote e
 }
 
-void launch_convert(const void *src, void *dst, int64_t n, bool to_fp32, hipStream_t s) {
+void launch_convert(const void *src, void *dst, int64_t n, bool to_fp32, hipStream_t s, const int *skip) {
     if (to_fp32)
         hipLaunchKernelGGL((k_convert<double, float>), dim3(nblocks(n, 256)), dim3(256), 0, s,
-                           static_cast<const double *>(src), static_cast<float *>(dst), n);
+                           static_cast<const double *>(src), static_cast<float *>(dst), n, skip);
     else
         hipLaunchKernelGGL((k_convert<float, double>), dim3(nblocks(n, 256)), dim3(256), 0, s,
-                           static_cast<const float *>(src), static_cast<double *>(dst), n);
+                           static_cast<const float *>(src), static_cast<double *>(dst), n, skip);
+}
+
+void launch_fill_zero(void *x, int64_t n_elems, bool fp32, hipStream_t s, const int *skip) {
+    if (fp32)
+        hipLaunchKernelGGL((k_fill<float>), dim3(nblocks(n_elems, 256)), dim3(256), 0, s, static_cast<float *>(x),
+                           n_elems, skip);
+    else
+        hipLaunchKernelGGL((k_fill<double>), dim3(nblocks(n_elems, 256)), dim3(256), 0, s, static_cast<double *>(x),
+                           n_elems, skip);
 }
 
 void launch_grad_kappa(const Problem &P, const double *u, const double *lam, double *g, hipStream_t s) {

@@ -5,6 +5,8 @@
 // Schwarz block matrices and the deterministic residual norm.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace iga2l {
@@ -28,14 +30,26 @@ __device__ __forceinline__ T dia_entry(const T *__restrict__ val, int64_t npad, 
 }
 
 // ------------------------------------------------------------------------
+// Interior rows of the kappa = 1 operator are translation invariant: rows whose
+// coordinates all lie in [ulo, uhi] carry the (2p+1)^d stencil cs.  A
+// workgroup whose whole tile is such rows reads cs (uniform addresses) instead
+// of the diagonals.
+__device__ __forceinline__ bool tile_uniform(int lo0, int hi0, int lo1, int hi1, int lo2, int hi2, int ulo, int uhi,
+                                             int dim) {
+    return lo0 >= ulo && hi0 <= uhi && lo1 >= ulo && hi1 <= uhi && (dim == 2 || (lo2 >= ulo && hi2 <= uhi));
+}
+
 // Residual r = b - A x over tiles of TX x TY (x TZ) points; x staged in LDS
-// with a halo of width P (zeros outside the grid).  NORM: per-workgroup
-// partial sums of r^2 (fixed reduction order) for the FP64 outer residual.
+// with a halo of width P (zeros outside the grid).  NORM: the per-workgroup
+// sums of r^2 are combined by the last workgroup to finish, in a fixed
+// order, into ||r||_2 and the scaling of the FP32 correction cycle.
 template <int D, int P, class T, bool NORM>
 __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
                                                   int n1, int TX, int TY, int TZ, const T *__restrict__ x,
                                                   const T *__restrict__ b, T *__restrict__ r,
-                                                  double *__restrict__ partial) {
+                                                  double *__restrict__ partial, const T *__restrict__ cs, int ulo,
+                                                  int uhi, const int *__restrict__ skip) {
+    const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     extern __shared__ unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
     const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
@@ -48,6 +62,9 @@ __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int
         xs[h] = in ? x[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
     }
     __syncthreads();
+    const bool uni = cs != nullptr &&
+                     tile_uniform(gx0, min(gx0 + TX, n1) - 1, gy0, min(gy0 + TY, n1) - 1, gz0,
+                                  min(gz0 + TZ, n1) - 1, ulo, uhi, D);
     const int t = threadIdx.x;
     const int tx = t % TX, ty = (t / TX) % TY, tz = (D == 3) ? t / (TX * TY) : 0;
     const int gx = gx0 + tx, gy = gy0 + ty, gz = gz0 + tz;
@@ -59,31 +76,52 @@ __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int
         const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
         T acc = T(0);
         if constexpr (D == 2) {
+            if (uni) {
 #pragma unroll
-            for (int oy = -P; oy <= P; ++oy)
+                for (int oy = -P; oy <= P; ++oy)
 #pragma unroll
-                for (int ox = -P; ox <= P; ++ox) {
-                    const int w = (oy + P) * (2 * P + 1) + (ox + P);
-                    const T a = dia_entry<D, P, T>(val, npad, padi, w, int64_t(ox) + int64_t(oy) * pitch1);
-                    acc += a * xs[lc + oy * HX + ox];
-                }
-        } else {
-#pragma unroll
-            for (int oz = -P; oz <= P; ++oz)
+                    for (int ox = -P; ox <= P; ++ox)
+                        acc += cs[(oy + P) * (2 * P + 1) + (ox + P)] * xs[lc + oy * HX + ox];
+            } else {
 #pragma unroll
                 for (int oy = -P; oy <= P; ++oy)
 #pragma unroll
                     for (int ox = -P; ox <= P; ++ox) {
-                        const int w = ((oz + P) * (2 * P + 1) + (oy + P)) * (2 * P + 1) + (ox + P);
-                        const T a = dia_entry<D, P, T>(val, npad, padi, w,
-                                                       int64_t(ox) + int64_t(oy) * pitch1 + int64_t(oz) * pitch2);
-                        acc += a * xs[lc + (oz * HY + oy) * HX + ox];
+                        const int w = (oy + P) * (2 * P + 1) + (ox + P);
+                        const T a = dia_entry<D, P, T>(val, npad, padi, w, int64_t(ox) + int64_t(oy) * pitch1);
+                        acc += a * xs[lc + oy * HX + ox];
                     }
+            }
+        } else {
+            if (uni) {
+#pragma unroll
+                for (int oz = -P; oz <= P; ++oz)
+#pragma unroll
+                    for (int oy = -P; oy <= P; ++oy)
+#pragma unroll
+                        for (int ox = -P; ox <= P; ++ox)
+                            acc += cs[((oz + P) * (2 * P + 1) + (oy + P)) * (2 * P + 1) + (ox + P)] *
+                                   xs[lc + (oz * HY + oy) * HX + ox];
+            } else {
+#pragma unroll
+                for (int oz = -P; oz <= P; ++oz)
+#pragma unroll
+                    for (int oy = -P; oy <= P; ++oy)
+#pragma unroll
+                        for (int ox = -P; ox <= P; ++ox) {
+                            const int w = ((oz + P) * (2 * P + 1) + (oy + P)) * (2 * P + 1) + (ox + P);
+                            const T a = dia_entry<D, P, T>(val, npad, padi, w,
+                                                           int64_t(ox) + int64_t(oy) * pitch1 + int64_t(oz) * pitch2);
+                            acc += a * xs[lc + (oz * HY + oy) * HX + ox];
+                        }
+            }
         }
         const T res = b[gi] - acc;
+        if (stop) return;
         r[gi] = res;
         rr = double(res) * double(res);
     }
+    if (stop) return;
     if constexpr (NORM) {
         __shared__ double red[256 / kWave];
         for (int off = kWave / 2; off > 0; off >>= 1) rr += __shfl_down(rr, off, kWave);
@@ -113,7 +151,9 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
                                                  int n1, const T *__restrict__ inv, const int *__restrict__ cls,
                                                  int ncls1, const T *__restrict__ x_src, T *__restrict__ x_dst,
                                                  const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz,
-                                                 int S, int NBX, int NBY, int NBZ) {
+                                                 int S, int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo,
+                                                 int uhi, const int *__restrict__ skip) {
+    const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     constexpr int BD = cpow(B, D);
     constexpr int HB = (B - 1) / 2;
     extern __shared__ unsigned char smem_raw[];
@@ -139,6 +179,9 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
     const int tx = t % TX, ty = (t / TX) % TY, tz = (D == 3) ? t / (TX * TY) : 0;
     const int gx = gx0 + tx, gy = gy0 + ty, gz = gz0 + tz;
     const bool mine = t < ntile && gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
+    const bool uni = cs != nullptr && tile_uniform(max(gx0, 0), min(gx0 + TX, n1) - 1, max(gy0, 0),
+                                                   min(gy0 + TY, n1) - 1, max(gz0, 0), min(gz0 + TZ, n1) - 1, ulo,
+                                                   uhi, D);
     const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
     // position inside the cell; points outside the block part are not in any block of this colour
     const int cx = tx % S, cy = ty % S, cz = (D == 3) ? tz % S : 0;
@@ -154,7 +197,16 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
                 const int64_t padi =
                     int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
                 T acc = T(0);
-                if constexpr (D == 2) {
+                if (uni) {
+#pragma unroll
+                    for (int qz = ((D == 3) ? -P : 0); qz <= ((D == 3) ? P : 0); ++qz)
+#pragma unroll
+                        for (int qy = -P; qy <= P; ++qy)
+#pragma unroll
+                            for (int qx = -P; qx <= P; ++qx)
+                                acc += cs[(((D == 3) ? (qz + P) * (2 * P + 1) : 0) + (qy + P)) * (2 * P + 1) + (qx + P)] *
+                                       xs[lc + (qz * HY + qy) * HX + qx];
+                } else if constexpr (D == 2) {
 #pragma unroll
                     for (int qy = -P; qy <= P; ++qy)
 #pragma unroll
@@ -180,6 +232,7 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
             }
         }
     }
+    if (stop) return;
     if (t < ntile) rs[t] = res;
     __syncthreads();
     if (!mine) return;
@@ -215,7 +268,8 @@ __global__ void __launch_bounds__(128) k_lex_step(const double *__restrict__ val
                                                   int pitch2, int n1, const double *__restrict__ inv,
                                                   const int *__restrict__ cls, int ncls1,
                                                   const int *__restrict__ blocks, int first, double *u,
-                                                  const double *__restrict__ b) {
+                                                  const double *__restrict__ b, const int *__restrict__ skip) {
+    if (skip && *skip) return;
     constexpr int BD = cpow(B, D);
     constexpr int HB = (B - 1) / 2;
     __shared__ double rs[BD];
@@ -328,9 +382,12 @@ __global__ void __launch_bounds__(kWave) k_block_inverse(const double *__restric
 
 // ------------------------------------------------------------------------
 // Fixed-order reduction of the per-workgroup partial sums into ||r||_2 and
-// the scaling used by the FP32 correction cycle.
+// the scaling used by the FP32 correction cycle.  book != nullptr: the
+// device-side convergence test after a cycle (record the relative residual,
+// count the cycle, raise the stop flag).
 __global__ void __launch_bounds__(256) k_norm_finalize(const double *__restrict__ partial, int np, double *scal,
-                                                       int scale_fp32) {
+                                                       int scale_fp32, int *book, double *hist, int hist_cap) {
+    if (book && book[kFlagDone]) return;
     __shared__ double red[256];
     double s = 0.0;
     for (int i = threadIdx.x; i < np; i += 256) s += partial[i];
@@ -346,14 +403,52 @@ __global__ void __launch_bounds__(256) k_norm_finalize(const double *__restrict_
         scal[kScalNorm] = nrm;
         scal[kScalSigma] = sigma;
         scal[kScalInvSigma] = 1.0 / sigma;
+        if (book) {
+            const double r0 = scal[kScalR0];
+            const double rel = r0 > 0.0 ? nrm / r0 : 0.0;
+            const int k = book[kFlagIter];
+            if (k < hist_cap) hist[k] = rel;
+            book[kFlagIter] = k + 1;
+            int status = 0;
+            if (!isfinite(rel) || rel > 1e3) status = 2;
+            else if (rel > scal[kScalTol] && k + 1 >= int(scal[kScalMaxCycles])) status = 1;
+            book[kFlagStatus] = status;
+            book[kFlagDone] = (status != 0 || rel <= scal[kScalTol]) ? 1 : 0;
+        }
     }
+}
+
+// Start of a solve: the norm just computed is r0; set the stopping data.
+__global__ void k_solve_init(double *scal, int *flags, double tol, int max_cycles) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double r0 = scal[kScalNorm];
+    scal[kScalR0] = r0;
+    scal[kScalTol] = tol;
+    scal[kScalMaxCycles] = double(max_cycles);
+    int status = 0, done = 0;
+    if (!isfinite(r0)) {
+        status = 2;
+        done = 1;
+    } else if (r0 == 0.0 || tol >= 1.0) {
+        done = 1;
+    } else if (max_cycles == 0) {
+        status = 1;
+        done = 1;
+    }
+    flags[kFlagDone] = done;
+    flags[kFlagIter] = 0;
+    flags[kFlagStatus] = status;
 }
 
 template <class T>
 __global__ void k_cast_scale(const double *__restrict__ r64, T *__restrict__ out, const double *__restrict__ scal,
-                             int64_t n) {
+                             int64_t n, const int *__restrict__ skip) {
+    const int stop = skip ? *skip : 0;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = T(r64[i] * scal[kScalInvSigma]);
+    if (i >= n) return;
+    const T v = T(r64[i] * scal[kScalInvSigma]);
+    if (stop) return;
+    out[i] = v;
 }
 
 // ------------------------------------------------------------ dispatch --
@@ -368,16 +463,27 @@ struct TileShape<3, P> {
     static constexpr int TX = 16, TY = 8, TZ = 2;
 };
 
+template <class T>
+const T *uniform_stencil(const Problem &Pb) {
+    return std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.cs64.ptr)
+                                          : reinterpret_cast<const T *>(Pb.cs32.ptr);
+}
+
 template <int D, int P, class T, bool NORM>
 void residual_launch(const Problem &Pb, const T *val, const T *x, const T *b, T *r, double *partial, int &nblocks,
-                     hipStream_t s) {
+                     bool scale_fp32, bool book, hipStream_t s) {
     using TS = TileShape<D, P>;
     const int n1 = Pb.fine.n1;
     dim3 grid((n1 + TS::TX - 1) / TS::TX, (n1 + TS::TY - 1) / TS::TY, D == 3 ? (n1 + TS::TZ - 1) / TS::TZ : 1);
     const size_t shm = size_t(TS::TX + 2 * P) * (TS::TY + 2 * P) * (D == 3 ? TS::TZ + 2 * P : 1) * sizeof(T);
     nblocks = int(grid.x * grid.y * grid.z);
     hipLaunchKernelGGL((k_residual<D, P, T, NORM>), grid, dim3(TS::TX * TS::TY * TS::TZ), shm, s, val, Pb.A.npad,
-                       Pb.A.pitch[1], Pb.A.pitch[2], n1, TS::TX, TS::TY, TS::TZ, x, b, r, partial);
+                       Pb.A.pitch[1], Pb.A.pitch[2], n1, TS::TX, TS::TY, TS::TZ, x, b, r, partial,
+                       uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip);
+    if (NORM)
+        hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, Pb.partial.as<double>(), nblocks,
+                           Pb.scal.as<double>(), scale_fp32 ? 1 : 0, book ? dev_flags(Pb) : nullptr, dev_hist(Pb),
+                           Pb.hist_cap);
 }
 
 #define IGA2L_DISPATCH_P2(F, ...)                                   \
@@ -402,14 +508,16 @@ void residual_launch(const Problem &Pb, const T *val, const T *x, const T *b, T 
     }
 
 template <int D, int P>
-void res64_dp(const Problem &Pb, const double *u, const double *b, double *r, bool norm, hipStream_t s) {
+void res64_dp(const Problem &Pb, const double *u, const double *b, double *r, bool norm, bool scale_fp32,
+              bool book, hipStream_t s) {
     int nb = 0;
     if (norm) {
         IGA2L_REQUIRE(residual_workgroups(Pb) <= Pb.npartial, IGA2L_EUNSUPPORTED,
                       "grid too large for the norm workspace");
-        residual_launch<D, P, double, true>(Pb, Pb.A.v64.as<double>(), u, b, r, Pb.partial.as<double>(), nb, s);
+        residual_launch<D, P, double, true>(Pb, Pb.A.v64.as<double>(), u, b, r, Pb.partial.as<double>(), nb,
+                                            scale_fp32, book, s);
     } else {
-        residual_launch<D, P, double, false>(Pb, Pb.A.v64.as<double>(), u, b, r, nullptr, nb, s);
+        residual_launch<D, P, double, false>(Pb, Pb.A.v64.as<double>(), u, b, r, nullptr, nb, false, false, s);
     }
 }
 
@@ -418,7 +526,7 @@ void defect_dp(const Problem &Pb, const T *e, const T *rhs, T *d, hipStream_t s)
     int nb = 0;
     const T *val = std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.A.v64.ptr)
                                                   : reinterpret_cast<const T *>(Pb.A.v32.ptr);
-    residual_launch<D, P, T, false>(Pb, val, e, rhs, d, nullptr, nb, s);
+    residual_launch<D, P, T, false>(Pb, val, e, rhs, d, nullptr, nb, false, false, s);
 }
 
 template <int D, int P, int B, class T>
@@ -451,7 +559,7 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
                                                   : reinterpret_cast<const T *>(Pb.Inv32.ptr);
     hipLaunchKernelGGL((k_colour<D, P, B, T>), grid, dim3(threads), shm, s, val, Pb.A.npad, Pb.A.pitch[1],
                        Pb.A.pitch[2], n1, inv, Pb.cls_d.as<int>(), Pb.ncls1, x_src, x_dst, rhs, x_zero ? 1 : 0, ox,
-                       oy, oz, S, nbx, nby, nbz);
+                       oy, oz, S, nbx, nby, nbz, uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip);
 }
 
 template <int D, int P, class T>
@@ -479,7 +587,7 @@ void lex_launch(const Problem &Pb, int step, double *u, const double *b, hipStre
     const int threads = BD <= 64 ? 64 : 128;
     hipLaunchKernelGGL((k_lex_step<D, P, B>), dim3(cnt), dim3(threads), 0, s, Pb.A.v64.as<double>(), Pb.A.npad,
                        Pb.A.pitch[1], Pb.A.pitch[2], Pb.fine.n1, Pb.Inv64.as<double>(), Pb.cls_d.as<int>(), Pb.ncls1,
-                       Pb.lex_blocks.as<int>(), first, u, b);
+                       Pb.lex_blocks.as<int>(), first, u, b, Pb.skip);
 }
 
 template <int D, int P>
@@ -502,12 +610,12 @@ void lex_dp(const Problem &Pb, int step, double *u, const double *b, hipStream_t
 }  // namespace
 
 // ------------------------------------------------------------ launchers --
-void launch_residual64(const Problem &Pb, const double *u, const double *b, double *r, bool partial_norm,
-                       hipStream_t s) {
+void launch_residual64(const Problem &Pb, const double *u, const double *b, double *r, bool with_norm,
+                       bool scale_fp32, bool book, hipStream_t s) {
     if (Pb.dim == 2) {
-        IGA2L_DISPATCH_P2(res64_dp, Pb, u, b, r, partial_norm, s);
+        IGA2L_DISPATCH_P2(res64_dp, Pb, u, b, r, with_norm, scale_fp32, book, s);
     } else {
-        IGA2L_DISPATCH_P3(res64_dp, Pb, u, b, r, partial_norm, s);
+        IGA2L_DISPATCH_P3(res64_dp, Pb, u, b, r, with_norm, scale_fp32, book, s);
     }
 }
 
@@ -530,12 +638,10 @@ int64_t residual_workgroups(const Problem &Pb) {
            ((n1 + TileShape<3, 1>::TZ - 1) / TileShape<3, 1>::TZ);
 }
 
-void launch_norm_finalize(const Problem &Pb, bool scale_fp32, hipStream_t s) {
-    const int64_t nb = residual_workgroups(Pb);
-    IGA2L_REQUIRE(nb <= Pb.npartial, IGA2L_EUNSUPPORTED, "grid too large for the norm workspace");
-    hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, Pb.partial.as<double>(), int(nb),
-                       Pb.scal.as<double>(), scale_fp32 ? 1 : 0);
+void launch_solve_init(const Problem &Pb, double tol, int max_cycles, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, s, Pb.scal.as<double>(), dev_flags(Pb), tol, max_cycles);
 }
+
 
 template <class T>
 void launch_colour_step(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs,
@@ -562,7 +668,8 @@ void launch_lex_step(const Problem &Pb, int step, double *u, const double *b, hi
 template <class T>
 void launch_cast_scale(const Problem &Pb, const double *r64, T *rhs, hipStream_t s) {
     const int64_t n = Pb.fine.n;
-    hipLaunchKernelGGL((k_cast_scale<T>), dim3((n + 255) / 256), dim3(256), 0, s, r64, rhs, Pb.scal.as<double>(), n);
+    hipLaunchKernelGGL((k_cast_scale<T>), dim3((n + 255) / 256), dim3(256), 0, s, r64, rhs, Pb.scal.as<double>(), n,
+                       Pb.skip);
 }
 template void launch_cast_scale<float>(const Problem &, const double *, float *, hipStream_t);
 template void launch_cast_scale<double>(const Problem &, const double *, double *, hipStream_t);

@@ -91,7 +91,8 @@ __device__ __forceinline__ T interp_value(const T *__restrict__ ec, int n1c, int
 template <int D, class T>
 __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restrict__ e_src, int zero_src,
                                                  const T *__restrict__ ec, int n1c, const T *__restrict__ rhs,
-                                                 T *__restrict__ e_dst) {
+                                                 T *__restrict__ e_dst, const int *__restrict__ skip) {
+    const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     constexpr int TX = VT<D>::TX, TY = VT<D>::TY, TZ = VT<D>::TZ;
     constexpr int HX = TX + 4, HY = TY + 4, HZ = (D == 3) ? TZ + 4 : 1;
     constexpr int NH = HX * HY * HZ;
@@ -133,6 +134,7 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
         e1[h] = e0[h] + (rhs[gi] - acc) * inv_diag<D, T>(L, gi);
     }
     __syncthreads();
+    if (stop) return;
     // black half step on the tile; write the result
     const int ntile = TX * TY * ((D == 3) ? TZ : 1);
     for (int t = threadIdx.x; t < ntile; t += blockDim.x) {
@@ -157,7 +159,8 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
 // e_dst = e_src + P ec (used only when no post-smoothing step follows)
 template <int D, class T>
 __global__ void k_interp_add2(const T *__restrict__ e_src, int zero_src, const T *__restrict__ ec, int n1c, int n1,
-                              T *__restrict__ e_dst) {
+                              T *__restrict__ e_dst, const int *__restrict__ skip) {
+    if (skip && *skip) return;
     const int64_t n = (D == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -170,7 +173,8 @@ __global__ void k_interp_add2(const T *__restrict__ e_src, int zero_src, const T
 template <int D, class T>
 __global__ void __launch_bounds__(256) k_res_restrict_tiled(LevelDev<T> L, const T *__restrict__ e, int zero_e,
                                                             const T *__restrict__ rhs, int n1c,
-                                                            T *__restrict__ rc) {
+                                                            T *__restrict__ rc, const int *__restrict__ skip) {
+    const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     constexpr int CX = VT<D>::CX, CY = VT<D>::CY, CZ = VT<D>::CZ;
     constexpr int FX = 2 * CX + 1, FY = 2 * CY + 1, FZ = (D == 3) ? 2 * CZ + 1 : 1;  // fine region
     constexpr int EX = FX + 2, EY = FY + 2, EZ = (D == 3) ? FZ + 2 : 1;              // + halo 1
@@ -211,6 +215,7 @@ __global__ void __launch_bounds__(256) k_res_restrict_tiled(LevelDev<T> L, const
         rs[f] = r;
     }
     __syncthreads();
+    if (stop) return;
     const int nct = CX * CY * ((D == 3) ? CZ : 1);
     for (int c = threadIdx.x; c < nct; c += blockDim.x) {
         const int cx = c % CX, cy = (c / CX) % CY, cz = (D == 3) ? c / (CX * CY) : 0;
@@ -247,18 +252,52 @@ __device__ __forceinline__ int64_t padded_size(int n1) {
     return (D == 3) ? int64_t(n1 + 2) * (n1 + 2) * (n1 + 2) : int64_t(n1 + 2) * (n1 + 2);
 }
 
+// thread layout of the one-workgroup kernel: 32 x 32 (2-D) or 16 x 8 x 8 (3-D)
+template <int D>
+struct BT;
+template <>
+struct BT<2> {
+    static constexpr int X = 32, Y = 32, Z = 1;
+};
+template <>
+struct BT<3> {
+    static constexpr int X = 16, Y = 8, Z = 8;
+};
+
 template <int D, class T>
 __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, T> A, const T *__restrict__ rhs_top,
-                                                                  T *__restrict__ e_top, int nu1, int nu2) {
+                                                                  T *__restrict__ e_top, int nu1, int nu2,
+                                                                  const int *__restrict__ skip) {
+    if (skip && *skip) return;
     extern __shared__ unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
-    // LDS: for each level: e (padded), rhs (padded); then one residual scratch (padded, level lb)
-    __shared__ int64_t off_e[16], off_r[16], off_end;
+    // LDS: for each level: e (padded), rhs (padded); then one residual scratch
+    // (padded, level lb).  A padded level of n1 points per direction has
+    // pitch n1+2 and the point (x,y,z) at ((z+1)(n1+2) + y+1)(n1+2) + x+1.
+    __shared__ int off_e[16], off_r[16], s_n1[16], s_cst[16], off_end;
+    constexpr int W3 = (D == 3) ? 27 : 9;
+    __shared__ T s_c[16][W3];          // constant stencils
+    __shared__ T s_cinv[16];
+    __shared__ const T *s_S[16];       // per-point stencils / reciprocal diagonals otherwise
+    __shared__ const T *s_invd[16];
+    __shared__ int64_t s_n[16];
     const int tid = threadIdx.x;
+    const int tx = tid % BT<D>::X, ty = (tid / BT<D>::X) % BT<D>::Y, tz = (D == 3) ? tid / (BT<D>::X * BT<D>::Y) : 0;
+    if (tid < A.nlev) {
+        const LevelDev<T> &L = A.levels[tid];
+        for (int w = 0; w < W3; ++w) s_c[tid][w] = L.c[w];
+        s_cinv[tid] = L.cinv;
+        s_S[tid] = L.S;
+        s_invd[tid] = L.invd;
+        s_n[tid] = L.n;
+    }
     if (tid == 0) {
-        int64_t acc = 0;
+        int acc = 0;
         for (int l = 0; l < A.nlev; ++l) {
-            const int64_t ps = padded_size<D>(A.levels[l].n1);
+            const int n1 = A.levels[l].n1;
+            const int ps = (D == 3) ? (n1 + 2) * (n1 + 2) * (n1 + 2) : (n1 + 2) * (n1 + 2);
+            s_n1[l] = n1;
+            s_cst[l] = A.levels[l].cst;
             off_e[l] = acc;
             acc += ps;
             off_r[l] = acc;
@@ -267,55 +306,68 @@ __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, 
         off_end = acc;
     }
     __syncthreads();
-    const int64_t o = off_end;
-    T *scr = sm + o;
-    // zero everything (padding must be zero)
-    const int64_t total = o + padded_size<D>(A.levels[0].n1);
-    for (int64_t i = tid; i < total; i += blockDim.x) sm[i] = T(0);
-    __syncthreads();
-    // load the top right-hand side
+    T *scr = sm + off_end;
     {
-        const int n1 = A.levels[0].n1;
-        const int64_t n = A.levels[0].n;
-        for (int64_t i = tid; i < n; i += blockDim.x) {
-            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
-            sm[off_r[0] + ((D == 3) ? (int64_t(z + 1) * (n1 + 2) + (y + 1)) * (n1 + 2) + (x + 1)
-                                    : int64_t(y + 1) * (n1 + 2) + (x + 1))] = rhs_top[i];
+        const int n1 = s_n1[0];
+        const int total = off_end + ((D == 3) ? (n1 + 2) * (n1 + 2) * (n1 + 2) : (n1 + 2) * (n1 + 2));
+        for (int i = tid; i < total; i += kBottomThreads) sm[i] = T(0);
+    }
+    __syncthreads();
+    // loops over the points of a level owned by this thread
+#define IGA2L_FOR_POINTS(n1)                                              \
+    for (int z = tz; z < ((D == 3) ? (n1) : 1); z += BT<D>::Z)            \
+        for (int y = ty; y < (n1); y += BT<D>::Y)                         \
+            for (int x = tx; x < (n1); x += BT<D>::X)
+    {
+        const int n1 = s_n1[0];
+        T *r0 = sm + off_r[0];
+        IGA2L_FOR_POINTS(n1) {
+            const int i = (z * n1 + y) * n1 + x;
+            r0[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1] = rhs_top[i];
         }
     }
     __syncthreads();
 
-    auto pidx = [](int n1, int x, int y, int z) -> int64_t {
-        return (D == 3) ? (int64_t(z + 1) * (n1 + 2) + (y + 1)) * (n1 + 2) + (x + 1) : int64_t(y + 1) * (n1 + 2) + (x + 1);
-    };
-    // A e at an unpadded point i of level l (e in LDS)
-    auto apply = [&](int l, const T *e, int64_t i, int x, int y, int z) -> T {
-        const LevelDev<T> &L = A.levels[l];
-        const int n1 = L.n1;
-        const int64_t c = pidx(n1, x, y, z);
-        const int64_t sy = n1 + 2, sz = int64_t(n1 + 2) * (n1 + 2);
+    // operator application at padded position c (unpadded index i) of level l
+    auto apply = [&](int l, int cst, const T *e, int n1, int c, int i) -> T {
+        const int sy = n1 + 2, sz = (n1 + 2) * (n1 + 2);
         T acc = T(0);
-        for (int oz = ((D == 3) ? -1 : 0); oz <= ((D == 3) ? 1 : 0); ++oz)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int ox = -1; ox <= 1; ++ox)
-                    acc += coef<D, T>(L, i, w_of<D>(ox, oy, oz)) * e[c + oz * sz + oy * sy + ox];
+        if (cst) {
+#pragma unroll
+            for (int oz = ((D == 3) ? -1 : 0); oz <= ((D == 3) ? 1 : 0); ++oz)
+#pragma unroll
+                for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+                    for (int ox = -1; ox <= 1; ++ox)
+                        acc += s_c[l][w_of<D>(ox, oy, oz)] * e[c + oz * sz + oy * sy + ox];
+        } else {
+            const T *S = s_S[l];
+            const int64_t n = s_n[l];
+#pragma unroll
+            for (int oz = ((D == 3) ? -1 : 0); oz <= ((D == 3) ? 1 : 0); ++oz)
+#pragma unroll
+                for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+                    for (int ox = -1; ox <= 1; ++ox)
+                        acc += S[int64_t(w_of<D>(ox, oy, oz)) * n + i] * e[c + oz * sz + oy * sy + ox];
+        }
         return acc;
     };
-    // one half step of the given colour on level l
     auto half = [&](int l, int colour) {
-        const LevelDev<T> &L = A.levels[l];
-        const int n1 = L.n1;
-        const int64_t n = L.n;
+        const int n1 = s_n1[l], cst = s_cst[l];
+        const T cinv = s_cinv[l];
+        const T *invd = s_invd[l];
         T *e = sm + off_e[l];
         const T *r = sm + off_r[l];
         T newv[kBottomMaxPts];
-        int64_t where[kBottomMaxPts];
+        int where[kBottomMaxPts];
         int cnt = 0;
-        for (int64_t i = tid; i < n && cnt < kBottomMaxPts; i += blockDim.x) {
-            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
-            if (((x + y + z) & 1) != colour) continue;
-            const int64_t c = pidx(n1, x, y, z);
-            newv[cnt] = e[c] + (r[c] - apply(l, e, i, x, y, z)) * inv_diag<D, T>(L, i);
+        IGA2L_FOR_POINTS(n1) {
+            if (((x + y + z) & 1) != colour || cnt >= kBottomMaxPts) continue;
+            const int i = (z * n1 + y) * n1 + x;
+            const int c = ((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1;
+            const T id = cst ? cinv : invd[i];
+            newv[cnt] = e[c] + (r[c] - apply(l, cst, e, n1, c, i)) * id;
             where[cnt++] = c;
         }
         __syncthreads();
@@ -324,61 +376,51 @@ __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, 
     };
 
     const int last = A.nlev - 1;
-    // descend
     for (int l = 0; l < last; ++l) {
         for (int k = 0; k < nu1; ++k) {
             half(l, 0);
             half(l, 1);
         }
-        // residual of level l into the scratch, then restriction into rhs of level l+1
-        const LevelDev<T> &L = A.levels[l];
-        const int n1 = L.n1;
+        const int n1 = s_n1[l], cst = s_cst[l];
         const T *e = sm + off_e[l];
         const T *r = sm + off_r[l];
-        for (int64_t i = tid; i < L.n; i += blockDim.x) {
-            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
-            const int64_t c = pidx(n1, x, y, z);
-            scr[c] = r[c] - apply(l, e, i, x, y, z);
+        IGA2L_FOR_POINTS(n1) {
+            const int i = (z * n1 + y) * n1 + x;
+            const int c = ((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1;
+            scr[c] = r[c] - apply(l, cst, e, n1, c, i);
         }
         __syncthreads();
-        const LevelDev<T> &C = A.levels[l + 1];
-        const int n1c = C.n1;
+        const int n1c = s_n1[l + 1];
         T *rc = sm + off_r[l + 1];
         T *ecl = sm + off_e[l + 1];
-        for (int64_t I = tid; I < C.n; I += blockDim.x) {
-            const int X = int(I % n1c), Y = int((I / n1c) % n1c), Z = (D == 3) ? int(I / (int64_t(n1c) * n1c)) : 0;
+        IGA2L_FOR_POINTS(n1c) {
             T acc = T(0);
             for (int az = ((D == 3) ? -1 : 0); az <= ((D == 3) ? 1 : 0); ++az)
                 for (int ay = -1; ay <= 1; ++ay)
                     for (int ax = -1; ax <= 1; ++ax) {
-                        const T w = (ax == 0 ? T(1) : T(0.5)) * (ay == 0 ? T(1) : T(0.5)) *
-                                    ((D == 3 && az != 0) ? T(0.5) : T(1));
-                        const int fx = 2 * X + 1 + ax, fy = 2 * Y + 1 + ay, fz = (D == 3) ? 2 * Z + 1 + az : 0;
+                        const int fx = 2 * x + 1 + ax, fy = 2 * y + 1 + ay, fz = (D == 3) ? 2 * z + 1 + az : 0;
                         // the scratch is shared by all levels: never read outside level l's points
                         if (fx >= n1 || fy >= n1 || (D == 3 && fz >= n1)) continue;
-                        acc += w * scr[pidx(n1, fx, fy, fz)];
+                        const T w = (ax == 0 ? T(1) : T(0.5)) * (ay == 0 ? T(1) : T(0.5)) *
+                                    ((D == 3 && az != 0) ? T(0.5) : T(1));
+                        acc += w * scr[((D == 3) ? ((fz + 1) * (n1 + 2) + fy + 1) : (fy + 1)) * (n1 + 2) + fx + 1];
                     }
-            rc[pidx(n1c, X, Y, Z)] = acc;
-            ecl[pidx(n1c, X, Y, Z)] = T(0);
+            const int cc = ((D == 3) ? ((z + 1) * (n1c + 2) + y + 1) : (y + 1)) * (n1c + 2) + x + 1;
+            rc[cc] = acc;
+            ecl[cc] = T(0);
         }
         __syncthreads();
     }
-    // coarsest level: one node per direction
-    if (tid == 0) {
-        const LevelDev<T> &Z = A.levels[last];
-        const int64_t c = pidx(Z.n1, 0, 0, 0);
-        sm[off_e[last] + c] = sm[off_r[last] + c] * inv_diag<D, T>(Z, 0);
+    if (tid == 0) {  // coarsest level: one node
+        const int c = (D == 3) ? (1 * 3 + 1) * 3 + 1 : 1 * 3 + 1;
+        sm[off_e[last] + c] = sm[off_r[last] + c] * (s_cst[last] ? s_cinv[last] : s_invd[last][0]);
     }
     __syncthreads();
-    // ascend
     for (int l = last - 1; l >= 0; --l) {
-        const LevelDev<T> &L = A.levels[l];
-        const LevelDev<T> &C = A.levels[l + 1];
-        const int n1 = L.n1, n1c = C.n1;
+        const int n1 = s_n1[l], n1c = s_n1[l + 1];
         T *e = sm + off_e[l];
         const T *ecl = sm + off_e[l + 1];
-        for (int64_t i = tid; i < L.n; i += blockDim.x) {
-            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
+        IGA2L_FOR_POINTS(n1) {
             int Ix[2], Iy[2], Iz[2];
             T wx[2], wy[2], wz[2];
             const int nx = parents<T>(x, n1c, Ix, wx), ny = parents<T>(y, n1c, Iy, wy);
@@ -389,8 +431,12 @@ __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, 
             T acc = T(0);
             for (int cc = 0; cc < nz; ++cc)
                 for (int bb = 0; bb < ny; ++bb)
-                    for (int aa = 0; aa < nx; ++aa) acc += wz[cc] * wy[bb] * wx[aa] * ecl[pidx(n1c, Ix[aa], Iy[bb], Iz[cc])];
-            e[pidx(n1, x, y, z)] += acc;
+                    for (int aa = 0; aa < nx; ++aa) {
+                        const int q = ((D == 3) ? ((Iz[cc] + 1) * (n1c + 2) + Iy[bb] + 1) : (Iy[bb] + 1)) * (n1c + 2) +
+                                      Ix[aa] + 1;
+                        acc += wz[cc] * wy[bb] * wx[aa] * ecl[q];
+                    }
+            e[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1] += acc;
         }
         __syncthreads();
         for (int k = 0; k < nu2; ++k) {
@@ -398,14 +444,14 @@ __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, 
             half(l, 1);
         }
     }
-    // write the result of level lb
     {
-        const int n1 = A.levels[0].n1;
-        for (int64_t i = tid; i < A.levels[0].n; i += blockDim.x) {
-            const int x = int(i % n1), y = int((i / n1) % n1), z = (D == 3) ? int(i / (int64_t(n1) * n1)) : 0;
-            e_top[i] = sm[off_e[0] + pidx(n1, x, y, z)];
+        const int n1 = s_n1[0];
+        const T *e0 = sm + off_e[0];
+        IGA2L_FOR_POINTS(n1) {
+            e_top[(z * n1 + y) * n1 + x] = e0[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1];
         }
     }
+#undef IGA2L_FOR_POINTS
 }
 
 template <class T>
@@ -433,7 +479,8 @@ void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, 
         const size_t nlev = P.levels.size() - lb;
         BottomArgs<D, T> a{int(nlev), levdev<T>(P) + lb};
         const size_t shm = size_t(vcycle_bottom_lds(P, lb)) * sizeof(T);
-        hipLaunchKernelGGL((k_vcycle_bottom<D, T>), dim3(1), dim3(kBottomThreads), shm, s, a, rhs, e_out, nu1, nu2);
+        hipLaunchKernelGGL((k_vcycle_bottom<D, T>), dim3(1), dim3(kBottomThreads), shm, s, a, rhs, e_out, nu1, nu2,
+                           P.skip);
         return;
     }
     Level &L = P.levels[l];
@@ -448,24 +495,26 @@ void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, 
     bool zero = true;
     for (int k = 0; k < nu1; ++k) {
         hipLaunchKernelGGL((k_rb_step<D, T>), sgrid, dim3(256), 0, s, Ld, buf[cur], zero ? 1 : 0,
-                           static_cast<const T *>(nullptr), 0, rhs, buf[1 - cur]);
+                           static_cast<const T *>(nullptr), 0, rhs, buf[1 - cur], P.skip);
         cur = 1 - cur;
         zero = false;
     }
     T *rc = C.rhs.as<T>();
     T *ecl = C.res.as<T>();
-    hipLaunchKernelGGL((k_res_restrict_tiled<D, T>), rgrid, dim3(256), 0, s, Ld, buf[cur], zero ? 1 : 0, rhs, n1c, rc);
+    hipLaunchKernelGGL((k_res_restrict_tiled<D, T>), rgrid, dim3(256), 0, s, Ld, buf[cur], zero ? 1 : 0, rhs, n1c, rc,
+                       P.skip);
     vcycle_top<D, T>(P, l + 1, rc, ecl, nu1, nu2, s);
     // post-smoothing; the first step loads e + P ec, the last one writes e_out
     if (nu2 == 0) {
         hipLaunchKernelGGL((k_interp_add2<D, T>), dim3(nblk(L.g.n, 256)), dim3(256), 0, s, buf[cur], zero ? 1 : 0,
-                           static_cast<const T *>(ecl), n1c, n1, e_out);
+                           static_cast<const T *>(ecl), n1c, n1, e_out, P.skip);
         return;
     }
     for (int k = 0; k < nu2; ++k) {
         T *dst = (k == nu2 - 1) ? e_out : buf[1 - cur];
         hipLaunchKernelGGL((k_rb_step<D, T>), sgrid, dim3(256), 0, s, Ld, buf[cur], zero ? 1 : 0,
-                           (k == 0) ? static_cast<const T *>(ecl) : static_cast<const T *>(nullptr), n1c, rhs, dst);
+                           (k == 0) ? static_cast<const T *>(ecl) : static_cast<const T *>(nullptr), n1c, rhs, dst,
+                           P.skip);
         cur = 1 - cur;
         zero = false;
     }
@@ -494,10 +543,13 @@ int64_t vcycle_bottom_lds(const Problem &P, size_t lb) {
     return tot + ps(P.levels[lb].g.n1);
 }
 
-// points per thread of one half step in the bottom kernel
+// points one thread owns in the bottom kernel (strided 32x32 or 16x8x8 layout)
 bool vcycle_bottom_fits(const Problem &P, size_t lb) {
-    const int64_t n = P.levels[lb].g.n;
-    return (n + kBottomThreads - 1) / kBottomThreads <= kBottomMaxPts && P.levels.size() - lb <= 16;
+    const int n1 = P.levels[lb].g.n1;
+    int64_t per;
+    if (P.dim == 2) per = int64_t((n1 + 31) / 32) * ((n1 + 31) / 32);
+    else per = int64_t((n1 + 15) / 16) * ((n1 + 7) / 8) * ((n1 + 7) / 8);
+    return per <= kBottomMaxPts && P.levels.size() - lb <= 16;
 }
 
 }  // namespace iga2l

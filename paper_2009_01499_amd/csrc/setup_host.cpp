@@ -240,6 +240,35 @@ void host_assemble(Problem &P) {
     A.v64.alloc(val.size() * sizeof(double));
     IGA2L_HIP(hipMemcpy(A.v64.ptr, val.data(), val.size() * sizeof(double), hipMemcpyHostToDevice));
 
+    // kappa = 1: rows whose coordinates lie in [2p-1, n1-2p] couple only
+    // translates of the cardinal B-spline and carry one common stencil, read
+    // here from the centre row of the assembled operator
+    P.ulo = 2 * p - 1;
+    P.uhi = n1 - 2 * p;
+    P.cs64.free();
+    P.cs32.free();
+    if (P.kappa_one && P.uhi >= P.ulo) {
+        int64_t padc = 0;
+        for (int k = 0; k < d; ++k) padc += int64_t(n1 / 2 + p) * A.pitch[k];
+        std::vector<double> cs(A.W);
+        std::vector<float> cs32(A.W);
+        int o[kMaxDim] = {0, 0, 0};
+        for (int w = 0; w < A.W; ++w) {
+            split(w, d, w1, o);
+            int64_t delta = 0;
+            for (int k = 0; k < d; ++k) delta += int64_t(o[k] - p) * A.pitch[k];
+            cs[w] = (w >= c0) ? val[size_t(w - c0) * A.npad + padc] : val[size_t(c0 - w) * A.npad + padc + delta];
+            cs32[w] = float(cs[w]);
+        }
+        P.cs64.alloc(cs.size() * sizeof(double));
+        P.cs32.alloc(cs32.size() * sizeof(float));
+        IGA2L_HIP(hipMemcpy(P.cs64.ptr, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice));
+        IGA2L_HIP(hipMemcpy(P.cs32.ptr, cs32.data(), cs32.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        P.ulo = 1;
+        P.uhi = 0;
+    }
+
     P.R1d64.alloc(P.R1.size() * sizeof(double));
     IGA2L_HIP(hipMemcpy(P.R1d64.ptr, P.R1.data(), P.R1.size() * sizeof(double), hipMemcpyHostToDevice));
 
@@ -270,8 +299,10 @@ void host_assemble(Problem &P) {
     P.ctmp.alloc(nc * sizeof(double));
     P.npartial = int(residual_workgroups(P));
     P.partial.alloc(size_t(P.npartial) * sizeof(double));
-    P.scal.alloc(kScalCount * sizeof(double));
-    IGA2L_HIP(hipMemset(P.scal.ptr, 0, kScalCount * sizeof(double)));
+    P.hist_cap = 128;
+    P.scal.alloc(status_bytes(P.hist_cap));
+    IGA2L_HIP(hipMemset(P.scal.ptr, 0, status_bytes(P.hist_cap)));
+    IGA2L_HIP(hipHostMalloc(&P.host_status, status_bytes(P.hist_cap), hipHostMallocDefault));
 }
 
 // ---------------------------------------------------- V-cycle hierarchy --
