@@ -78,6 +78,7 @@ def lib():
             "or_solve": (i, [vp, dp, dp, i, i, i, i, i, i, i, d, i, dp]),
             "or_direct_solve": (i, [vp, dp, dp]),
             "or_grad_kappa": (i, [vp, dp, dp, dp]),
+            "or_element_apply": (i, [vp, l, dp, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -325,6 +326,14 @@ class Problem:
         if lib().or_direct_solve(self._h, _p(b), _p(u)):
             raise ValueError(_err())
         return u
+
+    def element_apply(self, e: int, u):
+        """A_e u for element e (unit coefficient), full-length vector."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        out = np.zeros(self.n)
+        if lib().or_element_apply(self._h, e, _p(u), _p(out)):
+            raise ValueError(_err())
+        return out
 
     def grad_kappa(self, u, lam):
         u = np.ascontiguousarray(u, dtype=np.float64)

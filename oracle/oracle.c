@@ -1121,3 +1121,62 @@ int or_grad_kappa(const or_problem *P, const double *u, const double *lam, doubl
     free(t);
     return 0;
 }
+
+/*
+ * out = A_e u for one element e: (A_e u)_i = integral over e of grad phi_i .
+ * grad u_h (unit coefficient), for the interior functions i live on e; zero
+ * elsewhere.  A = sum_e kappa_e A_e (Section 2).  Tensor Gauss rule with p+1
+ * points per direction (exact).
+ */
+int or_element_apply(const or_problem *P, long el, const double *u, double *out) {
+    int d = P->d, p = P->p, m = P->m, n1 = P->n1;
+    if (el < 0 || el >= P->ne) return fail("or_element_apply: element out of range");
+    double *t = malloc(sizeof(double) * (2 * p + m + 1));
+    or_knots(p, m, t);
+    int q = p + 1;
+    double gx[64], gw[64];
+    or_gauss_legendre(q, gx, gw);
+    double h = 1.0 / m;
+    int nl = p + 1;
+    long nloc = ipow(nl, d), nqp = ipow(q, d);
+    double val[OR_MAXD * 16], der[OR_MAXD * 16];
+    int e[OR_MAXD], qi[OR_MAXD], a[OR_MAXD], ia[OR_MAXD];
+    memset(out, 0, sizeof(double) * P->n);
+    unravel(el, d, m, e);
+    for (long qq = 0; qq < nqp; qq++) {
+        unravel(qq, d, q, qi);
+        double wq = 1.0;
+        for (int k = 0; k < d; k++) {
+            double x = (e[k] + 0.5 * (gx[qi[k]] + 1.0)) * h;
+            wq *= 0.5 * h * gw[qi[k]];
+            live_basis(t, p, e[k], x, val + k * nl, der + k * nl);
+        }
+        double gu[OR_MAXD] = {0, 0, 0};
+        for (long la = 0; la < nloc; la++) {
+            unravel(la, d, nl, a);
+            for (int k = 0; k < d; k++) ia[k] = e[k] + a[k] - 1;
+            if (!inside(ia, d, n1)) continue;
+            long i = ravel(ia, d, n1);
+            for (int c = 0; c < d; c++) {
+                double g = 1.0;
+                for (int k = 0; k < d; k++) g *= (k == c) ? der[k * nl + a[k]] : val[k * nl + a[k]];
+                gu[c] += u[i] * g;
+            }
+        }
+        for (long la = 0; la < nloc; la++) {
+            unravel(la, d, nl, a);
+            for (int k = 0; k < d; k++) ia[k] = e[k] + a[k] - 1;
+            if (!inside(ia, d, n1)) continue;
+            long i = ravel(ia, d, n1);
+            double dot = 0.0;
+            for (int c = 0; c < d; c++) {
+                double g = 1.0;
+                for (int k = 0; k < d; k++) g *= (k == c) ? der[k * nl + a[k]] : val[k * nl + a[k]];
+                dot += g * gu[c];
+            }
+            out[i] += wq * dot;
+        }
+    }
+    free(t);
+    return 0;
+}

@@ -274,3 +274,54 @@ def header_functions() -> list:
     txt = open(HEADER_PATH).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(iga2l_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class IGASolve(torch.autograd.Function):
+        """u = A(kappa)^{-1} b on the degree-p B-spline space of m^dim elements.
+
+        forward(kappa, b, dim, p, m, opts_forward, opts_adjoint) assembles and
+        solves with the two-level method; backward(grad_u) solves the adjoint
+        system A lambda = grad_u with the same solver (A is symmetric) and
+        evaluates dL/dkappa_e = -integral_e grad(lambda_h) . grad(u_h) in one
+        element-wise kernel.  Returns (dL/dkappa, dL/db = lambda).
+        """
+
+        @staticmethod
+        def forward(ctx, kappa, b, dim, p, m, opts_forward=None, opts_adjoint=None):
+            kap = kappa.detach().to("cpu", torch.float64).contiguous().numpy()
+            dev = b.device
+            prob = Problem(dim, p, m, kappa=kap, device=dev.index or 0)
+            of = opts_forward or Opts()
+            oa = opts_adjoint or Opts(precision=FP64, tol=1e-12)
+            prob.setup(0, of)
+            if oa.precision != of.precision or oa.coarse != of.coarse:
+                prob.setup(0, oa)
+            u, _ = prob.solve(b.detach().contiguous(), None, of)
+            ctx.prob, ctx.oa = prob, oa
+            ctx.kappa_device, ctx.kappa_shape = kappa.device, kappa.shape
+            ctx.save_for_backward(u)
+            return u.clone()
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            (u,) = ctx.saved_tensors
+            lam, g = ctx.prob.solve_backward(u, grad_u.detach().contiguous(), ctx.oa)
+            gk = g.to(ctx.kappa_device).reshape(ctx.kappa_shape)
+            return gk, lam, None, None, None, None, None
+
+    return IGASolve
+
+
+_IGASolve = None
+
+
+def iga_solve(kappa, b, dim: int, p: int, m: int, opts_forward: Optional[Opts] = None,
+              opts_adjoint: Optional[Opts] = None):
+    """Differentiable solve u = A(kappa)^{-1} b (see the IGASolve Function)."""
+    global _IGASolve
+    if _IGASolve is None:
+        _IGASolve = _autograd_function()
+    return _IGASolve.apply(kappa, b, dim, p, m, opts_forward, opts_adjoint)

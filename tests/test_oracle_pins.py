@@ -563,3 +563,21 @@ def test_kappa_element_order_is_x_fastest():
     for i in np.nonzero(changed)[0]:
         ix, iy = i % n1, i // n1
         assert ix <= p - 1 and iy >= n1 - p
+
+
+def test_element_operator_sums_to_assembled_operator():
+    """sum_e kappa_e A_e u = A(kappa) u, and g_e = -lambda^T A_e u agrees with
+    the gradient routine (two independent element loops)."""
+    d, p, m = 2, 3, 5
+    kap = synth.kappa_grf(d, m, 1.0, 0.3, seed=4)
+    P = O.Problem(d, p, m, kappa=kap)
+    u = synth.initial_guess(d, p, m, seed=1)
+    lam = synth.initial_guess(d, p, m, seed=2)
+    acc = np.zeros(P.n)
+    g = np.zeros(P.ne)
+    for e in range(P.ne):
+        Aeu = P.element_apply(e, u)
+        acc += kap[e] * Aeu
+        g[e] = -lam @ Aeu
+    assert np.allclose(acc, P.apply_A(u), atol=1e-12)
+    assert np.allclose(g, P.grad_kappa(u, lam), atol=1e-12)
