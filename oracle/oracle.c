@@ -614,11 +614,13 @@ static int build_blocks(or_problem *P) {
  * m, is: the coarse nodes of a level are its odd-indexed interior nodes
  * (0-based) in every direction, P is linear interpolation between them (the
  * boundary value being zero), the coarse operator is the Galerkin product
- * P^T A P, and coarsening continues down to one node per direction, which is
- * solved exactly.  For m a power of two this is standard full coarsening of
- * the uniform mesh (and P^T A P equals rediscretisation for kappa = 1); for
- * other m the last coarse cell next to the boundary is narrower.
+ * P^T A P, and coarsening stops at the first level with at most
+ * OR_COARSEST_MAX unknowns, which is solved exactly.  For m a power of two
+ * this is standard full coarsening of the uniform mesh (and P^T A P equals
+ * rediscretisation for kappa = 1); for other m the last coarse cell next to
+ * the boundary is narrower.
  */
+#define OR_COARSEST_MAX 512
 static double interp_weight(int i_fine, int I_coarse) {
     /* fine interior node i sits at grid node i+1, coarse node I at fine grid
      * node 2(I+1), i.e. fine interior index 2I+1 */
@@ -631,7 +633,7 @@ static double interp_weight(int i_fine, int I_coarse) {
 static int build_levels(or_problem *P) {
     int d = P->d;
     int nl = 1, nn = P->m - 1;
-    while (nn > 1) { nn /= 2; nl++; }
+    while (ipow(nn, d) > OR_COARSEST_MAX) { nn /= 2; nl++; }
     P->nlev = nl;
     P->lev = calloc(nl, sizeof(or_level));
     long W3 = ipow(3, d);

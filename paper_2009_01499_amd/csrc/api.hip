@@ -89,8 +89,10 @@ void set_device(const Problem &P) { IGA2L_HIP(hipSetDevice(P.device)); }
 // one Schwarz sweep on A e = rhs in working precision (COLOUR ordering).
 // e_zero: e is zero on entry (its buffer content is ignored).  Returns the
 // buffer index (0/1 of P.ework) holding the result; start = buffer holding e.
+// r64 != null: the first colour also casts r64/sigma into rhs (FP32 sweeps from zero)
 template <class T>
-int sweep_colour(const Problem &P, int s_period, const T *rhs, int start, bool e_zero, hipStream_t s) {
+int sweep_colour(const Problem &P, int s_period, T *rhs, int start, bool e_zero, hipStream_t s,
+                 const double *r64 = nullptr) {
     const int S = s_period;
     const int ncz = (P.dim == 3) ? S : 1;
     int cur = start;
@@ -98,7 +100,9 @@ int sweep_colour(const Problem &P, int s_period, const T *rhs, int start, bool e
     for (int cz = 0; cz < ncz; ++cz)
         for (int cy = 0; cy < S; ++cy)
             for (int cx = 0; cx < S; ++cx) {
-                launch_colour_step<T>(P, cx, cy, cz, S, P.ework[cur].as<T>(), P.ework[1 - cur].as<T>(), rhs, zero, s);
+                const bool fuse = zero && r64;
+                launch_colour_step<T>(P, cx, cy, cz, S, P.ework[cur].as<T>(), P.ework[1 - cur].as<T>(), rhs, zero, s,
+                                      fuse ? r64 : nullptr, fuse ? rhs : nullptr);
                 cur = 1 - cur;
                 zero = false;
             }
@@ -125,17 +129,19 @@ void coarse_solve(Problem &P, const iga2l_opts &o, const T *dc, T *ec, hipStream
 // norm-carrying residual; performs u += sigma * cycle(0; r64 / sigma).
 template <class T>
 void correction_cycle(Problem &P, const iga2l_opts &o, double *u, hipStream_t s) {
-    const T *rhs;
+    T *rhs;
+    const double *fuse_r64 = nullptr;
     if constexpr (std::is_same<T, double>::value) {
         rhs = P.r64.as<double>();
     } else {
-        launch_cast_scale<T>(P, P.r64.as<double>(), P.rhs_w.as<T>(), s);
         rhs = P.rhs_w.as<T>();
+        if (o.ordering == IGA2L_COLOUR) fuse_r64 = P.r64.as<double>();  // cast inside the first colour
+        else launch_cast_scale<T>(P, P.r64.as<double>(), rhs, s);
     }
     int cur = 0;
     if (o.ordering == IGA2L_COLOUR) {
         const int S = o.colour_period ? o.colour_period : P.bw;
-        cur = sweep_colour<T>(P, S, rhs, 0, true, s);
+        cur = sweep_colour<T>(P, S, rhs, 0, true, s, fuse_r64);
     } else {
         // lexicographic: FP64 only, in place on a zeroed correction
         launch_fill_zero(P.ework[0].ptr, P.fine.n, false, s, P.skip);

@@ -13,6 +13,9 @@
 namespace iga2l {
 
 constexpr int kMaxDim = 3;
+// the V-cycle hierarchy stops at the first level with at most this many
+// unknowns; that level is solved exactly
+constexpr int64_t kCoarsestMax = 512;
 constexpr int kMaxP = 8;
 
 // -------------------------------------------------------------- errors --
@@ -89,6 +92,7 @@ struct SymDia {
 struct Level {
     Grid g;
     DevBuf S64, S32, invd64, invd32;
+    DevBuf Zinv64, Zinv32;       // coarsest level only: dense inverse [n][n]
     DevBuf e[2], rhs, res;       // working vectors, sized for FP64 (FP32 reuses them)
     bool cst = false;            // translation-invariant stencil (interior row everywhere)
 };
@@ -101,6 +105,7 @@ struct LevelDev {
     int64_t n;
     const T *S;       // [3^d][n]
     const T *invd;    // [n]
+    const T *Zinv;    // coarsest level: dense inverse [n][n], else null
     T c[27];          // interior stencil (cst only)
     T cinv;           // 1 / centre coefficient (cst only)
 };
@@ -200,9 +205,11 @@ template <class T>
 void launch_defect(const Problem &P, const T *e, const T *rhs, T *d, hipStream_t s);
 void launch_solve_init(const Problem &P, double tol, int max_cycles, hipStream_t s);
 int64_t residual_workgroups(const Problem &P);   // partial sums written by the FP64 residual
+// one colour of the Schwarz sweep; r64/rhs_out: fused FP32 cast of the residual
+// (first colour of an FP32 correction sweep only)
 template <class T>
 void launch_colour_step(const Problem &P, int cx, int cy, int cz, int s_period, const T *x_src, T *x_dst,
-                        const T *rhs, bool x_zero, hipStream_t s);
+                        const T *rhs, bool x_zero, hipStream_t s, const double *r64 = nullptr, T *rhs_out = nullptr);
 void launch_lex_step(const Problem &P, int step, double *u, const double *b, hipStream_t s);
 template <class T>
 void launch_cast_scale(const Problem &P, const double *r64, T *rhs, hipStream_t s);

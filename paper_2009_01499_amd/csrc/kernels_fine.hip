@@ -152,7 +152,12 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
                                                  int ncls1, const T *__restrict__ x_src, T *__restrict__ x_dst,
                                                  const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz,
                                                  int S, int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo,
-                                                 int uhi, const int *__restrict__ skip) {
+                                                 int uhi, const int *__restrict__ skip,
+                                                 const double *__restrict__ r64, const double *__restrict__ scal,
+                                                 T *__restrict__ rhs_out) {
+    // r64 != null (first colour of an FP32 correction sweep, x_zero): the
+    // right-hand side is r64 / sigma, cast here and stored to rhs_out for the
+    // later colours
     const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     constexpr int BD = cpow(B, D);
     constexpr int HB = (B - 1) / 2;
@@ -187,12 +192,14 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
     const int cx = tx % S, cy = ty % S, cz = (D == 3) ? tz % S : 0;
     const bool in_block = cx < B && cy < B && (D == 2 || cz < B);
     T res = T(0);
+    T cast_rhs = T(0);
     int64_t gi = 0;
     if (mine) {
         gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+        if (r64) cast_rhs = T(r64[gi] * scal[kScalInvSigma]);
         if (in_block) {
             if (x_zero) {
-                res = rhs[gi];
+                res = r64 ? cast_rhs : rhs[gi];
             } else {
                 const int64_t padi =
                     int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
@@ -233,6 +240,7 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
         }
     }
     if (stop) return;
+    if (r64 && mine) rhs_out[gi] = cast_rhs;
     if (t < ntile) rs[t] = res;
     __syncthreads();
     if (!mine) return;
@@ -531,7 +539,7 @@ void defect_dp(const Problem &Pb, const T *e, const T *rhs, T *d, hipStream_t s)
 
 template <int D, int P, int B, class T>
 void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs,
-                   bool x_zero, hipStream_t s) {
+                   bool x_zero, const double *r64, T *rhs_out, hipStream_t s) {
     const int n1 = Pb.fine.n1;
     constexpr int HB = (B - 1) / 2;
     int nbx = Pb.tile_bx, nby = Pb.tile_by, nbz = (D == 3) ? Pb.tile_bz : 1;
@@ -559,21 +567,24 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
                                                   : reinterpret_cast<const T *>(Pb.Inv32.ptr);
     hipLaunchKernelGGL((k_colour<D, P, B, T>), grid, dim3(threads), shm, s, val, Pb.A.npad, Pb.A.pitch[1],
                        Pb.A.pitch[2], n1, inv, Pb.cls_d.as<int>(), Pb.ncls1, x_src, x_dst, rhs, x_zero ? 1 : 0, ox,
-                       oy, oz, S, nbx, nby, nbz, uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip);
+                       oy, oz, S, nbx, nby, nbz, uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, r64,
+                       Pb.scal.as<double>(), rhs_out);
 }
 
 template <int D, int P, class T>
 void colour_dp(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs, bool x_zero,
-               hipStream_t s) {
+               const double *r64, T *rhs_out, hipStream_t s) {
     switch (Pb.bw) {
-        case 1: colour_launch<D, P, 1, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s); break;
-        case 3: colour_launch<D, P, 3, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s); break;
+        case 1: colour_launch<D, P, 1, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s); break;
+        case 3: colour_launch<D, P, 3, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s); break;
         case 5:
-            if constexpr (D == 2) colour_launch<D, P, 5, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s);
+            if constexpr (D == 2)
+                colour_launch<D, P, 5, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s);
             else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
             break;
         case 7:
-            if constexpr (D == 2) colour_launch<D, P, 7, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s);
+            if constexpr (D == 2)
+                colour_launch<D, P, 7, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s);
             else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
             break;
         default: throw Error{IGA2L_EUNSUPPORTED, "block width must be 1, 3, 5 or 7"};
@@ -645,17 +656,18 @@ void launch_solve_init(const Problem &Pb, double tol, int max_cycles, hipStream_
 
 template <class T>
 void launch_colour_step(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs,
-                        bool x_zero, hipStream_t s) {
+                        bool x_zero, hipStream_t s, const double *r64, T *rhs_out) {
+    IGA2L_REQUIRE(!r64 || (x_zero && rhs_out), IGA2L_EINVAL, "fused cast needs a zero iterate and an output");
     if (Pb.dim == 2) {
-        IGA2L_DISPATCH_P2(colour_dp, Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s);
+        IGA2L_DISPATCH_P2(colour_dp, Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s);
     } else {
-        IGA2L_DISPATCH_P3(colour_dp, Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, s);
+        IGA2L_DISPATCH_P3(colour_dp, Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s);
     }
 }
 template void launch_colour_step<double>(const Problem &, int, int, int, int, const double *, double *,
-                                         const double *, bool, hipStream_t);
+                                         const double *, bool, hipStream_t, const double *, double *);
 template void launch_colour_step<float>(const Problem &, int, int, int, int, const float *, float *, const float *,
-                                        bool, hipStream_t);
+                                        bool, hipStream_t, const double *, float *);
 
 void launch_lex_step(const Problem &Pb, int step, double *u, const double *b, hipStream_t s) {
     if (Pb.dim == 2) {

@@ -1,6 +1,7 @@
 // kernels_vcycle.hip -- the degree-1 h-multigrid V(nu1,nu2) cycle of the
 // coarse level (red-black Gauss-Seidel, linear interpolation onto the
-// odd-indexed nodes, Galerkin operators, exact solve on one node per direction).
+// odd-indexed nodes, Galerkin operators, exact solve of the first level with at
+// most kCoarsestMax unknowns by its precomputed dense inverse).
 //
 // Fine levels of the hierarchy run one kernel per full red-black step (tiles
 // with a halo of 2: the red half step is recomputed on the tile's halo ring so
@@ -237,9 +238,8 @@ __global__ void __launch_bounds__(256) k_res_restrict_tiled(LevelDev<T> L, const
 // --------------------------------------------------------------------------
 // The tail of the V-cycle (levels lb .. coarsest) in one workgroup.  Every
 // level's correction and right-hand side live in LDS on a zero-padded grid
-// ((n1+2)^D); the coarsest level has a single node and is solved exactly.
+// ((n1+2)^D); the coarsest level is solved with its dense inverse.
 constexpr int kBottomThreads = 1024;
-constexpr int kBottomMaxPts = 8;  // points per thread and half step
 
 template <int D, class T>
 struct BottomArgs {
@@ -258,10 +258,12 @@ struct BT;
 template <>
 struct BT<2> {
     static constexpr int X = 32, Y = 32, Z = 1;
+    static constexpr int KX = 2, KY = 2, KZ = 1;   // levels up to 64 x 64
 };
 template <>
 struct BT<3> {
     static constexpr int X = 16, Y = 8, Z = 8;
+    static constexpr int KX = 1, KY = 2, KZ = 2;   // levels up to 16 x 16 x 16
 };
 
 template <int D, class T>
@@ -280,6 +282,7 @@ __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, 
     __shared__ T s_cinv[16];
     __shared__ const T *s_S[16];       // per-point stencils / reciprocal diagonals otherwise
     __shared__ const T *s_invd[16];
+    __shared__ const T *s_Zinv;
     __shared__ int64_t s_n[16];
     const int tid = threadIdx.x;
     const int tx = tid % BT<D>::X, ty = (tid / BT<D>::X) % BT<D>::Y, tz = (D == 3) ? tid / (BT<D>::X * BT<D>::Y) : 0;
@@ -290,6 +293,7 @@ __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, 
         s_S[tid] = L.S;
         s_invd[tid] = L.invd;
         s_n[tid] = L.n;
+        if (tid == A.nlev - 1) s_Zinv = L.Zinv;
     }
     if (tid == 0) {
         int acc = 0;
@@ -353,25 +357,36 @@ __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, 
         }
         return acc;
     };
+    // one half step of the given colour on level l: every point of the colour
+    // is updated from the iterate at the start of the half step.  A thread owns
+    // the points (tx + X kx, ty + Y ky, tz + Z kz), kx < KX, ky < KY, kz < KZ
+    // (compile-time slots, so the new values stay in registers).
     auto half = [&](int l, int colour) {
         const int n1 = s_n1[l], cst = s_cst[l];
         const T cinv = s_cinv[l];
         const T *invd = s_invd[l];
         T *e = sm + off_e[l];
         const T *r = sm + off_r[l];
-        T newv[kBottomMaxPts];
-        int where[kBottomMaxPts];
-        int cnt = 0;
-        IGA2L_FOR_POINTS(n1) {
-            if (((x + y + z) & 1) != colour || cnt >= kBottomMaxPts) continue;
-            const int i = (z * n1 + y) * n1 + x;
-            const int c = ((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1;
-            const T id = cst ? cinv : invd[i];
-            newv[cnt] = e[c] + (r[c] - apply(l, cst, e, n1, c, i)) * id;
-            where[cnt++] = c;
+        constexpr int KX = BT<D>::KX, KY = BT<D>::KY, KZ = BT<D>::KZ;
+        T newv[KX * KY * KZ];
+        int where[KX * KY * KZ];
+#pragma unroll
+        for (int k = 0; k < KX * KY * KZ; ++k) {
+            const int x = tx + BT<D>::X * (k % KX), y = ty + BT<D>::Y * ((k / KX) % KY),
+                      z = (D == 3) ? tz + BT<D>::Z * (k / (KX * KY)) : 0;
+            where[k] = -1;
+            if (x < n1 && y < n1 && (D == 2 || z < n1) && ((x + y + z) & 1) == colour) {
+                const int i = (z * n1 + y) * n1 + x;
+                const int c = ((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1;
+                const T id = cst ? cinv : invd[i];
+                newv[k] = e[c] + (r[c] - apply(l, cst, e, n1, c, i)) * id;
+                where[k] = c;
+            }
         }
         __syncthreads();
-        for (int k = 0; k < cnt; ++k) e[where[k]] = newv[k];
+#pragma unroll
+        for (int k = 0; k < KX * KY * KZ; ++k)
+            if (where[k] >= 0) e[where[k]] = newv[k];
         __syncthreads();
     };
 
@@ -411,11 +426,53 @@ __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, 
         }
         __syncthreads();
     }
-    if (tid == 0) {  // coarsest level: one node
-        const int c = (D == 3) ? (1 * 3 + 1) * 3 + 1 : 1 * 3 + 1;
-        sm[off_e[last] + c] = sm[off_r[last] + c] * (s_cst[last] ? s_cinv[last] : s_invd[last][0]);
+    {
+        // coarsest level: e = Z^{-1} r.  The right-hand side is copied to a flat
+        // array; each row's dot product is split into nseg segments handled by
+        // different threads (Z^{-1} is symmetric: row i is read as column i, so
+        // consecutive threads read consecutive words), then summed in LDS.
+        // The residual scratch of level lb is free at this point.
+        const int n1 = s_n1[last];
+        const int n = (D == 3) ? n1 * n1 * n1 : n1 * n1;
+        const int scr_len = (D == 3) ? (s_n1[0] + 2) * (s_n1[0] + 2) * (s_n1[0] + 2) : (s_n1[0] + 2) * (s_n1[0] + 2);
+        int nseg = kBottomThreads / n;
+        if (nseg > (scr_len - n) / n) nseg = (scr_len - n) / n;
+        if (nseg < 1) nseg = 1;
+        const T *r = sm + off_r[last];
+        T *e = sm + off_e[last];
+        T *rflat = scr;
+        T *part = scr + n;
+        for (int i = tid; i < n; i += kBottomThreads) {
+            const int x = i % n1, y = (i / n1) % n1, z = (D == 3) ? i / (n1 * n1) : 0;
+            rflat[i] = r[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1];
+        }
+        __syncthreads();
+        const T *Zi = s_Zinv;
+        const int seg_len = (n + nseg - 1) / nseg;
+        for (int w = tid; w < n * nseg; w += kBottomThreads) {
+            const int i = w % n, sg = w / n;
+            const int j0 = sg * seg_len, j1 = min(n, j0 + seg_len);
+            T acc = T(0);
+#pragma unroll 8
+            for (int j = j0; j < j1; ++j) acc += Zi[int64_t(j) * n + i] * rflat[j];
+            if (nseg == 1) {
+                const int x = i % n1, y = (i / n1) % n1, z = (D == 3) ? i / (n1 * n1) : 0;
+                e[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1] = acc;
+            } else {
+                part[sg * n + i] = acc;
+            }
+        }
+        __syncthreads();
+        if (nseg > 1) {
+            for (int i = tid; i < n; i += kBottomThreads) {
+                T acc = T(0);
+                for (int sg = 0; sg < nseg; ++sg) acc += part[sg * n + i];
+                const int x = i % n1, y = (i / n1) % n1, z = (D == 3) ? i / (n1 * n1) : 0;
+                e[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1] = acc;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int l = last - 1; l >= 0; --l) {
         const int n1 = s_n1[l], n1c = s_n1[l + 1];
         T *e = sm + off_e[l];
@@ -546,10 +603,10 @@ int64_t vcycle_bottom_lds(const Problem &P, size_t lb) {
 // points one thread owns in the bottom kernel (strided 32x32 or 16x8x8 layout)
 bool vcycle_bottom_fits(const Problem &P, size_t lb) {
     const int n1 = P.levels[lb].g.n1;
-    int64_t per;
-    if (P.dim == 2) per = int64_t((n1 + 31) / 32) * ((n1 + 31) / 32);
-    else per = int64_t((n1 + 15) / 16) * ((n1 + 7) / 8) * ((n1 + 7) / 8);
-    return per <= kBottomMaxPts && P.levels.size() - lb <= 16;
+    bool ok;
+    if (P.dim == 2) ok = n1 <= BT<2>::X * BT<2>::KX && n1 <= BT<2>::Y * BT<2>::KY;
+    else ok = n1 <= BT<3>::X * BT<3>::KX && n1 <= BT<3>::Y * BT<3>::KY && n1 <= BT<3>::Z * BT<3>::KZ;
+    return ok && P.levels.size() - lb <= 16;
 }
 
 }  // namespace iga2l

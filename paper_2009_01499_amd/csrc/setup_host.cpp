@@ -359,7 +359,7 @@ void host_build_levels(Problem &P) {
         ops.push_back(std::move(S));
         sizes.push_back(n1);
     }
-    while (sizes.back() > 1) {
+    while (ipow(sizes.back(), d) > kCoarsestMax) {
         const int nf1 = sizes.back(), nc1 = nf1 / 2;
         const int64_t nf = ipow(nf1, d), nc = ipow(nc1, d);
         const std::vector<double> &Sf = ops.back();
@@ -493,6 +493,63 @@ void host_build_levels(Problem &P) {
         }
         h64.cinv = L.cst ? 1.0 / ref[cw] : 0.0;
         h32.cinv = L.cst ? 1.0f / float(ref[cw]) : 0.0f;
+        h64.Zinv = nullptr;
+        h32.Zinv = nullptr;
+        if (l + 1 == ops.size()) {
+            // coarsest level: dense matrix, Cholesky factor, explicit inverse
+            std::vector<double> Z(size_t(n) * n, 0.0);
+            int ix[kMaxDim] = {0, 0, 0}, o[kMaxDim] = {0, 0, 0};
+            for (int64_t i = 0; i < n; ++i) {
+                split(i, d, n1, ix);
+                for (int w = 0; w < W3; ++w) {
+                    split(w, d, 3, o);
+                    bool in = true;
+                    int64_t j = 0;
+                    for (int k = d - 1; k >= 0; --k) {
+                        const int jk = ix[k] + o[k] - 1;
+                        if (jk < 0 || jk >= n1) in = false;
+                        j = j * n1 + jk;
+                    }
+                    if (in) Z[size_t(i) * n + j] = S[size_t(w) * n + i];
+                }
+            }
+            std::vector<double> Lc(Z);  // lower Cholesky factor in place
+            for (int64_t j = 0; j < n; ++j) {
+                double sdiag = Lc[size_t(j) * n + j];
+                for (int64_t k = 0; k < j; ++k) sdiag -= Lc[size_t(j) * n + k] * Lc[size_t(j) * n + k];
+                IGA2L_REQUIRE(sdiag > 0.0, IGA2L_ENUMERIC, "coarsest V-cycle level is not positive definite");
+                const double ljj = std::sqrt(sdiag);
+                Lc[size_t(j) * n + j] = ljj;
+                for (int64_t i = j + 1; i < n; ++i) {
+                    double t = Lc[size_t(i) * n + j];
+                    for (int64_t k = 0; k < j; ++k) t -= Lc[size_t(i) * n + k] * Lc[size_t(j) * n + k];
+                    Lc[size_t(i) * n + j] = t / ljj;
+                }
+            }
+            // columns of Z^{-1}: solve L L^T x = e_c
+            std::vector<double> Zi(size_t(n) * n), col(n);
+            for (int64_t c = 0; c < n; ++c) {
+                for (int64_t i = 0; i < n; ++i) col[i] = (i == c) ? 1.0 : 0.0;
+                for (int64_t i = 0; i < n; ++i) {
+                    double t = col[i];
+                    for (int64_t k = 0; k < i; ++k) t -= Lc[size_t(i) * n + k] * col[k];
+                    col[i] = t / Lc[size_t(i) * n + i];
+                }
+                for (int64_t i = n - 1; i >= 0; --i) {
+                    double t = col[i];
+                    for (int64_t k = i + 1; k < n; ++k) t -= Lc[size_t(k) * n + i] * col[k];
+                    col[i] = t / Lc[size_t(i) * n + i];
+                }
+                for (int64_t i = 0; i < n; ++i) Zi[size_t(i) * n + c] = col[i];
+            }
+            std::vector<float> Zi32(Zi.begin(), Zi.end());
+            L.Zinv64.alloc(Zi.size() * sizeof(double));
+            L.Zinv32.alloc(Zi32.size() * sizeof(float));
+            IGA2L_HIP(hipMemcpy(L.Zinv64.ptr, Zi.data(), Zi.size() * sizeof(double), hipMemcpyHostToDevice));
+            IGA2L_HIP(hipMemcpy(L.Zinv32.ptr, Zi32.data(), Zi32.size() * sizeof(float), hipMemcpyHostToDevice));
+            h64.Zinv = L.Zinv64.as<double>();
+            h32.Zinv = L.Zinv32.as<float>();
+        }
     }
     P.levdev64.alloc(P.levhost64.size() * sizeof(LevelDev<double>));
     P.levdev32.alloc(P.levhost32.size() * sizeof(LevelDev<float>));

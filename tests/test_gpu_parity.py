@@ -111,8 +111,8 @@ def test_transfer_parity(d, p, m):
     assert e < 1e-14, e
 
 
-@pytest.mark.parametrize("d,m,kap", [(2, 32, None), (2, 64, None), (2, 33, "grf"), (2, 27, None), (3, 8, None),
-                                     (3, 7, "grf")])
+@pytest.mark.parametrize("d,m,kap", [(2, 32, None), (2, 64, None), (2, 33, "grf"), (2, 27, None), (2, 128, "grf"),
+                                     (3, 8, None), (3, 16, None), (3, 13, "grf")])
 @pytest.mark.parametrize("nu", [(1, 1), (2, 2), (1, 0)])
 def test_vcycle_parity(d, m, kap, nu):
     kappa = synth.kappa_grf(d, m, 1.0, 0.1, seed=9) if kap else None
