@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--large-m", type=int, default=4096, help="mesh of the bandwidth-regime roofline leg (0: skip)")
+    ap.add_argument("--suite", action="store_true",
+                    help="after the headline line, print one JSON line per other configuration")
     return ap.parse_args()
 
 
@@ -79,6 +82,45 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def roofline_large(torch, G, m, p=3):
+    """Kernels of the path in the bandwidth regime: 2-D p=3 on m x m elements
+    (m=4096: 16.8 M DOFs, every vector 134 MB, above the 256 MB Infinity Cache
+    together).  Algorithmic bytes per launch (kappa = 1, interior stencil in
+    registers): residual 24 B/DOF (u, b read, r written); restriction 8 B per
+    fine DOF read + 8 B per coarse DOF written; prolongation 16 B per fine DOF
+    (u read and written) + 8 B per coarse DOF; one Schwarz colour 24 B/DOF
+    (iterate read and written, right-hand side read).  Averages over many
+    launches, HIP events on the stream the library launches on."""
+    prob = G.Problem(2, p, m, device=0)
+    prob.setup(0, G.Opts(coarse=G.COARSE_DIRECT))
+    n, nc = prob.n, prob.nc
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    u = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+    b = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+    r = torch.empty_like(u)
+    dc = torch.rand(nc, dtype=torch.float64, device="cuda", generator=gen)
+    ec = torch.empty_like(dc)
+    out = {"workload": f"2D p={p} {m}x{m} ({n} fine DOFs, {nc} coarse), kappa=1, FP64"}
+    t = event_time(torch, lambda: prob.residual(u, b, r), 20)
+    out["k_residual"] = _rl(24.0 * n, t)
+    t = event_time(torch, lambda: prob.restrict(r, ec), 20)
+    out["k_restrict"] = _rl(8.0 * n + 8.0 * nc, t)
+    t = event_time(torch, lambda: prob.prolong_add(dc, u), 20)
+    out["k_prolong_add"] = _rl(16.0 * n + 8.0 * nc, t)
+    t = event_time(torch, lambda: prob.smooth(u, b, 1, G.Opts()), 5) / 9.0
+    out["k_colour"] = _rl(24.0 * n, t)
+    prob.close()
+    del u, b, r, dc, ec
+    torch.cuda.empty_cache()
+    return out
+
+
+def _rl(bytes_per_launch, ms):
+    gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "avg_launch_us": ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch}
 
 
 def event_time(torch, fn, reps):
@@ -186,6 +228,8 @@ def main():
         ach_res = bytes_per_dof * n / (ms_res * 1e-3) / 1e9
         out["roofline_residual"] = {"kernel": "k_residual<2,3,double>", "achieved": ach_res, "unit": "GB/s",
                                     "frac": ach_res / HBM_PEAK_GBS, "avg_launch_us": ms_res * 1e3}
+        if args.large_m:
+            out["roofline_large"] = roofline_large(torch, G, args.large_m)
     # ---- CPU oracle leg
     if not args.no_cpu_baseline:
         rec, u_orc = cpu_baseline(d, p, m, b_np, nu, out["cycles"]["mixed"])
@@ -194,7 +238,11 @@ def main():
             nrm = np.linalg.norm(u_orc)
             out["error_vs_oracle"] = {"mixed": float(np.linalg.norm(u_mixed - u_orc) / nrm),
                                       "fp64": float(np.linalg.norm(u_fp64 - u_orc) / nrm)}
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+    if args.suite:
+        import bench_suite
+        for line in bench_suite.run(torch, G, steps=max(3, args.steps // 2)):
+            print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

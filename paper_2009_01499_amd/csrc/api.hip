@@ -139,6 +139,7 @@ void correction_cycle(Problem &P, const iga2l_opts &o, double *u, hipStream_t s)
         else launch_cast_scale<T>(P, P.r64.as<double>(), rhs, s);
     }
     int cur = 0;
+    if (o.ordering == IGA2L_LEX && P.lex_off.empty()) host_lex_schedule(P);
     if (o.ordering == IGA2L_COLOUR) {
         const int S = o.colour_period ? o.colour_period : P.bw;
         cur = sweep_colour<T>(P, S, rhs, 0, true, s, fuse_r64);
@@ -351,7 +352,7 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             IGA2L_HIP(hipMemcpy(P.cls_d.ptr, cls1.data(), cls1.size() * sizeof(int), hipMemcpyHostToDevice));
             P.Inv64.alloc(size_t(P.nslots) * P.bd * P.bd * sizeof(double));
             launch_block_inverse(P, reps, s);
-            host_lex_schedule(P);
+            P.lex_off.clear();   // the lexicographic schedule is built on first use
             P.blocks_ready = true;
         }
         check_opts(P, o);
@@ -409,6 +410,7 @@ int iga2l_smooth(const iga2l_problem *prob, double *u, const double *b, int nswe
         set_device(P);
         hipStream_t s = static_cast<hipStream_t>(stream);
         const size_t bytes = sizeof(double) * size_t(P.fine.n);
+        if (o.ordering == IGA2L_LEX && P.lex_off.empty()) host_lex_schedule(P);
         for (int k = 0; k < nsweeps; ++k) {
             if (o.ordering == IGA2L_LEX) {
                 for (size_t st = 0; st + 1 < P.lex_off.size(); ++st) launch_lex_step(P, int(st), u, b, s);

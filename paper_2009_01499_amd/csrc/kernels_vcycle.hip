@@ -157,6 +157,112 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
     }
 }
 
+// --------------------------------------------------------------------------
+// NU full red-black steps on a 2-D level in one launch.  The tile of TX x TY
+// points is loaded with a halo of H = 2 NU (+2 when RESTRICT); half step j
+// updates the points of colour (j & 1) within halo H-1-j from the iterate at
+// the start of the half step (two LDS buffers, one barrier per half step), so
+// after 2 NU half steps the tile (and, with RESTRICT, a ring of 2 around it)
+// holds the smoothed iterate.  The input is (zero_src ? 0 : e_src) + P ec.
+// RESTRICT: additionally rc[I] = (P^T (rhs - A e))[I] for the coarse points I
+// whose centre child 2I+1 lies in the tile.
+template <class T, int NU, bool RESTRICT>
+__global__ void __launch_bounds__(256) k_rb_multi2(LevelDev<T> L, const T *__restrict__ e_src, int zero_src,
+                                                   const T *__restrict__ ec, int n1c_interp,
+                                                   const T *__restrict__ rhs, T *__restrict__ e_dst,
+                                                   T *__restrict__ rc, int n1c, const int *__restrict__ skip) {
+    constexpr int TX = 32, TY = 8;
+    constexpr int H = 2 * NU + (RESTRICT ? 2 : 0);
+    constexpr int HX = TX + 2 * H, HY = TY + 2 * H, NH = HX * HY;
+    __shared__ T buf[2][NH];
+    __shared__ T rs[NH];
+    const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
+    const int n1 = L.n1;
+    const int gx0 = blockIdx.x * TX, gy0 = blockIdx.y * TY;
+    for (int h = threadIdx.x; h < NH; h += blockDim.x) {
+        const int hx = h % HX, hy = h / HX;
+        const int gx = gx0 + hx - H, gy = gy0 + hy - H;
+        T v = T(0), f = T(0);
+        if (gx >= 0 && gx < n1 && gy >= 0 && gy < n1) {
+            const int64_t gi = int64_t(gy) * n1 + gx;
+            if (!zero_src) v = e_src[gi];
+            if (ec) v += interp_value<2, T>(ec, n1c_interp, gx, gy, 0);
+            f = rhs[gi];
+        }
+        buf[0][h] = v;
+        rs[h] = f;
+    }
+    __syncthreads();
+    int cur = 0;
+#pragma unroll
+    for (int j = 0; j < 2 * NU; ++j) {
+        const int colour = j & 1, halo = H - 1 - j;
+        const T *X = buf[cur];
+        T *Y = buf[1 - cur];
+        for (int h = threadIdx.x; h < NH; h += blockDim.x) {
+            const int hx = h % HX, hy = h / HX;
+            if (hx < H - halo || hx >= HX - (H - halo) || hy < H - halo || hy >= HY - (H - halo)) continue;
+            const int gx = gx0 + hx - H, gy = gy0 + hy - H;
+            T v = X[h];
+            if (gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && ((gx + gy) & 1) == colour) {
+                const int64_t gi = int64_t(gy) * n1 + gx;
+                T acc = T(0);
+#pragma unroll
+                for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+                    for (int ox = -1; ox <= 1; ++ox)
+                        acc += coef<2, T>(L, gi, w_of<2>(ox, oy, 0)) * X[h + oy * HX + ox];
+                v = X[h] + (rs[h] - acc) * inv_diag<2, T>(L, gi);
+            }
+            Y[h] = v;
+        }
+        cur = 1 - cur;
+        __syncthreads();
+    }
+    if (stop) return;
+    const T *E = buf[cur];
+    if constexpr (RESTRICT) {
+        // residual on the fine points gx0..gx0+TX, gy0..gy0+TY, kept in the free buffer
+        T *R = buf[1 - cur];
+        for (int f = threadIdx.x; f < (TX + 1) * (TY + 1); f += blockDim.x) {
+            const int fx = f % (TX + 1), fy = f / (TX + 1);
+            const int gx = gx0 + fx, gy = gy0 + fy;
+            const int h = (fy + H) * HX + (fx + H);
+            T r = T(0);
+            if (gx < n1 && gy < n1) {
+                const int64_t gi = int64_t(gy) * n1 + gx;
+                T acc = T(0);
+#pragma unroll
+                for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+                    for (int ox = -1; ox <= 1; ++ox) acc += coef<2, T>(L, gi, w_of<2>(ox, oy, 0)) * E[h + oy * HX + ox];
+                r = rs[h] - acc;
+            }
+            R[f] = r;
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < (TX / 2) * (TY / 2); c += blockDim.x) {
+            const int cx = c % (TX / 2), cy = c / (TX / 2);
+            const int I = gx0 / 2 + cx, J = gy0 / 2 + cy;
+            if (I >= n1c || J >= n1c) continue;
+            T acc = T(0);
+#pragma unroll
+            for (int ay = -1; ay <= 1; ++ay)
+#pragma unroll
+                for (int ax = -1; ax <= 1; ++ax) {
+                    const T w = (ax == 0 ? T(1) : T(0.5)) * (ay == 0 ? T(1) : T(0.5));
+                    acc += w * R[(2 * cy + 1 + ay) * (TX + 1) + (2 * cx + 1 + ax)];
+                }
+            rc[int64_t(J) * n1c + I] = acc;
+        }
+    }
+    for (int t = threadIdx.x; t < TX * TY; t += blockDim.x) {
+        const int tx = t % TX, ty = t / TX;
+        const int gx = gx0 + tx, gy = gy0 + ty;
+        if (gx < n1 && gy < n1) e_dst[int64_t(gy) * n1 + gx] = E[(ty + H) * HX + (tx + H)];
+    }
+}
+
 // e_dst = e_src + P ec (used only when no post-smoothing step follows)
 template <int D, class T>
 __global__ void k_interp_add2(const T *__restrict__ e_src, int zero_src, const T *__restrict__ ec, int n1c, int n1,
@@ -528,6 +634,47 @@ LevelDev<T> levhost(const Problem &P, size_t l) {
     else return P.levhost32[l];
 }
 
+template <int D, class T>
+void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, hipStream_t s);
+
+template <class T, int NU, bool RESTRICT>
+void launch_rb_multi2(const Problem &P, const LevelDev<T> &Ld, const T *e_src, bool zero_src, const T *ec,
+                      int n1c_interp, const T *rhs, T *e_dst, T *rc, int n1c, hipStream_t s) {
+    const dim3 grid(nblk(Ld.n1, 32), nblk(Ld.n1, 8), 1);
+    hipLaunchKernelGGL((k_rb_multi2<T, NU, RESTRICT>), grid, dim3(256), 0, s, Ld, e_src, zero_src ? 1 : 0, ec,
+                       n1c_interp, rhs, e_dst, rc, n1c, P.skip);
+}
+
+template <class T, bool RESTRICT>
+void rb_multi2(const Problem &P, int nu, const LevelDev<T> &Ld, const T *e_src, bool zero_src, const T *ec,
+               int n1c_interp, const T *rhs, T *e_dst, T *rc, int n1c, hipStream_t s) {
+    switch (nu) {
+        case 0: launch_rb_multi2<T, 0, RESTRICT>(P, Ld, e_src, zero_src, ec, n1c_interp, rhs, e_dst, rc, n1c, s); break;
+        case 1: launch_rb_multi2<T, 1, RESTRICT>(P, Ld, e_src, zero_src, ec, n1c_interp, rhs, e_dst, rc, n1c, s); break;
+        case 2: launch_rb_multi2<T, 2, RESTRICT>(P, Ld, e_src, zero_src, ec, n1c_interp, rhs, e_dst, rc, n1c, s); break;
+        case 3: launch_rb_multi2<T, 3, RESTRICT>(P, Ld, e_src, zero_src, ec, n1c_interp, rhs, e_dst, rc, n1c, s); break;
+        case 4: launch_rb_multi2<T, 4, RESTRICT>(P, Ld, e_src, zero_src, ec, n1c_interp, rhs, e_dst, rc, n1c, s); break;
+        default: throw Error{IGA2L_EUNSUPPORTED, "fused red-black steps support nu <= 4"};
+    }
+}
+
+// 2-D top level: pre-smoothing + residual + restriction in one launch, the
+// coarser levels, then prolongation + post-smoothing in one launch
+template <class T>
+void vcycle_top_fused2(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, hipStream_t s) {
+    Level &L = P.levels[l];
+    Level &C = P.levels[l + 1];
+    const LevelDev<T> Ld = levhost<T>(P, l);
+    const int n1c = C.g.n1;
+    T *epre = L.e[0].as<T>();
+    T *rc = C.rhs.as<T>();
+    T *ecl = C.res.as<T>();
+    rb_multi2<T, true>(P, nu1, Ld, static_cast<const T *>(nullptr), true, static_cast<const T *>(nullptr), 0, rhs,
+                       epre, rc, n1c, s);
+    vcycle_top<2, T>(P, l + 1, rc, ecl, nu1, nu2, s);
+    rb_multi2<T, false>(P, nu2, Ld, epre, nu1 == 0, ecl, n1c, rhs, e_out, static_cast<T *>(nullptr), 0, s);
+}
+
 // V-cycle from zero on level l of the multi-workgroup part; result in e_out
 template <int D, class T>
 void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, hipStream_t s) {
@@ -544,6 +691,12 @@ void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, 
     Level &C = P.levels[l + 1];
     const LevelDev<T> Ld = levhost<T>(P, l);
     const int n1 = L.g.n1, n1c = C.g.n1;
+    if constexpr (D == 2) {
+        if (nu1 <= 4 && nu2 <= 4 && nu2 >= 1) {
+            vcycle_top_fused2<T>(P, l, rhs, e_out, nu1, nu2, s);
+            return;
+        }
+    }
     using TS = VT<D>;
     const dim3 sgrid(nblk(n1, TS::TX), nblk(n1, TS::TY), D == 3 ? nblk(n1, TS::TZ) : 1);
     const dim3 rgrid(nblk(n1c, TS::CX), nblk(n1c, TS::CY), D == 3 ? nblk(n1c, TS::CZ) : 1);

@@ -201,7 +201,36 @@ void host_assemble(Problem &P) {
     const int nl = p + 1;
     const int64_t nloc = ipow(nl, d);
     int e[kMaxDim] = {0, 0, 0}, a[kMaxDim] = {0, 0, 0}, b[kMaxDim] = {0, 0, 0};
-    for (int64_t el = 0; el < P.ne; ++el) {
+    if (P.kappa_one) {
+        // kappa = 1: A = sum_c (x)_k (k == c ? K1 : M1), entry by entry from the
+        // assembled 1-D factors (O(n Wh) instead of the element loop)
+        int ix[kMaxDim] = {0, 0, 0}, o[kMaxDim] = {0, 0, 0};
+        for (int64_t i = 0; i < P.fine.n; ++i) {
+            split(i, d, n1, ix);
+            int64_t padi = 0;
+            for (int k = 0; k < d; ++k) padi += int64_t(ix[k] + p) * A.pitch[k];
+            for (int w = c0; w < A.W; ++w) {
+                split(w, d, w1, o);
+                bool in = true;
+                for (int k = 0; k < d; ++k) {
+                    const int j = ix[k] + o[k] - p;
+                    if (j < 0 || j >= n1) in = false;
+                }
+                if (!in) continue;
+                double term = 0.0;
+                for (int c = 0; c < d; ++c) {
+                    double prod = 1.0;
+                    for (int k = 0; k < d; ++k) {
+                        const std::vector<double> &F = (k == c) ? P.K1 : P.M1;
+                        prod *= F[size_t(ix[k]) * w1 + o[k]];
+                    }
+                    term += prod;
+                }
+                val[size_t(w - c0) * A.npad + padi] = term;
+            }
+        }
+    }
+    for (int64_t el = 0; el < (P.kappa_one ? 0 : P.ne); ++el) {
         split(el, d, m, e);
         const double kap = P.kappa_one ? 1.0 : P.kappa[el];
         for (int64_t la = 0; la < nloc; ++la) {
