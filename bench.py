@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--large-m", type=int, default=4096, help="mesh of the bandwidth-regime roofline leg (0: skip)")
     ap.add_argument("--suite", action="store_true",
                     help="after the headline line, print one JSON line per other configuration")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the bandwidth-regime roofline leg (for hardware-counter profiles)")
     return ap.parse_args()
 
 
@@ -111,6 +113,12 @@ def roofline_large(torch, G, m, p=3):
     out["k_prolong_add"] = _rl(16.0 * n + 8.0 * nc, t)
     t = event_time(torch, lambda: prob.smooth(u, b, 1, G.Opts()), 5) / 9.0
     out["k_colour"] = _rl(24.0 * n, t)
+    # a plain device copy of one vector: calibrates byte counters (FETCH_SIZE /
+    # WRITE_SIZE of this kernel against its known 8n bytes each way)
+    v = torch.empty_like(u)
+    t = event_time(torch, lambda: v.copy_(u), 20)
+    out["copy_reference"] = _rl(16.0 * n, t)
+    del v
     prob.close()
     del u, b, r, dc, ec
     torch.cuda.empty_cache()
@@ -148,6 +156,9 @@ def main():
     import paper_2009_01499_amd as G
     import synth
 
+    if args.only_large:
+        print(json.dumps({"roofline_large": roofline_large(torch, G, args.large_m)}), flush=True)
+        return
     d, p, m = 2, args.p, args.m
     nu = (2, 2)
     b_np = synth.rhs_normal(d, p, m, seed=0)

@@ -213,6 +213,14 @@ void launch_colour_step(const Problem &P, int cx, int cy, int cz, int s_period, 
 void launch_lex_step(const Problem &P, int step, double *u, const double *b, hipStream_t s);
 template <class T>
 void launch_cast_scale(const Problem &P, const double *r64, T *rhs, hipStream_t s);
+// 2-D bandwidth-oriented variants (kernels_2d.hip)
+template <class T>
+void launch_residual2d(const Problem &P, const T *val, const T *x, const T *b, T *r, double *partial, hipStream_t s);
+int64_t residual2d_workgroups(const Problem &P);
+template <class T>
+void launch_restrict2d(const Problem &P, const T *df, T *dc, hipStream_t s);
+template <class T>
+void launch_prolong2d(const Problem &P, const T *ec, T *uf, const T *e, double *u64, bool scaled, hipStream_t s);
 // transfers
 template <class T>
 void launch_restrict(const Problem &P, const T *df, T *dc, hipStream_t s);

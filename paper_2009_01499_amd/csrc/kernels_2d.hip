@@ -1,0 +1,318 @@
+// kernels_2d.hip -- bandwidth-oriented 2-D kernels of the two-level cycle:
+// the wide-band residual with register blocking along y, and the restriction
+// and prolongation as two 1-D passes (the transfer is R1 (x) R1, so a coarse
+// value needs p+2 taps per direction instead of (p+2)^2 gathers).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "internal.h"
+
+namespace iga2l {
+
+namespace {
+
+inline unsigned nblk(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+
+
+// ------------------------------------------------------------------------
+// r = b - A x on tiles of 64 x (4*RY) points.  Each thread owns a column of
+// RY consecutive points (x fixed); the LDS rows it needs are read once into
+// registers and reused by every output of the column they touch.  Tiles whose
+// rows all carry the interior stencil (kappa = 1) take it from cs; other tiles
+// read the diagonals of the symmetric padded-diagonal operator.
+constexpr int kResTX = 64, kResTYT = 4, kResRY = 8;
+
+template <int P, class T, bool NORM>
+__global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d(const T *__restrict__ val, int64_t npad, int pitch1,
+                                                                int n1, const T *__restrict__ x,
+                                                                const T *__restrict__ b, T *__restrict__ r,
+                                                                double *__restrict__ partial,
+                                                                const T *__restrict__ cs, int ulo, int uhi,
+                                                                const int *__restrict__ skip) {
+    constexpr int TX = kResTX, TY = kResTYT * kResRY, RY = kResRY;
+    constexpr int HX = TX + 2 * P, HY = TY + 2 * P;
+    constexpr int W1 = 2 * P + 1, W = W1 * W1, C0 = (W - 1) / 2;
+    __shared__ T xs[HX * HY];
+    const int stop = skip ? *skip : 0;
+    const int gx0 = blockIdx.x * TX, gy0 = blockIdx.y * TY;
+    for (int h = threadIdx.x; h < HX * HY; h += blockDim.x) {
+        const int hx = h % HX, hy = h / HX;
+        const int gx = gx0 + hx - P, gy = gy0 + hy - P;
+        xs[h] = (gx >= 0 && gx < n1 && gy >= 0 && gy < n1) ? x[int64_t(gy) * n1 + gx] : T(0);
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int gx = gx0 + tx, gyb = gy0 + ty * RY;
+    const bool uni = cs != nullptr && gx0 >= ulo && min(gx0 + TX, n1) - 1 <= uhi && gy0 >= ulo &&
+                     min(gy0 + TY, n1) - 1 <= uhi;
+    T acc[RY];
+#pragma unroll
+    for (int k = 0; k < RY; ++k) acc[k] = T(0);
+    if (uni) {
+        // row yy of the column window (0 .. RY+2P-1) feeds output k with oy = yy - P - k
+#pragma unroll
+        for (int yy = 0; yy < RY + 2 * P; ++yy) {
+            T v[W1];
+#pragma unroll
+            for (int ox = 0; ox < W1; ++ox) v[ox] = xs[(ty * RY + yy) * HX + tx + ox];
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                const int oy = yy - k;  // 0 .. 2P when the row touches output k
+                if (oy >= 0 && oy < W1) {
+#pragma unroll
+                    for (int ox = 0; ox < W1; ++ox) acc[k] += cs[oy * W1 + ox] * v[ox];
+                }
+            }
+        }
+    } else if (gx < n1) {
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int gy = gyb + k;
+            if (gy >= n1) continue;
+            const int64_t padi = int64_t(gx + P) + int64_t(gy + P) * pitch1;
+#pragma unroll
+            for (int oy = 0; oy < W1; ++oy)
+#pragma unroll
+                for (int ox = 0; ox < W1; ++ox) {
+                    const int w = oy * W1 + ox;
+                    const T a = (w >= C0) ? val[int64_t(w - C0) * npad + padi]
+                                          : val[int64_t(C0 - w) * npad + padi + (ox - P) + int64_t(oy - P) * pitch1];
+                    acc[k] += a * xs[(ty * RY + k + oy) * HX + tx + ox];
+                }
+        }
+    }
+    if (stop) return;
+    double rr = 0.0;
+    if (gx < n1) {
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int gy = gyb + k;
+            if (gy < n1) {
+                const int64_t gi = int64_t(gy) * n1 + gx;
+                const T res = b[gi] - acc[k];
+                r[gi] = res;
+                rr += double(res) * double(res);
+            }
+        }
+    }
+    if constexpr (NORM) {
+        __shared__ double red[kResTX * kResTYT / 64];
+        for (int off = 32; off > 0; off >>= 1) rr += __shfl_down(rr, off, 64);
+        if ((threadIdx.x % 64) == 0) red[threadIdx.x / 64] = rr;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int k = 0; k < int(blockDim.x / 64); ++k) s += red[k];
+            partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// d_c = (R1 (x) R1) d on tiles of CX x CY coarse points.  Coarse I uses fine
+// I-1 .. I+p per direction.  Pass 1 (x): t[row][I] for every fine row of the
+// window; pass 2 (y): d_c[J][I].  The 1-D factor rows of the tile are staged.
+// transfer tiles: 64 x 16 on large grids, 32 x 8 where that would leave the
+// device under-occupied
+inline void transfer_tile(int64_t n1, int &tx, int &ty) {
+    if (n1 >= 1024) { tx = 64; ty = 16; }
+    else { tx = 32; ty = 8; }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_restrict2d(const T *__restrict__ R1, int p, int n1f, int n1c,
+                                                    const T *__restrict__ df, T *__restrict__ dc,
+                                                    const int *__restrict__ skip, int CX, int CY) {
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    const int w = p + 2;
+    const int FX = CX + p + 1, FY = CY + p + 1;        // fine window (I0-1 .. I0+CX-1+p)
+    T *ds = sm;                                          // [FY][FX]
+    T *ts = ds + FX * FY;                                // [FY][CX]
+    T *rx = ts + FY * CX;                                // [CX][w]
+    T *ry = rx + CX * w;                                 // [CY][w]
+    const int stop = skip ? *skip : 0;
+    const int I0 = blockIdx.x * CX, J0 = blockIdx.y * CY;
+    for (int h = threadIdx.x; h < FX * FY; h += blockDim.x) {
+        const int hx = h % FX, hy = h / FX;
+        const int jx = I0 - 1 + hx, jy = J0 - 1 + hy;
+        ds[h] = (jx >= 0 && jx < n1f && jy >= 0 && jy < n1f) ? df[int64_t(jy) * n1f + jx] : T(0);
+    }
+    for (int h = threadIdx.x; h < CX * w; h += blockDim.x) {
+        const int I = I0 + h / w;
+        rx[h] = (I < n1c) ? R1[int64_t(I) * w + h % w] : T(0);
+    }
+    for (int h = threadIdx.x; h < CY * w; h += blockDim.x) {
+        const int J = J0 + h / w;
+        ry[h] = (J < n1c) ? R1[int64_t(J) * w + h % w] : T(0);
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < FY * CX; h += blockDim.x) {
+        const int cx = h % CX, fy = h / CX;
+        T acc = T(0);
+        for (int a = 0; a < w; ++a) acc += rx[cx * w + a] * ds[fy * FX + cx + a];
+        ts[fy * CX + cx] = acc;
+    }
+    __syncthreads();
+    if (stop) return;
+    for (int h = threadIdx.x; h < CX * CY; h += blockDim.x) {
+        const int cx = h % CX, cy = h / CX;
+        const int I = I0 + cx, J = J0 + cy;
+        if (I >= n1c || J >= n1c) continue;
+        T acc = T(0);
+        for (int bb = 0; bb < w; ++bb) acc += ry[cy * w + bb] * ts[(cy + bb) * CX + cx];
+        dc[int64_t(J) * n1c + I] = acc;
+    }
+}
+
+// ------------------------------------------------------------------------
+// (R1 (x) R1)^T e_c on tiles of TX x TY fine points; fine i takes coarse
+// I = i-p .. i+1 with weight R1[I][i-I+1].  mode 0: uf += P e_c;  mode 1:
+// u64 += sigma (e + P e_c) (end of a correction cycle; sigma from scal when
+// scaled).
+template <class T>
+__global__ void __launch_bounds__(256) k_prolong2d(const T *__restrict__ R1, int p, int n1f, int n1c,
+                                                   const T *__restrict__ ec, T *__restrict__ uf, int mode,
+                                                   const T *__restrict__ e, double *__restrict__ u64,
+                                                   const double *__restrict__ scal, int scaled,
+                                                   const int *__restrict__ skip, int TX, int TY) {
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    const int w = p + 2;
+    const int KX = TX + p + 1, KY = TY + p + 1;   // coarse window I0-p .. I0+TX
+    T *es = sm;                                    // [KY][KX]
+    T *ts = es + KX * KY;                          // [KY][TX]
+    T *rx = ts + KY * TX;                          // [KX][w] rows of the coarse columns
+    T *ry = rx + KX * w;                           // [KY][w]
+    const int stop = skip ? *skip : 0;
+    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    for (int h = threadIdx.x; h < KX * KY; h += blockDim.x) {
+        const int hx = h % KX, hy = h / KX;
+        const int Ix = i0 - p + hx, Iy = j0 - p + hy;
+        es[h] = (Ix >= 0 && Ix < n1c && Iy >= 0 && Iy < n1c) ? ec[int64_t(Iy) * n1c + Ix] : T(0);
+    }
+    for (int h = threadIdx.x; h < KX * w; h += blockDim.x) {
+        const int I = i0 - p + h / w;
+        rx[h] = (I >= 0 && I < n1c) ? R1[int64_t(I) * w + h % w] : T(0);
+    }
+    for (int h = threadIdx.x; h < KY * w; h += blockDim.x) {
+        const int I = j0 - p + h / w;
+        ry[h] = (I >= 0 && I < n1c) ? R1[int64_t(I) * w + h % w] : T(0);
+    }
+    __syncthreads();
+    // x pass: ts[row][tx] = sum over the coarse columns kx = tx .. tx+p+1 of
+    // R1[kx][tx - kx + p + 1] es[row][kx]  (fine i = i0+tx, coarse I = i0-p+kx)
+    for (int h = threadIdx.x; h < KY * TX; h += blockDim.x) {
+        const int tx = h % TX, row = h / TX;
+        T acc = T(0);
+        for (int q = 0; q < w; ++q) {
+            const int kx = tx + q;
+            acc += rx[kx * w + (p + 1 - q)] * es[row * KX + kx];
+        }
+        ts[row * TX + tx] = acc;
+    }
+    __syncthreads();
+    if (stop) return;
+    for (int h = threadIdx.x; h < TX * TY; h += blockDim.x) {
+        const int tx = h % TX, ty = h / TX;
+        const int i = i0 + tx, j = j0 + ty;
+        if (i >= n1f || j >= n1f) continue;
+        T acc = T(0);
+        for (int q = 0; q < w; ++q) {
+            const int ky = ty + q;
+            acc += ry[ky * w + (p + 1 - q)] * ts[ky * TX + tx];
+        }
+        const int64_t gi = int64_t(j) * n1f + i;
+        if (mode == 0) {
+            uf[gi] += acc;
+        } else {
+            const T corr = e[gi] + acc;
+            u64[gi] += scaled ? scal[kScalSigma] * double(corr) : double(corr);
+        }
+    }
+}
+
+template <class T>
+const T *R1_of(const Problem &P) {
+    return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.R1d64.ptr)
+                                          : reinterpret_cast<const T *>(P.R1d32.ptr);
+}
+
+template <class T>
+const T *cs_of(const Problem &P) {
+    return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.cs64.ptr)
+                                          : reinterpret_cast<const T *>(P.cs32.ptr);
+}
+
+template <int P, class T, bool NORM>
+void res2d_launch(const Problem &Pb, const T *val, const T *x, const T *b, T *r, double *partial, hipStream_t s) {
+    const int n1 = Pb.fine.n1;
+    const dim3 grid(nblk(n1, kResTX), nblk(n1, kResTYT * kResRY));
+    hipLaunchKernelGGL((k_residual2d<P, T, NORM>), grid, dim3(kResTX * kResTYT), 0, s, val, Pb.A.npad,
+                       Pb.A.pitch[1], n1, x, b, r, partial, cs_of<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip);
+}
+
+template <class T, bool NORM>
+void res2d_dispatch(const Problem &Pb, const T *val, const T *x, const T *b, T *r, double *partial, hipStream_t s) {
+    switch (Pb.p) {
+        case 1: res2d_launch<1, T, NORM>(Pb, val, x, b, r, partial, s); break;
+        case 2: res2d_launch<2, T, NORM>(Pb, val, x, b, r, partial, s); break;
+        case 3: res2d_launch<3, T, NORM>(Pb, val, x, b, r, partial, s); break;
+        case 4: res2d_launch<4, T, NORM>(Pb, val, x, b, r, partial, s); break;
+        case 5: res2d_launch<5, T, NORM>(Pb, val, x, b, r, partial, s); break;
+        case 6: res2d_launch<6, T, NORM>(Pb, val, x, b, r, partial, s); break;
+        case 7: res2d_launch<7, T, NORM>(Pb, val, x, b, r, partial, s); break;
+        case 8: res2d_launch<8, T, NORM>(Pb, val, x, b, r, partial, s); break;
+        default: throw Error{IGA2L_EUNSUPPORTED, "degree out of range"};
+    }
+}
+
+}  // namespace
+
+int64_t residual2d_workgroups(const Problem &P) {
+    const int64_t n1 = P.fine.n1;
+    return ((n1 + kResTX - 1) / kResTX) * ((n1 + kResTYT * kResRY - 1) / (kResTYT * kResRY));
+}
+
+template <class T>
+void launch_residual2d(const Problem &P, const T *val, const T *x, const T *b, T *r, double *partial,
+                       hipStream_t s) {
+    if (partial) res2d_dispatch<T, true>(P, val, x, b, r, partial, s);
+    else res2d_dispatch<T, false>(P, val, x, b, r, nullptr, s);
+}
+template void launch_residual2d<double>(const Problem &, const double *, const double *, const double *, double *,
+                                        double *, hipStream_t);
+template void launch_residual2d<float>(const Problem &, const float *, const float *, const float *, float *,
+                                       double *, hipStream_t);
+
+template <class T>
+void launch_restrict2d(const Problem &P, const T *df, T *dc, hipStream_t s) {
+    const int p = P.p, w = p + 2;
+    int CX, CY;
+    transfer_tile(P.coarse.n1, CX, CY);
+    const size_t shm = (size_t(CX + p + 1) * (CY + p + 1) + size_t(CY + p + 1) * CX + CX * w + CY * w) * sizeof(T);
+    const dim3 grid(nblk(P.coarse.n1, CX), nblk(P.coarse.n1, CY));
+    hipLaunchKernelGGL((k_restrict2d<T>), grid, dim3(256), shm, s, R1_of<T>(P), p, P.fine.n1, P.coarse.n1, df, dc,
+                       P.skip, CX, CY);
+}
+template void launch_restrict2d<double>(const Problem &, const double *, double *, hipStream_t);
+template void launch_restrict2d<float>(const Problem &, const float *, float *, hipStream_t);
+
+template <class T>
+void launch_prolong2d(const Problem &P, const T *ec, T *uf, const T *e, double *u64, bool scaled, hipStream_t s) {
+    const int p = P.p, w = p + 2;
+    int TX, TY;
+    transfer_tile(P.fine.n1, TX, TY);
+    const int KX = TX + p + 1, KY = TY + p + 1;
+    const size_t shm = (size_t(KX) * KY + size_t(KY) * TX + size_t(KX) * w + size_t(KY) * w) * sizeof(T);
+    const dim3 grid(nblk(P.fine.n1, TX), nblk(P.fine.n1, TY));
+    hipLaunchKernelGGL((k_prolong2d<T>), grid, dim3(256), shm, s, R1_of<T>(P), p, P.fine.n1, P.coarse.n1, ec, uf,
+                       u64 ? 1 : 0, e, u64, P.scal.as<double>(), scaled ? 1 : 0, P.skip, TX, TY);
+}
+template void launch_prolong2d<double>(const Problem &, const double *, double *, const double *, double *, bool,
+                                       hipStream_t);
+template void launch_prolong2d<float>(const Problem &, const float *, float *, const float *, double *, bool,
+                                      hipStream_t);
+
+}  // namespace iga2l

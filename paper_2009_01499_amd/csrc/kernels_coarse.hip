@@ -186,6 +186,10 @@ const T *R1_of(const Problem &P) {
 // ------------------------------------------------------------ launchers --
 template <class T>
 void launch_restrict(const Problem &P, const T *df, T *dc, hipStream_t s) {
+    if (P.dim == 2) {
+        launch_restrict2d<T>(P, df, dc, s);
+        return;
+    }
     const int64_t nc = P.coarse.n;
     if (P.dim == 2)
         hipLaunchKernelGGL((k_restrict<2, T>), dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
@@ -199,6 +203,10 @@ template void launch_restrict<float>(const Problem &, const float *, float *, hi
 
 template <class T>
 void launch_prolong_add(const Problem &P, const T *ec, T *uf, hipStream_t s) {
+    if (P.dim == 2) {
+        launch_prolong2d<T>(P, ec, uf, nullptr, nullptr, false, s);
+        return;
+    }
     const int64_t nf = P.fine.n;
     if (P.dim == 2)
         hipLaunchKernelGGL((k_prolong_add<2, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
@@ -212,6 +220,10 @@ template void launch_prolong_add<float>(const Problem &, const float *, float *,
 
 template <class T>
 void launch_prolong_update(const Problem &P, const T *ec, const T *e, double *u, bool scaled, hipStream_t s) {
+    if (P.dim == 2) {
+        launch_prolong2d<T>(P, ec, nullptr, e, u, scaled, s);
+        return;
+    }
     const int64_t nf = P.fine.n;
     if (P.dim == 2)
         hipLaunchKernelGGL((k_prolong_update<2, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p,

@@ -480,6 +480,17 @@ const T *uniform_stencil(const Problem &Pb) {
 template <int D, int P, class T, bool NORM>
 void residual_launch(const Problem &Pb, const T *val, const T *x, const T *b, T *r, double *partial, int &nblocks,
                      bool scale_fp32, bool book, hipStream_t s) {
+    // column-blocked 2-D kernel on large grids (bandwidth regime); the small-tile
+    // kernel below keeps more workgroups in flight on small ones
+    if constexpr (D == 2) if (Pb.fine.n >= (int64_t(1) << 20)) {
+        launch_residual2d<T>(Pb, val, x, b, r, NORM ? partial : nullptr, s);
+        nblocks = int(residual2d_workgroups(Pb));
+        if (NORM)
+            hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, Pb.partial.as<double>(), nblocks,
+                               Pb.scal.as<double>(), scale_fp32 ? 1 : 0, book ? dev_flags(Pb) : nullptr,
+                               dev_hist(Pb), Pb.hist_cap);
+        return;
+    }
     using TS = TileShape<D, P>;
     const int n1 = Pb.fine.n1;
     dim3 grid((n1 + TS::TX - 1) / TS::TX, (n1 + TS::TY - 1) / TS::TY, D == 3 ? (n1 + TS::TZ - 1) / TS::TZ : 1);
