@@ -182,6 +182,22 @@ enum { kScalNorm = 0, kScalSigma = 1, kScalInvSigma = 2, kScalR0 = 3, kScalTol =
 // device int slots in Problem::flags: stop flag, cycles done, status (0 running/converged, 1 max cycles, 2 numeric)
 enum { kFlagDone = 0, kFlagIter = 1, kFlagStatus = 2, kFlagCount = 4 };
 
+// Workgroups are dealt to the XCDs (each with its own L2) round-robin by
+// linear id.  xcd_tile_2d relabels a 2-D grid of tiles so that the workgroups
+// one XCD runs cover a contiguous band of tiles in row-major order: halos
+// shared by neighbouring tiles are then re-read from the same L2.  The map is
+// a bijection of the tile set; results do not depend on it.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ void xcd_tile_2d(int &bx, int &by) {
+    const int ntx = gridDim.x, nb = gridDim.x * gridDim.y;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    const int x = b % kNumXcd, k = b / kNumXcd;
+    const int q = nb / kNumXcd, r = nb % kNumXcd;
+    const int L = x * q + (x < r ? x : r) + k;
+    bx = L % ntx;
+    by = L / ntx;
+}
+
 // views into the status block
 inline int *dev_flags(const Problem &P) { return reinterpret_cast<int *>(P.scal.as<double>() + kScalCount); }
 inline double *dev_hist(const Problem &P) { return P.scal.as<double>() + kScalCount + kFlagCount / 2; }

@@ -35,7 +35,9 @@ __global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d(const T *__restr
     constexpr int W1 = 2 * P + 1, W = W1 * W1, C0 = (W - 1) / 2;
     __shared__ T xs[HX * HY];
     const int stop = skip ? *skip : 0;
-    const int gx0 = blockIdx.x * TX, gy0 = blockIdx.y * TY;
+    int bx, by;
+    xcd_tile_2d(bx, by);
+    const int gx0 = bx * TX, gy0 = by * TY;
     for (int h = threadIdx.x; h < HX * HY; h += blockDim.x) {
         const int hx = h % HX, hy = h / HX;
         const int gx = gx0 + hx - P, gy = gy0 + hy - P;
@@ -133,7 +135,9 @@ __global__ void __launch_bounds__(256) k_restrict2d(const T *__restrict__ R1, in
     T *rx = ts + FY * CX;                                // [CX][w]
     T *ry = rx + CX * w;                                 // [CY][w]
     const int stop = skip ? *skip : 0;
-    const int I0 = blockIdx.x * CX, J0 = blockIdx.y * CY;
+    int bx, by;
+    xcd_tile_2d(bx, by);
+    const int I0 = bx * CX, J0 = by * CY;
     for (int h = threadIdx.x; h < FX * FY; h += blockDim.x) {
         const int hx = h % FX, hy = h / FX;
         const int jx = I0 - 1 + hx, jy = J0 - 1 + hy;
@@ -186,7 +190,9 @@ __global__ void __launch_bounds__(256) k_prolong2d(const T *__restrict__ R1, int
     T *rx = ts + KY * TX;                          // [KX][w] rows of the coarse columns
     T *ry = rx + KX * w;                           // [KY][w]
     const int stop = skip ? *skip : 0;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    int bx, by;
+    xcd_tile_2d(bx, by);
+    const int i0 = bx * TX, j0 = by * TY;
     for (int h = threadIdx.x; h < KX * KY; h += blockDim.x) {
         const int hx = h % KX, hy = h / KX;
         const int Ix = i0 - p + hx, Iy = j0 - p + hy;

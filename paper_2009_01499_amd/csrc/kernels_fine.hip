@@ -53,7 +53,9 @@ __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int
     extern __shared__ unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
     const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
-    const int gx0 = blockIdx.x * TX, gy0 = blockIdx.y * TY, gz0 = (D == 3) ? blockIdx.z * TZ : 0;
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (D == 2) xcd_tile_2d(bx, by);
+    const int gx0 = bx * TX, gy0 = by * TY, gz0 = (D == 3) ? blockIdx.z * TZ : 0;
     const int nh = HX * HY * HZ;
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
         int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
@@ -168,7 +170,9 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
     const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
     T *xs = reinterpret_cast<T *>(smem_raw);
     T *rs = xs + HX * HY * HZ;
-    const int gx0 = ox + blockIdx.x * TX, gy0 = oy + blockIdx.y * TY, gz0 = (D == 3) ? oz + blockIdx.z * TZ : 0;
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (D == 2) xcd_tile_2d(bx, by);
+    const int gx0 = ox + bx * TX, gy0 = oy + by * TY, gz0 = (D == 3) ? oz + blockIdx.z * TZ : 0;
     const int nh = HX * HY * HZ;
     if (!x_zero) {
         for (int h = threadIdx.x; h < nh; h += blockDim.x) {

@@ -100,7 +100,9 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
     __shared__ T e0[NH];
     __shared__ T e1[NH];
     const int n1 = L.n1;
-    const int gx0 = blockIdx.x * TX, gy0 = blockIdx.y * TY, gz0 = (D == 3) ? blockIdx.z * TZ : 0;
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (D == 2) xcd_tile_2d(bx, by);
+    const int gx0 = bx * TX, gy0 = by * TY, gz0 = (D == 3) ? blockIdx.z * TZ : 0;
     const int zoff = (D == 3) ? 2 : 0;
     auto inside = [n1](int x, int y, int z) {
         return x >= 0 && x < n1 && y >= 0 && y < n1 && (D == 2 || (z >= 0 && z < n1));
@@ -178,7 +180,9 @@ __global__ void __launch_bounds__(256) k_rb_multi2(LevelDev<T> L, const T *__res
     __shared__ T rs[NH];
     const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     const int n1 = L.n1;
-    const int gx0 = blockIdx.x * TX, gy0 = blockIdx.y * TY;
+    int bx, by;
+    xcd_tile_2d(bx, by);
+    const int gx0 = bx * TX, gy0 = by * TY;
     for (int h = threadIdx.x; h < NH; h += blockDim.x) {
         const int hx = h % HX, hy = h / HX;
         const int gx = gx0 + hx - H, gy = gy0 + hy - H;
@@ -288,7 +292,9 @@ __global__ void __launch_bounds__(256) k_res_restrict_tiled(LevelDev<T> L, const
     __shared__ T es[EX * EY * EZ];
     __shared__ T rs[FX * FY * FZ];
     const int n1 = L.n1;
-    const int I0 = blockIdx.x * CX, J0 = blockIdx.y * CY, K0 = (D == 3) ? blockIdx.z * CZ : 0;
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (D == 2) xcd_tile_2d(bx, by);
+    const int I0 = bx * CX, J0 = by * CY, K0 = (D == 3) ? blockIdx.z * CZ : 0;
     const int fx0 = 2 * I0, fy0 = 2 * J0, fz0 = 2 * K0;  // fine region origin (fine index of child 2I)
     const int ez = (D == 3) ? 1 : 0;
     auto inside = [n1](int x, int y, int z) {
