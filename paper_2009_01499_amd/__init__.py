@@ -256,16 +256,26 @@ class Problem:
         return lam, g
 
 
-def solve_batch(problems: Sequence[Problem], bs, us, opts: Optional[Opts] = None, stream=None):
-    """Solve independent problems b[k] -> u[k] in one call; returns a list of Info."""
+def solve_batch(problems: Sequence[Problem], bs, us, opts: Optional[Opts] = None, stream=None,
+                raise_on_notconv: bool = True):
+    """Solve independent problems b[k] -> u[k] (u[k] holds the start) in one
+    call; returns a list of Info.  2-D batches with the coloured sweep and the
+    V-cycle run with batched launches, other batches problem by problem."""
     n = len(problems)
+    o = opts or Opts()
     hs = (ctypes.c_void_p * n)(*[p._h.value for p in problems])
     bp = (ctypes.c_void_p * n)(*[_dev_ptr(b, p.n, "b").value for b, p in zip(bs, problems)])
     up = (ctypes.c_void_p * n)(*[_dev_ptr(u, p.n, "u").value for u, p in zip(us, problems)])
     infos = (CIgaInfo * n)()
-    co = (opts or Opts()).c()
-    _check(lib().iga2l_solve_batch(hs, n, bp, up, ctypes.byref(co), infos, _stream(stream)))
-    return [Info(i.iters, i.status, i.r0, i.relres, i.t_solve_ms, np.zeros(0)) for i in infos]
+    hists = [np.zeros(max(o.max_cycles, 1)) for _ in range(n)]
+    for i, h in zip(infos, hists):
+        i.relres_history = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        i.history_cap = len(h)
+    co = o.c()
+    code = lib().iga2l_solve_batch(hs, n, bp, up, ctypes.byref(co), infos, _stream(stream))
+    if code != OK and not (code == ENOTCONV and not raise_on_notconv):
+        _check(code)
+    return [Info(i.iters, i.status, i.r0, i.relres, i.t_solve_ms, h[:i.iters].copy()) for i, h in zip(infos, hists)]
 
 
 def header_functions() -> list:

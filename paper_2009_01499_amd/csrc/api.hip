@@ -181,6 +181,8 @@ struct SkipGuard {
     ~SkipGuard() { P.skip = nullptr; }
 };
 
+}  // namespace
+
 void ensure_history(Problem &P, int cap) {
     if (cap <= P.hist_cap) return;
     DevBuf nb;
@@ -192,7 +194,10 @@ void ensure_history(Problem &P, int cap) {
     P.host_status = nullptr;
     IGA2L_HIP(hipHostMalloc(&P.host_status, status_bytes(cap), hipHostMallocDefault));
     P.hist_cap = cap;
+    P.layout_id = next_layout_id();
 }
+
+namespace {
 
 // Solve loop.  The convergence test runs on the device (the norm-carrying
 // residual after each cycle records the history and raises a stop flag that
@@ -320,6 +325,7 @@ int iga2l_assemble(int dim, const double *const *knots, const int *nknots, int p
             }
             set_device(P);
             host_assemble(P);
+            P.layout_id = next_layout_id();
         } catch (...) {
             delete h;
             throw;
@@ -375,6 +381,7 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             host_build_dst(P);
         }
         IGA2L_HIP(hipDeviceSynchronize());
+        P.layout_id = next_layout_id();
     });
 }
 
@@ -490,10 +497,20 @@ int iga2l_solve_batch(iga2l_problem *const *probs, int nprob, const double *cons
         iga2l_opts o = effective_opts(opts);
         int worst = IGA2L_OK;
         std::string msg;
+        std::vector<Problem *> pv(size_t(std::max(nprob, 0)));
         for (int k = 0; k < nprob; ++k) {
             IGA2L_REQUIRE(probs[k], IGA2L_EINVAL, "problem is NULL");
-            Problem &P = probs[k]->P;
-            check_opts(P, o);
+            pv[k] = &probs[k]->P;
+            check_opts(*pv[k], o);
+        }
+        if (batch_supported(pv.data(), nprob, o)) {
+            set_device(*pv[0]);
+            solve_batch_fused(pv.data(), nprob, b, u, o, infos, static_cast<hipStream_t>(stream), worst, msg);
+            if (worst != IGA2L_OK) throw Error{worst, msg};
+            return;
+        }
+        for (int k = 0; k < nprob; ++k) {
+            Problem &P = *pv[k];
             set_device(P);
             try {
                 solve_impl(P, b[k], u[k], o, infos ? &infos[k] : nullptr, static_cast<hipStream_t>(stream));

@@ -175,7 +175,14 @@ struct Problem {
 
     // tuning knobs (numerics-neutral)
     int tile_bx = 4, tile_by = 4, tile_bz = 1;   // Schwarz tile in blocks
+
+    // identifies the device layout (buffers, levels, set-up state); renewed
+    // whenever it changes, never reused, so cached batch plans can tell
+    // whether they still describe this problem
+    uint64_t layout_id = 0;
 };
+
+uint64_t next_layout_id();
 
 // device scalar slots in Problem::scal (doubles)
 enum { kScalNorm = 0, kScalSigma = 1, kScalInvSigma = 2, kScalR0 = 3, kScalTol = 4, kScalMaxCycles = 5, kScalCount = 8 };
@@ -188,20 +195,103 @@ enum { kFlagDone = 0, kFlagIter = 1, kFlagStatus = 2, kFlagCount = 4 };
 // shared by neighbouring tiles are then re-read from the same L2.  The map is
 // a bijection of the tile set; results do not depend on it.
 constexpr int kNumXcd = 8;
-__device__ __forceinline__ void xcd_tile_2d(int &bx, int &by) {
-    const int ntx = gridDim.x, nb = gridDim.x * gridDim.y;
-    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+__host__ __device__ __forceinline__ void xcd_relabel(int b, int ntx, int nb, int &bx, int &by) {
     const int x = b % kNumXcd, k = b / kNumXcd;
     const int q = nb / kNumXcd, r = nb % kNumXcd;
     const int L = x * q + (x < r ? x : r) + k;
     bx = L % ntx;
     by = L / ntx;
 }
+__device__ __forceinline__ void xcd_tile_2d(int &bx, int &by) {
+    xcd_relabel(int(blockIdx.y * gridDim.x + blockIdx.x), int(gridDim.x), int(gridDim.x * gridDim.y), bx, by);
+}
 
 // views into the status block
 inline int *dev_flags(const Problem &P) { return reinterpret_cast<int *>(P.scal.as<double>() + kScalCount); }
 inline double *dev_hist(const Problem &P) { return P.scal.as<double>() + kScalCount + kFlagCount / 2; }
 inline size_t status_bytes(int hist_cap) { return sizeof(double) * (kScalCount + kFlagCount / 2 + hist_cap); }
+
+// ------------------------------------------------------ batched launches --
+// A batched launch runs one step of the cycle for many independent 2-D
+// problems at once: workgroup w handles tile map[w].y of problem map[w].x,
+// with that problem's operands read from a device table.  The arithmetic of
+// every tile is that of the single-problem kernel, so batched and single
+// solves agree bitwise.
+enum VecRole { kVecU, kVecB, kVecR64, kVecE0, kVecE1, kVecRhsW, kVecDFine, kVecDC, kVecEC, kVecCount };
+
+struct BatchProb {
+    const void *val[2], *inv[2], *cs[2], *R1[2];   // [0] FP64, [1] FP32 (null if not set up)
+    const int *cls;
+    int64_t npad;
+    int pitch1, n1, n1c, p, ncls1, ulo, uhi;
+    int hist_cap;
+    double *scal, *partial, *hist;
+    int *flags;                                    // also the stop flag of every kernel
+    void *vec[kVecCount];
+    int res_ntx, res_nty;                          // residual tiles (64 x 4 points)
+    int col_ntx, col_nty;                          // colour tiles, a grid covering every colour
+    int tr_cx, tr_cy, tr_ntx, tr_nty;              // restriction tiles (coarse points)
+    int pr_tx, pr_ty, pr_ntx, pr_nty;              // prolongation tiles (fine points)
+};
+
+// level l (above the one-workgroup tail) of one problem's V-cycle
+template <class T>
+struct BatchLevel {
+    LevelDev<T> L;
+    const T *rhs;      // right-hand side of the level
+    T *e_pre;          // pre-smoothed iterate
+    T *rc;             // restricted residual = right-hand side of level l+1
+    const T *ecl;      // correction of level l+1
+    T *e_out;          // result of the level
+    int n1c;           // points per direction of level l+1
+    int ntx, nty;      // 32 x 8 tiles
+    const int *skip;
+};
+
+// one problem's tail of the V-cycle (one workgroup)
+template <class T>
+struct BatchBottom {
+    const LevelDev<T> *levels;   // first entry = first level of the tail
+    int nlev;
+    const T *rhs;
+    T *e;
+    const int *skip;
+};
+
+void launch_norm_finalize_batch(const BatchProb *bp, int nprob, bool scale_fp32, bool book, hipStream_t s);
+void launch_solve_init_batch(const BatchProb *bp, int nprob, double tol, int max_cycles, hipStream_t s);
+template <class T>
+void launch_colour_batch(const BatchProb *bp, const int2 *map, int nwg, int p, int bw, int nbx, int nby, int cx,
+                         int cy, int S, int role_src, int role_dst, int role_rhs, bool x_zero, bool fuse,
+                         hipStream_t s);
+template <class T>
+void launch_residual_batch_dispatch(int p, const BatchProb *bp, const int2 *map, int nwg, int role_x, int role_b,
+                                    int role_r, bool norm, bool use_skip, hipStream_t s);
+template <class T>
+void launch_restrict_batch(const BatchProb *bp, const int2 *map, int nwg, size_t shm, int role_f, int role_c,
+                           hipStream_t s);
+template <class T>
+void launch_prolong_update_batch(const BatchProb *bp, const int2 *map, int nwg, size_t shm, int role_c, int role_e,
+                                 bool scaled, hipStream_t s);
+size_t restrict2d_lds(int p, int cx, int cy, size_t elem);
+size_t prolong2d_lds(int p, int tx, int ty, size_t elem);
+void transfer_tile_2d(int64_t n1, int &tx, int &ty);
+template <class T>
+void launch_rb_multi2_batch(const BatchLevel<T> *bl, const int2 *map, int nwg, int nu, bool restrict_, bool zero_src,
+                            hipStream_t s);
+template <class T>
+void launch_vcycle_bottom_batch(const BatchBottom<T> *bb, int nprob, size_t shm, int nu1, int nu2, hipStream_t s);
+size_t colour_lds(int p, int S, int nbx, int nby, size_t elem);
+void colour_tile_clamp(int S, int &nbx, int &nby);
+
+// grows the status block so that it holds cap cycles of history
+void ensure_history(Problem &P, int cap);
+// the batched solve handles these problems and options (2-D, coloured
+// Schwarz, fused V-cycle, below 2^20 unknowns each, one device)
+bool batch_supported(Problem *const *probs, int nprob, const iga2l_opts &o);
+// worst / msg: the first non-converged (or numerically failed) problem
+void solve_batch_fused(Problem *const *probs, int nprob, const double *const *b, double *const *u,
+                       const iga2l_opts &o, iga2l_info *infos, hipStream_t s, int &worst, std::string &msg);
 
 // ------------------------------------------------------------ host set-up --
 void host_assemble(Problem &P);                 // 1-D factors, DIA, transfers, kappa

@@ -10,6 +10,12 @@
 
 namespace iga2l {
 
+// transfer tiles: 64 x 16 points on large grids, 32 x 8 otherwise
+void transfer_tile_2d(int64_t n1, int &tx, int &ty) {
+    if (n1 >= 1024) { tx = 64; ty = 16; }
+    else { tx = 32; ty = 8; }
+}
+
 namespace {
 
 inline unsigned nblk(int64_t n, int t) { return unsigned((n + t - 1) / t); }
@@ -117,17 +123,12 @@ __global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d(const T *__restr
 // window; pass 2 (y): d_c[J][I].  The 1-D factor rows of the tile are staged.
 // transfer tiles: 64 x 16 on large grids, 32 x 8 where that would leave the
 // device under-occupied
-inline void transfer_tile(int64_t n1, int &tx, int &ty) {
-    if (n1 >= 1024) { tx = 64; ty = 16; }
-    else { tx = 32; ty = 8; }
-}
 
 template <class T>
-__global__ void __launch_bounds__(256) k_restrict2d(const T *__restrict__ R1, int p, int n1f, int n1c,
-                                                    const T *__restrict__ df, T *__restrict__ dc,
-                                                    const int *__restrict__ skip, int CX, int CY) {
-    extern __shared__ unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
+__device__ __forceinline__ void restrict2d_body(const T *__restrict__ R1, int p, int n1f, int n1c,
+                                                const T *__restrict__ df, T *__restrict__ dc,
+                                                const int *__restrict__ skip, int CX, int CY, int bx, int by,
+                                                T *sm) {
     const int w = p + 2;
     const int FX = CX + p + 1, FY = CY + p + 1;        // fine window (I0-1 .. I0+CX-1+p)
     T *ds = sm;                                          // [FY][FX]
@@ -135,8 +136,6 @@ __global__ void __launch_bounds__(256) k_restrict2d(const T *__restrict__ R1, in
     T *rx = ts + FY * CX;                                // [CX][w]
     T *ry = rx + CX * w;                                 // [CY][w]
     const int stop = skip ? *skip : 0;
-    int bx, by;
-    xcd_tile_2d(bx, by);
     const int I0 = bx * CX, J0 = by * CY;
     for (int h = threadIdx.x; h < FX * FY; h += blockDim.x) {
         const int hx = h % FX, hy = h / FX;
@@ -170,19 +169,27 @@ __global__ void __launch_bounds__(256) k_restrict2d(const T *__restrict__ R1, in
     }
 }
 
+template <class T>
+__global__ void __launch_bounds__(256) k_restrict2d(const T *__restrict__ R1, int p, int n1f, int n1c,
+                                                    const T *__restrict__ df, T *__restrict__ dc,
+                                                    const int *__restrict__ skip, int CX, int CY) {
+    extern __shared__ unsigned char smem_raw[];
+    int bx, by;
+    xcd_tile_2d(bx, by);
+    restrict2d_body<T>(R1, p, n1f, n1c, df, dc, skip, CX, CY, bx, by, reinterpret_cast<T *>(smem_raw));
+}
+
 // ------------------------------------------------------------------------
 // (R1 (x) R1)^T e_c on tiles of TX x TY fine points; fine i takes coarse
 // I = i-p .. i+1 with weight R1[I][i-I+1].  mode 0: uf += P e_c;  mode 1:
 // u64 += sigma (e + P e_c) (end of a correction cycle; sigma from scal when
 // scaled).
 template <class T>
-__global__ void __launch_bounds__(256) k_prolong2d(const T *__restrict__ R1, int p, int n1f, int n1c,
-                                                   const T *__restrict__ ec, T *__restrict__ uf, int mode,
-                                                   const T *__restrict__ e, double *__restrict__ u64,
-                                                   const double *__restrict__ scal, int scaled,
-                                                   const int *__restrict__ skip, int TX, int TY) {
-    extern __shared__ unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
+__device__ __forceinline__ void prolong2d_body(const T *__restrict__ R1, int p, int n1f, int n1c,
+                                               const T *__restrict__ ec, T *__restrict__ uf, int mode,
+                                               const T *__restrict__ e, double *__restrict__ u64,
+                                               const double *__restrict__ scal, int scaled,
+                                               const int *__restrict__ skip, int TX, int TY, int bx, int by, T *sm) {
     const int w = p + 2;
     const int KX = TX + p + 1, KY = TY + p + 1;   // coarse window I0-p .. I0+TX
     T *es = sm;                                    // [KY][KX]
@@ -190,8 +197,6 @@ __global__ void __launch_bounds__(256) k_prolong2d(const T *__restrict__ R1, int
     T *rx = ts + KY * TX;                          // [KX][w] rows of the coarse columns
     T *ry = rx + KX * w;                           // [KY][w]
     const int stop = skip ? *skip : 0;
-    int bx, by;
-    xcd_tile_2d(bx, by);
     const int i0 = bx * TX, j0 = by * TY;
     for (int h = threadIdx.x; h < KX * KY; h += blockDim.x) {
         const int hx = h % KX, hy = h / KX;
@@ -237,6 +242,52 @@ __global__ void __launch_bounds__(256) k_prolong2d(const T *__restrict__ R1, int
             u64[gi] += scaled ? scal[kScalSigma] * double(corr) : double(corr);
         }
     }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_prolong2d(const T *__restrict__ R1, int p, int n1f, int n1c,
+                                                   const T *__restrict__ ec, T *__restrict__ uf, int mode,
+                                                   const T *__restrict__ e, double *__restrict__ u64,
+                                                   const double *__restrict__ scal, int scaled,
+                                                   const int *__restrict__ skip, int TX, int TY) {
+    extern __shared__ unsigned char smem_raw[];
+    int bx, by;
+    xcd_tile_2d(bx, by);
+    prolong2d_body<T>(R1, p, n1f, n1c, ec, uf, mode, e, u64, scal, scaled, skip, TX, TY, bx, by,
+                      reinterpret_cast<T *>(smem_raw));
+}
+
+// ----------------------------------------------------------- batched --
+template <class T>
+constexpr int prec_slot() { return std::is_same<T, double>::value ? 0 : 1; }
+
+template <class T>
+__global__ void __launch_bounds__(256) kb_restrict2d(const BatchProb *__restrict__ bp, const int2 *__restrict__ map,
+                                                     int role_f, int role_c) {
+    extern __shared__ unsigned char smem_raw[];
+    const int2 m = map[blockIdx.x];
+    const BatchProb &q = bp[m.x];
+    int bx, by;
+    xcd_relabel(m.y, q.tr_ntx, q.tr_ntx * q.tr_nty, bx, by);
+    restrict2d_body<T>(static_cast<const T *>(q.R1[prec_slot<T>()]), q.p, q.n1, q.n1c,
+                       static_cast<const T *>(q.vec[role_f]), static_cast<T *>(q.vec[role_c]), q.flags, q.tr_cx,
+                       q.tr_cy, bx, by, reinterpret_cast<T *>(smem_raw));
+}
+
+// u64 += sigma (e + P e_c): the end of a correction cycle
+template <class T>
+__global__ void __launch_bounds__(256) kb_prolong_update2d(const BatchProb *__restrict__ bp,
+                                                           const int2 *__restrict__ map, int role_c, int role_e,
+                                                           int scaled) {
+    extern __shared__ unsigned char smem_raw[];
+    const int2 m = map[blockIdx.x];
+    const BatchProb &q = bp[m.x];
+    int bx, by;
+    xcd_relabel(m.y, q.pr_ntx, q.pr_ntx * q.pr_nty, bx, by);
+    prolong2d_body<T>(static_cast<const T *>(q.R1[prec_slot<T>()]), q.p, q.n1, q.n1c,
+                      static_cast<const T *>(q.vec[role_c]), static_cast<T *>(nullptr), 1,
+                      static_cast<const T *>(q.vec[role_e]), static_cast<double *>(q.vec[kVecU]), q.scal, scaled,
+                      q.flags, q.pr_tx, q.pr_ty, bx, by, reinterpret_cast<T *>(smem_raw));
 }
 
 template <class T>
@@ -294,10 +345,10 @@ template void launch_residual2d<float>(const Problem &, const float *, const flo
 
 template <class T>
 void launch_restrict2d(const Problem &P, const T *df, T *dc, hipStream_t s) {
-    const int p = P.p, w = p + 2;
+    const int p = P.p;
     int CX, CY;
-    transfer_tile(P.coarse.n1, CX, CY);
-    const size_t shm = (size_t(CX + p + 1) * (CY + p + 1) + size_t(CY + p + 1) * CX + CX * w + CY * w) * sizeof(T);
+    transfer_tile_2d(P.coarse.n1, CX, CY);
+    const size_t shm = restrict2d_lds(p, CX, CY, sizeof(T));
     const dim3 grid(nblk(P.coarse.n1, CX), nblk(P.coarse.n1, CY));
     hipLaunchKernelGGL((k_restrict2d<T>), grid, dim3(256), shm, s, R1_of<T>(P), p, P.fine.n1, P.coarse.n1, df, dc,
                        P.skip, CX, CY);
@@ -307,11 +358,10 @@ template void launch_restrict2d<float>(const Problem &, const float *, float *, 
 
 template <class T>
 void launch_prolong2d(const Problem &P, const T *ec, T *uf, const T *e, double *u64, bool scaled, hipStream_t s) {
-    const int p = P.p, w = p + 2;
+    const int p = P.p;
     int TX, TY;
-    transfer_tile(P.fine.n1, TX, TY);
-    const int KX = TX + p + 1, KY = TY + p + 1;
-    const size_t shm = (size_t(KX) * KY + size_t(KY) * TX + size_t(KX) * w + size_t(KY) * w) * sizeof(T);
+    transfer_tile_2d(P.fine.n1, TX, TY);
+    const size_t shm = prolong2d_lds(p, TX, TY, sizeof(T));
     const dim3 grid(nblk(P.fine.n1, TX), nblk(P.fine.n1, TY));
     hipLaunchKernelGGL((k_prolong2d<T>), grid, dim3(256), shm, s, R1_of<T>(P), p, P.fine.n1, P.coarse.n1, ec, uf,
                        u64 ? 1 : 0, e, u64, P.scal.as<double>(), scaled ? 1 : 0, P.skip, TX, TY);
@@ -320,5 +370,34 @@ template void launch_prolong2d<double>(const Problem &, const double *, double *
                                        hipStream_t);
 template void launch_prolong2d<float>(const Problem &, const float *, float *, const float *, double *, bool,
                                       hipStream_t);
+
+size_t restrict2d_lds(int p, int cx, int cy, size_t elem) {
+    const size_t w = p + 2, FX = cx + p + 1, FY = cy + p + 1;
+    return (FX * FY + FY * cx + cx * w + cy * w) * elem;
+}
+
+size_t prolong2d_lds(int p, int tx, int ty, size_t elem) {
+    const size_t w = p + 2, KX = tx + p + 1, KY = ty + p + 1;
+    return (KX * KY + KY * tx + KX * w + KY * w) * elem;
+}
+
+template <class T>
+void launch_restrict_batch(const BatchProb *bp, const int2 *map, int nwg, size_t shm, int role_f, int role_c,
+                           hipStream_t s) {
+    hipLaunchKernelGGL((kb_restrict2d<T>), dim3(nwg), dim3(256), shm, s, bp, map, role_f, role_c);
+}
+template void launch_restrict_batch<double>(const BatchProb *, const int2 *, int, size_t, int, int, hipStream_t);
+template void launch_restrict_batch<float>(const BatchProb *, const int2 *, int, size_t, int, int, hipStream_t);
+
+template <class T>
+void launch_prolong_update_batch(const BatchProb *bp, const int2 *map, int nwg, size_t shm, int role_c, int role_e,
+                                 bool scaled, hipStream_t s) {
+    hipLaunchKernelGGL((kb_prolong_update2d<T>), dim3(nwg), dim3(256), shm, s, bp, map, role_c, role_e,
+                       scaled ? 1 : 0);
+}
+template void launch_prolong_update_batch<double>(const BatchProb *, const int2 *, int, size_t, int, int, bool,
+                                                  hipStream_t);
+template void launch_prolong_update_batch<float>(const BatchProb *, const int2 *, int, size_t, int, int, bool,
+                                                 hipStream_t);
 
 }  // namespace iga2l

@@ -191,12 +191,8 @@ void launch_restrict(const Problem &P, const T *df, T *dc, hipStream_t s) {
         return;
     }
     const int64_t nc = P.coarse.n;
-    if (P.dim == 2)
-        hipLaunchKernelGGL((k_restrict<2, T>), dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
-                           P.coarse.n1, df, dc, P.skip);
-    else
-        hipLaunchKernelGGL((k_restrict<3, T>), dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
-                           P.coarse.n1, df, dc, P.skip);
+    hipLaunchKernelGGL((k_restrict<3, T>), dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
+                       P.coarse.n1, df, dc, P.skip);
 }
 template void launch_restrict<double>(const Problem &, const double *, double *, hipStream_t);
 template void launch_restrict<float>(const Problem &, const float *, float *, hipStream_t);
@@ -208,12 +204,8 @@ void launch_prolong_add(const Problem &P, const T *ec, T *uf, hipStream_t s) {
         return;
     }
     const int64_t nf = P.fine.n;
-    if (P.dim == 2)
-        hipLaunchKernelGGL((k_prolong_add<2, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
-                           P.coarse.n1, ec, uf, P.skip);
-    else
-        hipLaunchKernelGGL((k_prolong_add<3, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
-                           P.coarse.n1, ec, uf, P.skip);
+    hipLaunchKernelGGL((k_prolong_add<3, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
+                       P.coarse.n1, ec, uf, P.skip);
 }
 template void launch_prolong_add<double>(const Problem &, const double *, double *, hipStream_t);
 template void launch_prolong_add<float>(const Problem &, const float *, float *, hipStream_t);
@@ -225,12 +217,8 @@ void launch_prolong_update(const Problem &P, const T *ec, const T *e, double *u,
         return;
     }
     const int64_t nf = P.fine.n;
-    if (P.dim == 2)
-        hipLaunchKernelGGL((k_prolong_update<2, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p,
-                           P.fine.n1, P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0, P.skip);
-    else
-        hipLaunchKernelGGL((k_prolong_update<3, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p,
-                           P.fine.n1, P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0, P.skip);
+    hipLaunchKernelGGL((k_prolong_update<3, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p,
+                       P.fine.n1, P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0, P.skip);
 }
 template void launch_prolong_update<double>(const Problem &, const double *, const double *, double *, bool,
                                             hipStream_t);

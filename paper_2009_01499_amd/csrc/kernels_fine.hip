@@ -43,19 +43,17 @@ __device__ __forceinline__ bool tile_uniform(int lo0, int hi0, int lo1, int hi1,
 // with a halo of width P (zeros outside the grid).  NORM: the per-workgroup
 // sums of r^2 are combined by the last workgroup to finish, in a fixed
 // order, into ||r||_2 and the scaling of the FP32 correction cycle.
+// The body serves the single-problem kernel and the batched one: tile
+// (bx, by, bz), its partial sum goes to *part, xs = LDS of the halo tile.
 template <int D, int P, class T, bool NORM>
-__global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
-                                                  int n1, int TX, int TY, int TZ, const T *__restrict__ x,
-                                                  const T *__restrict__ b, T *__restrict__ r,
-                                                  double *__restrict__ partial, const T *__restrict__ cs, int ulo,
-                                                  int uhi, const int *__restrict__ skip) {
+__device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2, int n1,
+                                              int TX, int TY, int TZ, const T *__restrict__ x,
+                                              const T *__restrict__ b, T *__restrict__ r, double *__restrict__ part,
+                                              const T *__restrict__ cs, int ulo, int uhi,
+                                              const int *__restrict__ skip, int bx, int by, int bz, T *xs) {
     const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
-    extern __shared__ unsigned char smem_raw[];
-    T *xs = reinterpret_cast<T *>(smem_raw);
     const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
-    int bx = blockIdx.x, by = blockIdx.y;
-    if (D == 2) xcd_tile_2d(bx, by);
-    const int gx0 = bx * TX, gy0 = by * TY, gz0 = (D == 3) ? blockIdx.z * TZ : 0;
+    const int gx0 = bx * TX, gy0 = by * TY, gz0 = (D == 3) ? bz * TZ : 0;
     const int nh = HX * HY * HZ;
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
         int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
@@ -132,9 +130,23 @@ __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int
         if (threadIdx.x == 0) {
             double s = 0.0;
             for (int k = 0; k < int(blockDim.x / kWave); ++k) s += red[k];
-            partial[(int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+            *part = s;
         }
     }
+}
+
+template <int D, int P, class T, bool NORM>
+__global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
+                                                  int n1, int TX, int TY, int TZ, const T *__restrict__ x,
+                                                  const T *__restrict__ b, T *__restrict__ r,
+                                                  double *__restrict__ partial, const T *__restrict__ cs, int ulo,
+                                                  int uhi, const int *__restrict__ skip) {
+    extern __shared__ unsigned char smem_raw[];
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (D == 2) xcd_tile_2d(bx, by);
+    double *part = NORM ? partial + (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x : nullptr;
+    residual_body<D, P, T, NORM>(val, npad, pitch1, pitch2, n1, TX, TY, TZ, x, b, r, part, cs, ulo, uhi, skip, bx, by,
+                                 int(blockIdx.z), reinterpret_cast<T *>(smem_raw));
 }
 
 // ------------------------------------------------------------------------
@@ -148,31 +160,30 @@ __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int
 // all corrections of the colour based on the colour-start iterate.
 // For a colour period s > B the same kernel runs with the tile spacing s; the
 // points between blocks are copied unchanged.
+// The body serves the single-problem kernel and the batched one: tile
+// (tbx, tby, tbz) of the colour, smem = LDS of the tile.
 template <int D, int P, int B, class T>
-__global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
-                                                 int n1, const T *__restrict__ inv, const int *__restrict__ cls,
-                                                 int ncls1, const T *__restrict__ x_src, T *__restrict__ x_dst,
-                                                 const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz,
-                                                 int S, int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo,
-                                                 int uhi, const int *__restrict__ skip,
-                                                 const double *__restrict__ r64, const double *__restrict__ scal,
-                                                 T *__restrict__ rhs_out) {
+__device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2, int n1,
+                                            const T *__restrict__ inv, const int *__restrict__ cls, int ncls1,
+                                            const T *__restrict__ x_src, T *__restrict__ x_dst,
+                                            const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz, int S,
+                                            int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo, int uhi,
+                                            const int *__restrict__ skip, const double *__restrict__ r64,
+                                            const double *__restrict__ scal, T *__restrict__ rhs_out, int tbx,
+                                            int tby, int tbz, unsigned char *smem_raw) {
     // r64 != null (first colour of an FP32 correction sweep, x_zero): the
     // right-hand side is r64 / sigma, cast here and stored to rhs_out for the
     // later colours
     const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     constexpr int BD = cpow(B, D);
     constexpr int HB = (B - 1) / 2;
-    extern __shared__ unsigned char smem_raw[];
     // tile = NBX x NBY (x NBZ) cells of S points; each cell holds one block in
     // its first B x B points
     const int TX = NBX * S, TY = NBY * S, TZ = (D == 3) ? NBZ * S : 1;
     const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
     T *xs = reinterpret_cast<T *>(smem_raw);
     T *rs = xs + HX * HY * HZ;
-    int bx = blockIdx.x, by = blockIdx.y;
-    if (D == 2) xcd_tile_2d(bx, by);
-    const int gx0 = ox + bx * TX, gy0 = oy + by * TY, gz0 = (D == 3) ? oz + blockIdx.z * TZ : 0;
+    const int gx0 = ox + tbx * TX, gy0 = oy + tby * TY, gz0 = (D == 3) ? oz + tbz * TZ : 0;
     const int nh = HX * HY * HZ;
     if (!x_zero) {
         for (int h = threadIdx.x; h < nh; h += blockDim.x) {
@@ -269,6 +280,22 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
         }
     }
     x_dst[gi] = xi + delta;
+}
+
+template <int D, int P, int B, class T>
+__global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
+                                                 int n1, const T *__restrict__ inv, const int *__restrict__ cls,
+                                                 int ncls1, const T *__restrict__ x_src, T *__restrict__ x_dst,
+                                                 const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz,
+                                                 int S, int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo,
+                                                 int uhi, const int *__restrict__ skip,
+                                                 const double *__restrict__ r64, const double *__restrict__ scal,
+                                                 T *__restrict__ rhs_out) {
+    extern __shared__ unsigned char smem_raw[];
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (D == 2) xcd_tile_2d(bx, by);
+    colour_body<D, P, B, T>(val, npad, pitch1, pitch2, n1, inv, cls, ncls1, x_src, x_dst, rhs, x_zero, ox, oy, oz, S,
+                            NBX, NBY, NBZ, cs, ulo, uhi, skip, r64, scal, rhs_out, bx, by, int(blockIdx.z), smem_raw);
 }
 
 // ------------------------------------------------------------------------
@@ -397,8 +424,8 @@ __global__ void __launch_bounds__(kWave) k_block_inverse(const double *__restric
 // the scaling used by the FP32 correction cycle.  book != nullptr: the
 // device-side convergence test after a cycle (record the relative residual,
 // count the cycle, raise the stop flag).
-__global__ void __launch_bounds__(256) k_norm_finalize(const double *__restrict__ partial, int np, double *scal,
-                                                       int scale_fp32, int *book, double *hist, int hist_cap) {
+__device__ __forceinline__ void finalize_body(const double *__restrict__ partial, int np, double *scal,
+                                              int scale_fp32, int *book, double *hist, int hist_cap) {
     if (book && book[kFlagDone]) return;
     __shared__ double red[256];
     double s = 0.0;
@@ -430,9 +457,13 @@ __global__ void __launch_bounds__(256) k_norm_finalize(const double *__restrict_
     }
 }
 
+__global__ void __launch_bounds__(256) k_norm_finalize(const double *__restrict__ partial, int np, double *scal,
+                                                       int scale_fp32, int *book, double *hist, int hist_cap) {
+    finalize_body(partial, np, scal, scale_fp32, book, hist, hist_cap);
+}
+
 // Start of a solve: the norm just computed is r0; set the stopping data.
-__global__ void k_solve_init(double *scal, int *flags, double tol, int max_cycles) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void init_body(double *scal, int *flags, double tol, int max_cycles) {
     const double r0 = scal[kScalNorm];
     scal[kScalR0] = r0;
     scal[kScalTol] = tol;
@@ -450,6 +481,11 @@ __global__ void k_solve_init(double *scal, int *flags, double tol, int max_cycle
     flags[kFlagDone] = done;
     flags[kFlagIter] = 0;
     flags[kFlagStatus] = status;
+}
+
+__global__ void k_solve_init(double *scal, int *flags, double tol, int max_cycles) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    init_body(scal, flags, tol, max_cycles);
 }
 
 template <class T>
@@ -633,6 +669,61 @@ void lex_dp(const Problem &Pb, int step, double *u, const double *b, hipStream_t
     }
 }
 
+// ----------------------------------------------------------- batched --
+template <class T>
+constexpr int prec_slot() { return std::is_same<T, double>::value ? 0 : 1; }
+
+template <int P, class T, bool NORM>
+__global__ void __launch_bounds__(256) kb_residual(const BatchProb *__restrict__ bp, const int2 *__restrict__ map,
+                                                   int role_x, int role_b, int role_r, int use_skip) {
+    extern __shared__ unsigned char smem_raw[];
+    const int2 m = map[blockIdx.x];
+    const BatchProb &q = bp[m.x];
+    using TS = TileShape<2, P>;
+    int bx, by;
+    xcd_relabel(m.y, q.res_ntx, q.res_ntx * q.res_nty, bx, by);
+    constexpr int pr = prec_slot<T>();
+    residual_body<2, P, T, NORM>(static_cast<const T *>(q.val[pr]), q.npad, q.pitch1, 0, q.n1, TS::TX, TS::TY, 1,
+                                 static_cast<const T *>(q.vec[role_x]), static_cast<const T *>(q.vec[role_b]),
+                                 static_cast<T *>(q.vec[role_r]), NORM ? q.partial + m.y : nullptr,
+                                 static_cast<const T *>(q.cs[pr]), q.ulo, q.uhi, use_skip ? q.flags : nullptr, bx,
+                                 by, 0, reinterpret_cast<T *>(smem_raw));
+}
+
+__global__ void __launch_bounds__(256) kb_norm_finalize(const BatchProb *__restrict__ bp, int scale_fp32, int book) {
+    const BatchProb &q = bp[blockIdx.x];
+    finalize_body(q.partial, q.res_ntx * q.res_nty, q.scal, scale_fp32, book ? q.flags : nullptr, q.hist, q.hist_cap);
+}
+
+__global__ void kb_solve_init(const BatchProb *__restrict__ bp, int nprob, double tol, int max_cycles) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nprob) init_body(bp[i].scal, bp[i].flags, tol, max_cycles);
+}
+
+// colour (cx, cy) of period S; the tile grid of every problem covers the
+// grids of all colours, so tiles past the end of a colour's grid do nothing
+template <int P, int B, class T>
+__global__ void __launch_bounds__(1024) kb_colour(const BatchProb *__restrict__ bp, const int2 *__restrict__ map,
+                                                  int nbx, int nby, int cx, int cy, int S, int role_src, int role_dst,
+                                                  int role_rhs, int x_zero, int fuse) {
+    extern __shared__ unsigned char smem_raw[];
+    const int2 m = map[blockIdx.x];
+    const BatchProb &q = bp[m.x];
+    constexpr int HB = (B - 1) / 2;
+    int ox = cx - HB, oy = cy - HB;
+    if (ox > 0) ox -= S;
+    if (oy > 0) oy -= S;
+    const int bx = m.y % q.col_ntx, by = m.y / q.col_ntx;
+    if (ox + bx * nbx * S >= q.n1 || oy + by * nby * S >= q.n1) return;
+    constexpr int pr = prec_slot<T>();
+    colour_body<2, P, B, T>(static_cast<const T *>(q.val[pr]), q.npad, q.pitch1, 0, q.n1,
+                            static_cast<const T *>(q.inv[pr]), q.cls, q.ncls1, static_cast<const T *>(q.vec[role_src]),
+                            static_cast<T *>(q.vec[role_dst]), static_cast<const T *>(q.vec[role_rhs]), x_zero, ox, oy,
+                            0, S, nbx, nby, 1, static_cast<const T *>(q.cs[pr]), q.ulo, q.uhi, q.flags,
+                            fuse ? static_cast<const double *>(q.vec[kVecR64]) : nullptr, q.scal,
+                            fuse ? static_cast<T *>(q.vec[kVecRhsW]) : nullptr, bx, by, 0, smem_raw);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers --
@@ -734,5 +825,100 @@ void launch_block_inverse(Problem &Pb, const std::vector<int64_t> &reps, hipStre
     IGA2L_HIP(hipStreamSynchronize(s));
     IGA2L_REQUIRE(herr == 0, IGA2L_ENUMERIC, "a Schwarz block matrix is not positive definite");
 }
+
+// ------------------------------------------------------- batched launchers --
+void colour_tile_clamp(int S, int &nbx, int &nby) {
+    while (nbx * S * nby * S > 1024) {
+        if (nby > 1) --nby;
+        else if (nbx > 1) --nbx;
+        else break;
+    }
+}
+
+size_t colour_lds(int p, int S, int nbx, int nby, size_t elem) {
+    const size_t TX = size_t(nbx) * S, TY = size_t(nby) * S;
+    return ((TX + 2 * p) * (TY + 2 * p) + TX * TY) * elem;
+}
+
+template <int P, class T, bool NORM>
+void launch_residual_batch(const BatchProb *bp, const int2 *map, int nwg, int role_x, int role_b, int role_r,
+                           bool use_skip, hipStream_t s) {
+    using TS = TileShape<2, P>;
+    const size_t shm = size_t(TS::TX + 2 * P) * (TS::TY + 2 * P) * sizeof(T);
+    hipLaunchKernelGGL((kb_residual<P, T, NORM>), dim3(nwg), dim3(TS::TX * TS::TY), shm, s, bp, map, role_x, role_b,
+                       role_r, use_skip ? 1 : 0);
+}
+
+template <class T>
+void launch_residual_batch_dispatch(int p, const BatchProb *bp, const int2 *map, int nwg, int role_x, int role_b,
+                                    int role_r, bool norm, bool use_skip, hipStream_t s) {
+#define IGA2L_RB_CASE(PP)                                                                                 \
+    case PP:                                                                                              \
+        if (norm) launch_residual_batch<PP, T, true>(bp, map, nwg, role_x, role_b, role_r, use_skip, s);  \
+        else launch_residual_batch<PP, T, false>(bp, map, nwg, role_x, role_b, role_r, use_skip, s);      \
+        break;
+    switch (p) {
+        IGA2L_RB_CASE(1)
+        IGA2L_RB_CASE(2)
+        IGA2L_RB_CASE(3)
+        IGA2L_RB_CASE(4)
+        IGA2L_RB_CASE(5)
+        IGA2L_RB_CASE(6)
+        IGA2L_RB_CASE(7)
+        IGA2L_RB_CASE(8)
+        default: throw Error{IGA2L_EUNSUPPORTED, "degree out of range"};
+    }
+#undef IGA2L_RB_CASE
+}
+template void launch_residual_batch_dispatch<double>(int, const BatchProb *, const int2 *, int, int, int, int, bool,
+                                                     bool, hipStream_t);
+template void launch_residual_batch_dispatch<float>(int, const BatchProb *, const int2 *, int, int, int, int, bool,
+                                                    bool, hipStream_t);
+
+void launch_norm_finalize_batch(const BatchProb *bp, int nprob, bool scale_fp32, bool book, hipStream_t s) {
+    hipLaunchKernelGGL(kb_norm_finalize, dim3(nprob), dim3(256), 0, s, bp, scale_fp32 ? 1 : 0, book ? 1 : 0);
+}
+
+void launch_solve_init_batch(const BatchProb *bp, int nprob, double tol, int max_cycles, hipStream_t s) {
+    hipLaunchKernelGGL(kb_solve_init, dim3((nprob + 63) / 64), dim3(64), 0, s, bp, nprob, tol, max_cycles);
+}
+
+template <class T>
+void launch_colour_batch(const BatchProb *bp, const int2 *map, int nwg, int p, int bw, int nbx, int nby, int cx,
+                         int cy, int S, int role_src, int role_dst, int role_rhs, bool x_zero, bool fuse,
+                         hipStream_t s) {
+    const int threads = ((nbx * S * nby * S + kWave - 1) / kWave) * kWave;
+    const size_t shm = colour_lds(p, S, nbx, nby, sizeof(T));
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nwg), dim3(threads), shm, s, bp, map, nbx, nby, cx, cy, S, role_src, role_dst,
+                           role_rhs, x_zero ? 1 : 0, fuse ? 1 : 0);
+    };
+#define IGA2L_CB_P(PP)                                                           \
+    case PP:                                                                     \
+        switch (bw) {                                                            \
+            case 1: go(kb_colour<PP, 1, T>); break;                              \
+            case 3: go(kb_colour<PP, 3, T>); break;                              \
+            case 5: go(kb_colour<PP, 5, T>); break;                              \
+            case 7: go(kb_colour<PP, 7, T>); break;                              \
+            default: throw Error{IGA2L_EUNSUPPORTED, "block width must be 1, 3, 5 or 7"}; \
+        }                                                                        \
+        break;
+    switch (p) {
+        IGA2L_CB_P(1)
+        IGA2L_CB_P(2)
+        IGA2L_CB_P(3)
+        IGA2L_CB_P(4)
+        IGA2L_CB_P(5)
+        IGA2L_CB_P(6)
+        IGA2L_CB_P(7)
+        IGA2L_CB_P(8)
+        default: throw Error{IGA2L_EUNSUPPORTED, "degree out of range"};
+    }
+#undef IGA2L_CB_P
+}
+template void launch_colour_batch<double>(const BatchProb *, const int2 *, int, int, int, int, int, int, int, int,
+                                          int, int, int, bool, bool, hipStream_t);
+template void launch_colour_batch<float>(const BatchProb *, const int2 *, int, int, int, int, int, int, int, int, int,
+                                         int, int, bool, bool, hipStream_t);
 
 }  // namespace iga2l

@@ -168,11 +168,12 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
 // holds the smoothed iterate.  The input is (zero_src ? 0 : e_src) + P ec.
 // RESTRICT: additionally rc[I] = (P^T (rhs - A e))[I] for the coarse points I
 // whose centre child 2I+1 lies in the tile.
+// The body serves the single-problem kernel and the batched one (tile bx, by).
 template <class T, int NU, bool RESTRICT>
-__global__ void __launch_bounds__(256) k_rb_multi2(LevelDev<T> L, const T *__restrict__ e_src, int zero_src,
-                                                   const T *__restrict__ ec, int n1c_interp,
-                                                   const T *__restrict__ rhs, T *__restrict__ e_dst,
-                                                   T *__restrict__ rc, int n1c, const int *__restrict__ skip) {
+__device__ __forceinline__ void rb_multi2_body(const LevelDev<T> &L, const T *__restrict__ e_src, int zero_src,
+                                               const T *__restrict__ ec, int n1c_interp, const T *__restrict__ rhs,
+                                               T *__restrict__ e_dst, T *__restrict__ rc, int n1c,
+                                               const int *__restrict__ skip, int bx, int by) {
     constexpr int TX = 32, TY = 8;
     constexpr int H = 2 * NU + (RESTRICT ? 2 : 0);
     constexpr int HX = TX + 2 * H, HY = TY + 2 * H, NH = HX * HY;
@@ -180,8 +181,6 @@ __global__ void __launch_bounds__(256) k_rb_multi2(LevelDev<T> L, const T *__res
     __shared__ T rs[NH];
     const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     const int n1 = L.n1;
-    int bx, by;
-    xcd_tile_2d(bx, by);
     const int gx0 = bx * TX, gy0 = by * TY;
     for (int h = threadIdx.x; h < NH; h += blockDim.x) {
         const int hx = h % HX, hy = h / HX;
@@ -265,6 +264,33 @@ __global__ void __launch_bounds__(256) k_rb_multi2(LevelDev<T> L, const T *__res
         const int gx = gx0 + tx, gy = gy0 + ty;
         if (gx < n1 && gy < n1) e_dst[int64_t(gy) * n1 + gx] = E[(ty + H) * HX + (tx + H)];
     }
+}
+
+template <class T, int NU, bool RESTRICT>
+__global__ void __launch_bounds__(256) k_rb_multi2(LevelDev<T> L, const T *__restrict__ e_src, int zero_src,
+                                                   const T *__restrict__ ec, int n1c_interp,
+                                                   const T *__restrict__ rhs, T *__restrict__ e_dst,
+                                                   T *__restrict__ rc, int n1c, const int *__restrict__ skip) {
+    int bx, by;
+    xcd_tile_2d(bx, by);
+    rb_multi2_body<T, NU, RESTRICT>(L, e_src, zero_src, ec, n1c_interp, rhs, e_dst, rc, n1c, skip, bx, by);
+}
+
+// batched: pre-smoothing + residual restriction (RESTRICT) or prolongation +
+// post-smoothing of level l of every problem of the table
+template <class T, int NU, bool RESTRICT>
+__global__ void __launch_bounds__(256) kb_rb_multi2(const BatchLevel<T> *__restrict__ bl,
+                                                    const int2 *__restrict__ map, int zero_src) {
+    const int2 m = map[blockIdx.x];
+    const BatchLevel<T> &q = bl[m.x];
+    int bx, by;
+    xcd_relabel(m.y, q.ntx, q.ntx * q.nty, bx, by);
+    if constexpr (RESTRICT)
+        rb_multi2_body<T, NU, true>(q.L, static_cast<const T *>(nullptr), 1, static_cast<const T *>(nullptr), 0, q.rhs,
+                                    q.e_pre, q.rc, q.n1c, q.skip, bx, by);
+    else
+        rb_multi2_body<T, NU, false>(q.L, q.e_pre, zero_src, q.ecl, q.n1c, q.rhs, q.e_out, static_cast<T *>(nullptr),
+                                     0, q.skip, bx, by);
 }
 
 // e_dst = e_src + P ec (used only when no post-smoothing step follows)
@@ -379,11 +405,10 @@ struct BT<3> {
 };
 
 template <int D, class T>
-__global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, T> A, const T *__restrict__ rhs_top,
-                                                                  T *__restrict__ e_top, int nu1, int nu2,
-                                                                  const int *__restrict__ skip) {
+__device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, const T *__restrict__ rhs_top,
+                                                   T *__restrict__ e_top, int nu1, int nu2,
+                                                   const int *__restrict__ skip, unsigned char *smem_raw) {
     if (skip && *skip) return;
-    extern __shared__ unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     // LDS: for each level: e (padded), rhs (padded); then one residual scratch
     // (padded, level lb).  A padded level of n1 points per direction has
@@ -623,6 +648,24 @@ __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, 
 #undef IGA2L_FOR_POINTS
 }
 
+template <int D, class T>
+__global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, T> A, const T *__restrict__ rhs_top,
+                                                                  T *__restrict__ e_top, int nu1, int nu2,
+                                                                  const int *__restrict__ skip) {
+    extern __shared__ unsigned char smem_raw[];
+    vcycle_bottom_body<D, T>(A, rhs_top, e_top, nu1, nu2, skip, smem_raw);
+}
+
+// batched: one workgroup per problem of the table
+template <class T>
+__global__ void __launch_bounds__(kBottomThreads) kb_vcycle_bottom(const BatchBottom<T> *__restrict__ bb, int nu1,
+                                                                   int nu2) {
+    extern __shared__ unsigned char smem_raw[];
+    const BatchBottom<T> &q = bb[blockIdx.x];
+    const BottomArgs<2, T> a{q.nlev, q.levels};
+    vcycle_bottom_body<2, T>(a, q.rhs, q.e, nu1, nu2, q.skip, smem_raw);
+}
+
 template <class T>
 size_t bottom_level(const Problem &P) {
     return std::is_same<T, double>::value ? P.vc_bottom64 : P.vc_bottom32;
@@ -767,5 +810,37 @@ bool vcycle_bottom_fits(const Problem &P, size_t lb) {
     else ok = n1 <= BT<3>::X * BT<3>::KX && n1 <= BT<3>::Y * BT<3>::KY && n1 <= BT<3>::Z * BT<3>::KZ;
     return ok && P.levels.size() - lb <= 16;
 }
+
+// ------------------------------------------------------- batched launchers --
+template <class T>
+void launch_rb_multi2_batch(const BatchLevel<T> *bl, const int2 *map, int nwg, int nu, bool restrict_, bool zero_src,
+                            hipStream_t s) {
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), 0, s, bl, map, zero_src ? 1 : 0); };
+#define IGA2L_RBB(NU)                                   \
+    case NU:                                            \
+        if (restrict_) go(kb_rb_multi2<T, NU, true>);   \
+        else go(kb_rb_multi2<T, NU, false>);            \
+        break;
+    switch (nu) {
+        IGA2L_RBB(0)
+        IGA2L_RBB(1)
+        IGA2L_RBB(2)
+        IGA2L_RBB(3)
+        IGA2L_RBB(4)
+        default: throw Error{IGA2L_EUNSUPPORTED, "fused red-black steps support nu <= 4"};
+    }
+#undef IGA2L_RBB
+}
+template void launch_rb_multi2_batch<double>(const BatchLevel<double> *, const int2 *, int, int, bool, bool,
+                                             hipStream_t);
+template void launch_rb_multi2_batch<float>(const BatchLevel<float> *, const int2 *, int, int, bool, bool,
+                                            hipStream_t);
+
+template <class T>
+void launch_vcycle_bottom_batch(const BatchBottom<T> *bb, int nprob, size_t shm, int nu1, int nu2, hipStream_t s) {
+    hipLaunchKernelGGL((kb_vcycle_bottom<T>), dim3(nprob), dim3(kBottomThreads), shm, s, bb, nu1, nu2);
+}
+template void launch_vcycle_bottom_batch<double>(const BatchBottom<double> *, int, size_t, int, int, hipStream_t);
+template void launch_vcycle_bottom_batch<float>(const BatchBottom<float> *, int, size_t, int, int, hipStream_t);
 
 }  // namespace iga2l

@@ -51,3 +51,83 @@ def test_batch_equals_single_solves(precision):
         err = np.linalg.norm(us[k].cpu().numpy() - ref) / np.linalg.norm(ref)
         print(f"[batch] problem {k} (m={sp['m']}, p={sp['p']}): error vs oracle direct solve {err:.2e}")
         assert err < 1e-7
+
+
+def _single_vs_batch(G, probs, bs, opts, label):
+    us = [torch.zeros_like(b) for b in bs]
+    infos = G.solve_batch(probs, bs, us, opts)
+    for k, (pr, b) in enumerate(zip(probs, bs)):
+        u1, i1 = pr.solve(b, None, opts)
+        assert i1.iters == infos[k].iters, (label, k, i1.iters, infos[k].iters)
+        assert infos[k].relres == i1.relres, (label, k)
+        assert np.array_equal(infos[k].history, i1.history), (label, k)
+        assert torch.equal(u1, us[k]), (label, k, (u1 - us[k]).abs().max().item())
+    return us, infos
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_mixed_block_widths_and_depths(precision):
+    """Problems of block width 3 and 5 (colour periods 3 and 5), a grid deep
+    enough for two multi-workgroup V-cycle levels, constant and variable
+    kappa, and a zero right-hand side (converged before the first cycle)."""
+    G = _G()
+    prec = G.FP64 if precision == "fp64" else G.MIXED_FP32
+    opts = G.Opts(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2, tol=1e-10, precision=prec)
+    cases = [(2, 40, True), (5, 36, True), (3, 300, True), (6, 33, False), (4, 64, False), (2, 17, True)]
+    print("\n[case] batch (p, m, grf) =", cases, precision, flush=True)
+    probs, bs = [], []
+    for i, (p, m, grf) in enumerate(cases):
+        kap = synth.kappa_grf(2, m, 1.0, 0.1, seed=10 + i) if grf else None
+        probs.append(G.Problem(2, p, m, kappa=kap).setup(0, opts))
+        b = torch.tensor(synth.rhs_normal(2, p, m, seed=20 + i), device="cuda")
+        if i == 3:
+            b.zero_()
+        bs.append(b)
+    us, infos = _single_vs_batch(G, probs, bs, opts, precision)
+    assert infos[3].iters == 0 and float(us[3].abs().max()) == 0.0
+    for k in (0, 1, 2, 4, 5):
+        assert infos[k].relres <= 1e-10, (k, infos[k])
+    # a second call reuses the cached plan with other vectors
+    bs2 = [b.flip(0).contiguous() for b in bs]
+    _single_vs_batch(G, probs, bs2, opts, precision + "-again")
+
+
+def test_batch_options_nu1_zero_and_colour_period():
+    G = _G()
+    opts = G.Opts(coarse=G.COARSE_VCYCLE, nu1=0, nu2=3, tol=1e-9, colour_period=5, max_cycles=200)
+    cases = [(2, 48), (3, 130), (4, 70)]
+    print("\n[case] batch nu1=0 nu2=3 s=5", cases, flush=True)
+    probs = [G.Problem(2, p, m).setup(3, opts) for p, m in cases]
+    bs = [torch.tensor(synth.rhs_normal(2, p, m, seed=3 + i), device="cuda") for i, (p, m) in enumerate(cases)]
+    _single_vs_batch(G, probs, bs, opts, "nu1=0")
+
+
+def test_batch_not_converged_reports_error():
+    G = _G()
+    opts = G.Opts(coarse=G.COARSE_VCYCLE, nu1=1, nu2=1, tol=1e-14, max_cycles=3)
+    probs = [G.Problem(2, 3, m).setup(3, opts) for m in (32, 50)]
+    bs = [torch.tensor(synth.rhs_normal(2, 3, m, seed=1), device="cuda") for m in (32, 50)]
+    us = [torch.zeros_like(b) for b in bs]
+    with pytest.raises(G.IGA2LError) as ei:
+        G.solve_batch(probs, bs, us, opts)
+    assert ei.value.code == G.ENOTCONV
+    # the partial iterates equal three cycles of the single solve
+    for pr, b, u in zip(probs, bs, us):
+        u1 = torch.zeros_like(b)
+        _, info = pr.solve(b, u1, opts, raise_on_notconv=False)
+        assert info.iters == 3
+        assert torch.equal(u1, u)
+
+
+def test_batch_fallback_paths():
+    """Batches outside the batched launcher's scope (lexicographic order,
+    3-D) run problem by problem and still match the single solves."""
+    G = _G()
+    lex = G.Opts(ordering=G.LEX, coarse=G.COARSE_VCYCLE, nu1=1, nu2=1, tol=1e-9)
+    probs = [G.Problem(2, p, m).setup(3, lex) for p, m in ((2, 16), (3, 20))]
+    bs = [torch.tensor(synth.rhs_normal(2, pr.p, pr.m, seed=5), device="cuda") for pr in probs]
+    _single_vs_batch(G, probs, bs, lex, "lex")
+    col3 = G.Opts(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2, tol=1e-9)
+    probs3 = [G.Problem(3, 2, m).setup(3, col3) for m in (8, 12)]
+    bs3 = [torch.tensor(synth.rhs_normal(3, 2, m, seed=6), device="cuda") for m in (8, 12)]
+    _single_vs_batch(G, probs3, bs3, col3, "3d")
