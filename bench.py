@@ -49,6 +49,8 @@ def parse():
                     help="after the headline line, print one JSON line per other configuration")
     ap.add_argument("--only-large", action="store_true",
                     help="run only the bandwidth-regime roofline leg (for hardware-counter profiles)")
+    ap.add_argument("--only-config", default="",
+                    help="comma-separated configurations of the suite (C1..C5) to run alone (for profiles)")
     return ap.parse_args()
 
 
@@ -158,6 +160,11 @@ def main():
 
     if args.only_large:
         print(json.dumps({"roofline_large": roofline_large(torch, G, args.large_m)}), flush=True)
+        return
+    if args.only_config:
+        import bench_suite
+        for line in bench_suite.run(torch, G, steps=max(3, args.steps // 2), only=set(args.only_config.split(","))):
+            print(json.dumps(line), flush=True)
         return
     d, p, m = 2, args.p, args.m
     nu = (2, 2)

@@ -50,21 +50,36 @@ def _solve_line(torch, G, name, d, p, m, opts_list, steps, kappa=None, block_wid
     return line
 
 
-def run(torch, G, steps=5):
+def run(torch, G, steps=5, only=None):
+    """One record per configuration; only: names of the configurations to run (all if None)."""
     lines = []
     v22 = dict(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2, tol=1e-10)
+
+    def want(name):
+        return only is None or name in only
+
     # C1
-    lines.append(_solve_line(torch, G, "C1", 2, 3, 32,
-                             {"fp64_lex_direct": G.Opts(ordering=G.LEX, coarse=G.COARSE_DIRECT, tol=1e-10)}, steps))
+    if want("C1"):
+        lines.append(_solve_line(torch, G, "C1", 2, 3, 32,
+                                 {"fp64_lex_direct": G.Opts(ordering=G.LEX, coarse=G.COARSE_DIRECT, tol=1e-10)},
+                                 steps))
     # C2 sweep over p
-    for p in (2, 3, 4, 5):
+    for p in ((2, 3, 4, 5) if want("C2") else ()):
         lines.append(_solve_line(torch, G, "C2", 2, p, 256,
                                  {"fp64": G.Opts(**v22), "mixed": G.Opts(precision=G.MIXED_FP32, **v22)}, steps))
     # C3
-    lines.append(_solve_line(torch, G, "C3", 3, 3, 64,
-                             {"fp64": G.Opts(**v22), "mixed": G.Opts(precision=G.MIXED_FP32, **v22)},
-                             max(2, steps // 2)))
-    # C4
+    if want("C3"):
+        lines.append(_solve_line(torch, G, "C3", 3, 3, 64,
+                                 {"fp64": G.Opts(**v22), "mixed": G.Opts(precision=G.MIXED_FP32, **v22)},
+                                 max(2, steps // 2)))
+    if want("C4"):
+        lines.append(_c4(torch, G, v22))
+    if want("C5"):
+        lines.append(_c5(torch, G))
+    return lines
+
+
+def _c4(torch, G, v22):
     specs = synth.batch_specs(256, seed=4)
     t0 = time.perf_counter()
     probs, bs = [], []
@@ -96,16 +111,18 @@ def run(torch, G, steps=5):
     t_seq, _ = _timed(torch, one_by_one, 1)
     ndof = sum(p.n for p in probs)
     cyc = sum(p.n * i.iters for p, i in zip(probs, infos))
-    lines.append({"config": "C4", "problems": len(probs), "total_fine_dofs": ndof, "setup_s": t_setup,
-                  "mixed": {"time_to_tol_ms": 1e3 * t_mixed, "max_cycles": max(i.iters for i in infos),
-                            "worst_relres": max(i.relres for i in infos),
-                            "fine_dof_cycles_per_s": cyc / t_mixed},
-                  "fp64": {"time_to_tol_ms": 1e3 * t_fp64, "max_cycles": max(i.iters for i in infos64),
-                           "worst_relres": max(i.relres for i in infos64)},
-                  "mixed_one_problem_at_a_time_ms": 1e3 * t_seq})
+    rec = {"config": "C4", "problems": len(probs), "total_fine_dofs": ndof, "setup_s": t_setup,
+           "mixed": {"time_to_tol_ms": 1e3 * t_mixed, "max_cycles": max(i.iters for i in infos),
+                     "worst_relres": max(i.relres for i in infos), "fine_dof_cycles_per_s": cyc / t_mixed},
+           "fp64": {"time_to_tol_ms": 1e3 * t_fp64, "max_cycles": max(i.iters for i in infos64),
+                    "worst_relres": max(i.relres for i in infos64)},
+           "mixed_one_problem_at_a_time_ms": 1e3 * t_seq}
     for pr in probs:
         pr.close()
-    # C5
+    return rec
+
+
+def _c5(torch, G):
     d, p, m = 2, 4, 256
     kap = synth.kappa_grf(d, m, 0.5, 0.05, seed=1)
     kap_obs = synth.kappa_grf(d, m, 0.5, 0.05, seed=2)
@@ -124,9 +141,8 @@ def run(torch, G, steps=5):
         return loss
 
     t, _ = _timed(torch, fb, 2)
-    lines.append({"config": "C5", "dim": d, "p": p, "m": m,
-                  "forward_backward_ms_incl_assembly": 1e3 * t,
-                  "note": "assembly + set-up of A(kappa), mixed forward solve, FP64 adjoint solve to 1e-12, "
-                          "dL/dkappa kernel"})
+    rec = {"config": "C5", "dim": d, "p": p, "m": m, "forward_backward_ms_incl_assembly": 1e3 * t,
+           "note": "assembly + set-up of A(kappa), mixed forward solve, FP64 adjoint solve to 1e-12, "
+                   "dL/dkappa kernel"}
     obs.close()
-    return lines
+    return rec

@@ -348,6 +348,7 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
         if (!P.blocks_ready || P.bw != bw) {
             P.blocks_ready = false;
             P.fp32_ready = false;
+            P.tuned[0] = P.tuned[1] = false;
             P.bw = bw;
             P.bd = 1;
             for (int k = 0; k < P.dim; ++k) P.bd *= bw;
@@ -381,6 +382,16 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             host_build_dst(P);
         }
         IGA2L_HIP(hipDeviceSynchronize());
+        // tile shapes of the coloured sweep, timed once per working precision
+        const int S = o.colour_period ? o.colour_period : P.bw;
+        if (P.dim == 2 && !P.tuned[0]) {
+            autotune_colour_tile<double>(P, S, s);
+            P.tuned[0] = true;
+        }
+        if (P.dim == 2 && P.fp32_ready && !P.tuned[1]) {
+            autotune_colour_tile<float>(P, S, s);
+            P.tuned[1] = true;
+        }
         P.layout_id = next_layout_id();
     });
 }

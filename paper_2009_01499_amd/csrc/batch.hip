@@ -149,6 +149,74 @@ void build_vcycle(Plan &pl, const std::vector<Problem *> &probs) {
     IGA2L_HIP(hipMemcpy(pl.bottom_args.ptr, bb.data(), bb.size() * sizeof(BatchBottom<T>), hipMemcpyHostToDevice));
 }
 
+// colour tiles of a group for the shape (nbx, nby): per-problem tile grids
+// covering every colour, and the workgroup map
+void colour_layout(Plan &pl, Group &g, const std::vector<int> &members) {
+    std::vector<int2> cm;
+    for (int k : members) {
+        BatchProb &q = pl.host_table[k];
+        q.col_ntx = cdiv(q.n1 + g.S - 1, g.nbx * g.S);
+        q.col_nty = cdiv(q.n1 + g.S - 1, g.nby * g.S);
+        for (int t = 0; t < q.col_ntx * q.col_nty; ++t) cm.push_back(make_int2(k, t));
+    }
+    g.col_map = upload_map(cm);
+    g.col_nwg = int(cm.size());
+}
+
+// Autotuner of the batched coloured sweep: every candidate tile shape runs
+// one colour of the whole group on its own workspaces (numerics-neutral: a
+// point's arithmetic does not depend on the tile); the fastest is kept.
+void tune_group(Plan &pl, Group &g, const std::vector<int> &members, bool fp32) {
+    int n1max = 0;
+    for (int k : members) n1max = std::max(n1max, pl.host_table[k].n1);
+    auto cands = colour_tile_candidates(g.S, n1max);
+    hipEvent_t e0, e1;
+    IGA2L_HIP(hipEventCreate(&e0));
+    IGA2L_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bx = 4, by = 4;
+    colour_tile_clamp(g.S, bx, by);
+    const int rhs_role = fp32 ? kVecRhsW : kVecR64;
+    const BatchProb *tb = pl.table.as<BatchProb>();
+    auto launch = [&]() {
+        if (fp32)
+            launch_colour_batch<float>(tb, g.col_map.as<int2>(), g.col_nwg, g.p, g.bw, g.nbx, g.nby, 1 % g.S, 1 % g.S,
+                                       g.S, kVecE0, kVecE1, rhs_role, false, false, nullptr, false);
+        else
+            launch_colour_batch<double>(tb, g.col_map.as<int2>(), g.col_nwg, g.p, g.bw, g.nbx, g.nby, 1 % g.S,
+                                        1 % g.S, g.S, kVecE0, kVecE1, rhs_role, false, false, nullptr, false);
+    };
+    try {
+        for (auto [cbx, cby] : cands) {
+            g.nbx = cbx;
+            g.nby = cby;
+            colour_layout(pl, g, members);
+            IGA2L_HIP(hipMemcpy(pl.table.ptr, pl.host_table, pl.nprob * sizeof(BatchProb), hipMemcpyHostToDevice));
+            launch();
+            IGA2L_HIP(hipEventRecord(e0, nullptr));
+            for (int r = 0; r < 3; ++r) launch();
+            IGA2L_HIP(hipEventRecord(e1, nullptr));
+            IGA2L_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            IGA2L_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bx = cbx;
+                by = cby;
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g.nbx = bx;
+    g.nby = by;
+    colour_layout(pl, g, members);
+}
+
 std::unique_ptr<Plan> build_plan(const std::vector<Problem *> &probs, const iga2l_opts &o) {
     auto pl = std::make_unique<Plan>();
     const int n = int(probs.size());
@@ -219,34 +287,24 @@ std::unique_ptr<Plan> build_plan(const std::vector<Problem *> &probs, const iga2
         expected = std::max(expected, P.expected_cycles);
     }
     pl->expected_cycles = expected;
+    pl->table.alloc(n * sizeof(BatchProb));
     for (auto &kv : group_of) {
         Group g;
         std::tie(g.p, g.bw, g.S) = kv.first;
-        const Problem &P0 = *probs[kv.second[0]];
-        g.nbx = P0.tile_bx;
-        g.nby = P0.tile_by;
-        colour_tile_clamp(g.S, g.nbx, g.nby);
-        IGA2L_REQUIRE(g.nbx * g.S * g.nby * g.S <= 1024, IGA2L_EUNSUPPORTED,
-                      "colour period too large for one workgroup");
-        std::vector<int2> rm, cm;
+        std::vector<int2> rm;
         for (int k : kv.second) {
-            BatchProb &q = pl->host_table[k];
-            q.col_ntx = cdiv(q.n1 + g.S - 1, g.nbx * g.S);
-            q.col_nty = cdiv(q.n1 + g.S - 1, g.nby * g.S);
+            const BatchProb &q = pl->host_table[k];
             for (int t = 0; t < q.res_ntx * q.res_nty; ++t) rm.push_back(make_int2(k, t));
-            for (int t = 0; t < q.col_ntx * q.col_nty; ++t) cm.push_back(make_int2(k, t));
         }
         g.res_map = upload_map(rm);
         g.res_nwg = int(rm.size());
-        g.col_map = upload_map(cm);
-        g.col_nwg = int(cm.size());
+        tune_group(*pl, g, kv.second, fp32);
         pl->groups.push_back(std::move(g));
     }
     pl->tr_map = upload_map(tr_map);
     pl->tr_nwg = int(tr_map.size());
     pl->pr_map = upload_map(pr_map);
     pl->pr_nwg = int(pr_map.size());
-    pl->table.alloc(n * sizeof(BatchProb));
     if (fp32) build_vcycle<float>(*pl, probs);
     else build_vcycle<double>(*pl, probs);
     pl->status_stride = kScalCount + kFlagCount / 2 + pl->hist_cap;

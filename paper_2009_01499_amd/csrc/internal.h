@@ -173,8 +173,10 @@ struct Problem {
         if (host_status) (void)hipHostFree(host_status);
     }
 
-    // tuning knobs (numerics-neutral)
-    int tile_bx = 4, tile_by = 4, tile_bz = 1;   // Schwarz tile in blocks
+    // tuning knobs (numerics-neutral): Schwarz tile in blocks, per working
+    // precision ([0] FP64, [1] FP32); 2-D shapes are chosen by the autotuner
+    int tile_bx[2] = {4, 4}, tile_by[2] = {4, 4}, tile_bz = 1;
+    bool tuned[2] = {false, false};
 
     // identifies the device layout (buffers, levels, set-up state); renewed
     // whenever it changes, never reused, so cached batch plans can tell
@@ -263,7 +265,7 @@ void launch_solve_init_batch(const BatchProb *bp, int nprob, double tol, int max
 template <class T>
 void launch_colour_batch(const BatchProb *bp, const int2 *map, int nwg, int p, int bw, int nbx, int nby, int cx,
                          int cy, int S, int role_src, int role_dst, int role_rhs, bool x_zero, bool fuse,
-                         hipStream_t s);
+                         hipStream_t s, bool use_skip = true);
 template <class T>
 void launch_residual_batch_dispatch(int p, const BatchProb *bp, const int2 *map, int nwg, int role_x, int role_b,
                                     int role_r, bool norm, bool use_skip, hipStream_t s);
@@ -317,6 +319,12 @@ template <class T>
 void launch_colour_step(const Problem &P, int cx, int cy, int cz, int s_period, const T *x_src, T *x_dst,
                         const T *rhs, bool x_zero, hipStream_t s, const double *r64 = nullptr, T *rhs_out = nullptr);
 void launch_lex_step(const Problem &P, int step, double *u, const double *b, hipStream_t s);
+// times the coloured Schwarz kernel for candidate tile shapes on the problem's
+// own workspaces (2-D) and keeps the fastest in P.tile_bx / P.tile_by
+template <class T>
+void autotune_colour_tile(Problem &P, int S, hipStream_t s);
+// candidate tile shapes (blocks per tile in x, y) for a colour period S
+std::vector<std::pair<int, int>> colour_tile_candidates(int S, int n1);
 template <class T>
 void launch_cast_scale(const Problem &P, const double *r64, T *rhs, hipStream_t s);
 // 2-D bandwidth-oriented variants (kernels_2d.hip)

@@ -590,10 +590,12 @@ void defect_dp(const Problem &Pb, const T *e, const T *rhs, T *d, hipStream_t s)
 
 template <int D, int P, int B, class T>
 void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs,
-                   bool x_zero, const double *r64, T *rhs_out, hipStream_t s) {
+                   bool x_zero, const double *r64, T *rhs_out, hipStream_t s, int tile_nbx = 0, int tile_nby = 0) {
     const int n1 = Pb.fine.n1;
     constexpr int HB = (B - 1) / 2;
-    int nbx = Pb.tile_bx, nby = Pb.tile_by, nbz = (D == 3) ? Pb.tile_bz : 1;
+    constexpr int pr = std::is_same<T, double>::value ? 0 : 1;
+    int nbx = tile_nbx >= 1 ? tile_nbx : Pb.tile_bx[pr], nby = tile_nby >= 1 ? tile_nby : Pb.tile_by[pr];
+    int nbz = (D == 3) ? Pb.tile_bz : 1;
     // keep the tile within one workgroup of at most 1024 threads
     while (nbx * S * nby * S * ((D == 3) ? nbz * S : 1) > 1024) {
         if (nby > 1) --nby;
@@ -624,18 +626,18 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
 
 template <int D, int P, class T>
 void colour_dp(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs, bool x_zero,
-               const double *r64, T *rhs_out, hipStream_t s) {
+               const double *r64, T *rhs_out, hipStream_t s, int nbx = 0, int nby = 0) {
     switch (Pb.bw) {
-        case 1: colour_launch<D, P, 1, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s); break;
-        case 3: colour_launch<D, P, 3, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s); break;
+        case 1: colour_launch<D, P, 1, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s, nbx, nby); break;
+        case 3: colour_launch<D, P, 3, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s, nbx, nby); break;
         case 5:
             if constexpr (D == 2)
-                colour_launch<D, P, 5, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s);
+                colour_launch<D, P, 5, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s, nbx, nby);
             else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
             break;
         case 7:
             if constexpr (D == 2)
-                colour_launch<D, P, 7, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s);
+                colour_launch<D, P, 7, T>(Pb, cx, cy, cz, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, s, nbx, nby);
             else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
             break;
         default: throw Error{IGA2L_EUNSUPPORTED, "block width must be 1, 3, 5 or 7"};
@@ -705,7 +707,7 @@ __global__ void kb_solve_init(const BatchProb *__restrict__ bp, int nprob, doubl
 template <int P, int B, class T>
 __global__ void __launch_bounds__(1024) kb_colour(const BatchProb *__restrict__ bp, const int2 *__restrict__ map,
                                                   int nbx, int nby, int cx, int cy, int S, int role_src, int role_dst,
-                                                  int role_rhs, int x_zero, int fuse) {
+                                                  int role_rhs, int x_zero, int fuse, int use_skip) {
     extern __shared__ unsigned char smem_raw[];
     const int2 m = map[blockIdx.x];
     const BatchProb &q = bp[m.x];
@@ -719,7 +721,8 @@ __global__ void __launch_bounds__(1024) kb_colour(const BatchProb *__restrict__ 
     colour_body<2, P, B, T>(static_cast<const T *>(q.val[pr]), q.npad, q.pitch1, 0, q.n1,
                             static_cast<const T *>(q.inv[pr]), q.cls, q.ncls1, static_cast<const T *>(q.vec[role_src]),
                             static_cast<T *>(q.vec[role_dst]), static_cast<const T *>(q.vec[role_rhs]), x_zero, ox, oy,
-                            0, S, nbx, nby, 1, static_cast<const T *>(q.cs[pr]), q.ulo, q.uhi, q.flags,
+                            0, S, nbx, nby, 1, static_cast<const T *>(q.cs[pr]), q.ulo, q.uhi,
+                            use_skip ? q.flags : nullptr,
                             fuse ? static_cast<const double *>(q.vec[kVecR64]) : nullptr, q.scal,
                             fuse ? static_cast<T *>(q.vec[kVecRhsW]) : nullptr, bx, by, 0, smem_raw);
 }
@@ -886,12 +889,12 @@ void launch_solve_init_batch(const BatchProb *bp, int nprob, double tol, int max
 template <class T>
 void launch_colour_batch(const BatchProb *bp, const int2 *map, int nwg, int p, int bw, int nbx, int nby, int cx,
                          int cy, int S, int role_src, int role_dst, int role_rhs, bool x_zero, bool fuse,
-                         hipStream_t s) {
+                         hipStream_t s, bool use_skip) {
     const int threads = ((nbx * S * nby * S + kWave - 1) / kWave) * kWave;
     const size_t shm = colour_lds(p, S, nbx, nby, sizeof(T));
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(nwg), dim3(threads), shm, s, bp, map, nbx, nby, cx, cy, S, role_src, role_dst,
-                           role_rhs, x_zero ? 1 : 0, fuse ? 1 : 0);
+                           role_rhs, x_zero ? 1 : 0, fuse ? 1 : 0, use_skip ? 1 : 0);
     };
 #define IGA2L_CB_P(PP)                                                           \
     case PP:                                                                     \
@@ -917,8 +920,73 @@ void launch_colour_batch(const BatchProb *bp, const int2 *map, int nwg, int p, i
 #undef IGA2L_CB_P
 }
 template void launch_colour_batch<double>(const BatchProb *, const int2 *, int, int, int, int, int, int, int, int,
-                                          int, int, int, bool, bool, hipStream_t);
+                                          int, int, int, bool, bool, hipStream_t, bool);
 template void launch_colour_batch<float>(const BatchProb *, const int2 *, int, int, int, int, int, int, int, int, int,
-                                         int, int, bool, bool, hipStream_t);
+                                         int, int, bool, bool, hipStream_t, bool);
+
+// -------------------------------------------------------------- autotuner --
+std::vector<std::pair<int, int>> colour_tile_candidates(int S, int n1) {
+    static const int shapes[][2] = {{4, 4}, {8, 2}, {8, 4}, {16, 1}, {16, 2}, {16, 4}, {32, 1}, {32, 2},
+                                    {4, 8},  {2, 16}, {11, 3}, {22, 2}};
+    std::vector<std::pair<int, int>> out;
+    const int cells = (n1 + 2 * S - 1) / S;   // cells a colour's grid spans per direction
+    for (auto &sh : shapes) {
+        const int bx = sh[0], by = sh[1];
+        if (bx * S * by * S > 1024 || bx * S * by * S < 64) continue;
+        if (bx > cells + 1 && !(bx == 4 && by == 4)) continue;   // wider than the grid
+        out.emplace_back(bx, by);
+    }
+    return out;
+}
+
+template <class T>
+void autotune_colour_tile(Problem &Pb, int S, hipStream_t s) {
+    if (Pb.dim != 2) return;
+    constexpr int pr = std::is_same<T, double>::value ? 0 : 1;
+    const T *rhs = std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.r64.ptr)
+                                                  : reinterpret_cast<const T *>(Pb.rhs_w.ptr);
+    const T *src = Pb.ework[0].as<T>();
+    T *dst = Pb.ework[1].as<T>();
+    const int *saved = Pb.skip;
+    Pb.skip = nullptr;
+    hipEvent_t e0, e1;
+    IGA2L_HIP(hipEventCreate(&e0));
+    IGA2L_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bbx = Pb.tile_bx[pr], bby = Pb.tile_by[pr];
+    const int reps = 3;
+    try {
+        for (auto [cbx, cby] : colour_tile_candidates(S, Pb.fine.n1)) {
+            // the middle colour; warm-up launch, then timed launches
+            IGA2L_DISPATCH_P2(colour_dp, Pb, 1, 1, 0, S, src, dst, rhs, false, nullptr, static_cast<T *>(nullptr), s,
+                              cbx, cby);
+            IGA2L_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r)
+                IGA2L_DISPATCH_P2(colour_dp, Pb, 1, 1, 0, S, src, dst, rhs, false, nullptr,
+                                  static_cast<T *>(nullptr), s, cbx, cby);
+            IGA2L_HIP(hipEventRecord(e1, s));
+            IGA2L_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            IGA2L_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bbx = cbx;
+                bby = cby;
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        Pb.skip = saved;
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    Pb.skip = saved;
+    Pb.tile_bx[pr] = bbx;
+    Pb.tile_by[pr] = bby;
+}
+template void autotune_colour_tile<double>(Problem &, int, hipStream_t);
+template void autotune_colour_tile<float>(Problem &, int, hipStream_t);
 
 }  // namespace iga2l

@@ -116,6 +116,14 @@ void element_matrices(int p, int m, std::vector<std::vector<double>> &Ke, std::v
                 }
         }
     }
+    // Elements p .. m-1-p carry only cardinal (translated) B-splines, so their
+    // matrices are equal in exact arithmetic; one copy for all of them makes
+    // the assembled interior rows exact translates of each other, bit for bit
+    // (the interior stencil then equals every interior row of the operator).
+    for (int e = p + 1; e <= m - 1 - p; ++e) {
+        Ke[e] = Ke[p];
+        Me[e] = Me[p];
+    }
 }
 
 // linear index <-> multi-index over a box of extent n in each of dim directions
