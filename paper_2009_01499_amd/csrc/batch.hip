@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdio>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -199,6 +200,9 @@ void tune_group(Plan &pl, Group &g, const std::vector<int> &members, bool fp32) 
             IGA2L_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
             IGA2L_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (tune_log())
+                std::fprintf(stderr, "[iga2l tune] batch p=%d b=%d s=%d %d problems: tile %dx%d blocks %.2f us\n", g.p,
+                             g.bw, g.S, int(members.size()), cbx, cby, 1e3f * ms / 3);
             if (ms < best) {
                 best = ms;
                 bx = cbx;

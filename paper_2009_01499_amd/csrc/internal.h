@@ -323,6 +323,8 @@ void launch_lex_step(const Problem &P, int step, double *u, const double *b, hip
 // own workspaces (2-D) and keeps the fastest in P.tile_bx / P.tile_by
 template <class T>
 void autotune_colour_tile(Problem &P, int S, hipStream_t s);
+// IGA2L_TUNE_LOG=1 in the environment: the autotuners print their timings to stderr
+bool tune_log();
 // candidate tile shapes (blocks per tile in x, y) for a colour period S
 std::vector<std::pair<int, int>> colour_tile_candidates(int S, int n1);
 template <class T>

@@ -5,6 +5,8 @@
 // Schwarz block matrices and the deterministic residual norm.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
 #include <type_traits>
 
 #include "internal.h"
@@ -14,6 +16,8 @@ namespace iga2l {
 namespace {
 
 constexpr int kWave = 64;
+// at most 512 threads per Schwarz tile: 256 VGPRs per lane, no spills for 7x7 blocks
+constexpr int kColourThreads = 512;
 
 __host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
 
@@ -31,12 +35,11 @@ __device__ __forceinline__ T dia_entry(const T *__restrict__ val, int64_t npad, 
 
 // ------------------------------------------------------------------------
 // Interior rows of the kappa = 1 operator are translation invariant: rows whose
-// coordinates all lie in [ulo, uhi] carry the (2p+1)^d stencil cs.  A
-// workgroup whose whole tile is such rows reads cs (uniform addresses) instead
-// of the diagonals.
-__device__ __forceinline__ bool tile_uniform(int lo0, int hi0, int lo1, int hi1, int lo2, int hi2, int ulo, int uhi,
-                                             int dim) {
-    return lo0 >= ulo && hi0 <= uhi && lo1 >= ulo && hi1 <= uhi && (dim == 2 || (lo2 >= ulo && hi2 <= uhi));
+// coordinates all lie in [ulo, uhi] carry the (2p+1)^d stencil cs (bit for
+// bit: the interior element matrices are one copy).  Such rows read cs
+// (uniform addresses) instead of the diagonals.
+__device__ __forceinline__ bool point_uniform(int x, int y, int z, int ulo, int uhi, int dim) {
+    return x >= ulo && x <= uhi && y >= ulo && y <= uhi && (dim == 2 || (z >= ulo && z <= uhi));
 }
 
 // Residual r = b - A x over tiles of TX x TY (x TZ) points; x staged in LDS
@@ -55,23 +58,24 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
     const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
     const int gx0 = bx * TX, gy0 = by * TY, gz0 = (D == 3) ? bz * TZ : 0;
     const int nh = HX * HY * HZ;
-    for (int h = threadIdx.x; h < nh; h += blockDim.x) {
-        int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-        int gx = gx0 + hx - P, gy = gy0 + hy - P, gz = (D == 3) ? gz0 + hz - P : 0;
-        bool in = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
-        xs[h] = in ? x[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
-    }
-    __syncthreads();
-    const bool uni = cs != nullptr &&
-                     tile_uniform(gx0, min(gx0 + TX, n1) - 1, gy0, min(gy0 + TY, n1) - 1, gz0,
-                                  min(gz0 + TZ, n1) - 1, ulo, uhi, D);
     const int t = threadIdx.x;
     const int tx = t % TX, ty = (t / TX) % TY, tz = (D == 3) ? t / (TX * TY) : 0;
     const int gx = gx0 + tx, gy = gy0 + ty, gz = gz0 + tz;
     const bool active = t < TX * TY * ((D == 3) ? TZ : 1) && gx < n1 && gy < n1 && (D == 2 || gz < n1);
+    const int64_t gi = active ? (int64_t(gz) * n1 + gy) * n1 + gx : 0;
+    const T bv = active ? b[gi] : T(0);   // issued with the halo loads
+    for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+        int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        int hgx = gx0 + hx - P, hgy = gy0 + hy - P, hgz = (D == 3) ? gz0 + hz - P : 0;
+        bool in = hgx >= 0 && hgx < n1 && hgy >= 0 && hgy < n1 && (D == 2 || (hgz >= 0 && hgz < n1));
+        xs[h] = in ? x[(int64_t(hgz) * n1 + hgy) * n1 + hgx] : T(0);
+    }
+    __syncthreads();
+    // rows of the interior stencil read it instead of the diagonals (per point:
+    // only the rows next to the boundary of the grid read the operator)
+    const bool uni = cs != nullptr && point_uniform(gx, gy, gz, ulo, uhi, D);
     double rr = 0.0;
     if (active) {
-        const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
         const int64_t padi = int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
         const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
         T acc = T(0);
@@ -116,7 +120,7 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
                         }
             }
         }
-        const T res = b[gi] - acc;
+        const T res = bv - acc;
         if (stop) return;
         r[gi] = res;
         rr = double(res) * double(res);
@@ -162,7 +166,7 @@ __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int
 // points between blocks are copied unchanged.
 // The body serves the single-problem kernel and the batched one: tile
 // (tbx, tby, tbz) of the colour, smem = LDS of the tile.
-template <int D, int P, int B, class T>
+template <int D, int P, int B, class T, bool PRE>
 __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2, int n1,
                                             const T *__restrict__ inv, const int *__restrict__ cls, int ncls1,
                                             const T *__restrict__ x_src, T *__restrict__ x_dst,
@@ -185,36 +189,60 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
     T *rs = xs + HX * HY * HZ;
     const int gx0 = ox + tbx * TX, gy0 = oy + tby * TY, gz0 = (D == 3) ? oz + tbz * TZ : 0;
     const int nh = HX * HY * HZ;
-    if (!x_zero) {
-        for (int h = threadIdx.x; h < nh; h += blockDim.x) {
-            int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-            int gx = gx0 + hx - P, gy = gy0 + hy - P, gz = (D == 3) ? gz0 + hz - P : 0;
-            bool in = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
-            xs[h] = in ? x_src[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
-        }
-        __syncthreads();
-    }
+    // this thread's point, its block and the data it reads from global memory
+    // besides the halo: issued first, so that one memory latency covers them
+    // and the halo
     const int t = threadIdx.x;
     const int ntile = TX * TY * TZ;
     const int tx = t % TX, ty = (t / TX) % TY, tz = (D == 3) ? t / (TX * TY) : 0;
     const int gx = gx0 + tx, gy = gy0 + ty, gz = gz0 + tz;
     const bool mine = t < ntile && gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
-    const bool uni = cs != nullptr && tile_uniform(max(gx0, 0), min(gx0 + TX, n1) - 1, max(gy0, 0),
-                                                   min(gy0 + TY, n1) - 1, max(gz0, 0), min(gz0 + TZ, n1) - 1, ulo,
-                                                   uhi, D);
-    const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
     // position inside the cell; points outside the block part are not in any block of this colour
     const int cx = tx % S, cy = ty % S, cz = (D == 3) ? tz % S : 0;
     const bool in_block = cx < B && cy < B && (D == 2 || cz < B);
+    const int bx = tx / S, by = ty / S, bz = (D == 3) ? tz / S : 0;
+    const int ccx = gx0 + bx * S + HB, ccy = gy0 + by * S + HB, ccz = (D == 3) ? gz0 + bz * S + HB : 0;
+    const bool covered = in_block && ccx >= 0 && ccx < n1 && ccy >= 0 && ccy < n1 &&
+                         (D == 2 || (ccz >= 0 && ccz < n1));
+    const int64_t gi = mine ? (int64_t(gz) * n1 + gy) * n1 + gx : 0;
+    T rhs_v = T(0);
+    double r64_v = 0.0;
+    if (mine && in_block && !r64) rhs_v = rhs[gi];
+    if (mine && r64) r64_v = r64[gi];
+    // row loc of the block inverse (PRE: held in registers when it is short,
+    // for latency-bound launches; batched launches keep the registers free)
+    constexpr bool kPreRow = PRE && BD * sizeof(T) <= 128;
+    constexpr int NR = kPreRow ? BD : 1;
+    T irow[NR];
+    const T *row = nullptr;
+    if (mine && covered) {
+        int64_t slot = cls[ccx] + int64_t(ncls1) * cls[ccy];
+        if (D == 3) slot += int64_t(ncls1) * ncls1 * cls[ccz];
+        const int loc = cx + B * cy + ((D == 3) ? B * B * cz : 0);
+        row = inv + (slot * BD + loc) * BD;
+        if constexpr (kPreRow) {
+#pragma unroll
+            for (int l = 0; l < BD; ++l) irow[l] = row[l];
+        }
+    }
+    if (!x_zero) {
+        for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+            int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+            int hgx = gx0 + hx - P, hgy = gy0 + hy - P, hgz = (D == 3) ? gz0 + hz - P : 0;
+            bool in = hgx >= 0 && hgx < n1 && hgy >= 0 && hgy < n1 && (D == 2 || (hgz >= 0 && hgz < n1));
+            xs[h] = in ? x_src[(int64_t(hgz) * n1 + hgy) * n1 + hgx] : T(0);
+        }
+        __syncthreads();
+    }
+    const bool uni = cs != nullptr && point_uniform(gx, gy, gz, ulo, uhi, D);
+    const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
     T res = T(0);
     T cast_rhs = T(0);
-    int64_t gi = 0;
     if (mine) {
-        gi = (int64_t(gz) * n1 + gy) * n1 + gx;
-        if (r64) cast_rhs = T(r64[gi] * scal[kScalInvSigma]);
+        if (r64) cast_rhs = T(r64_v * scal[kScalInvSigma]);
         if (in_block) {
             if (x_zero) {
-                res = r64 ? cast_rhs : rhs[gi];
+                res = r64 ? cast_rhs : rhs_v;
             } else {
                 const int64_t padi =
                     int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
@@ -250,7 +278,7 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
                                        xs[lc + (qz * HY + qy) * HX + qx];
                             }
                 }
-                res = rhs[gi] - acc;
+                res = rhs_v - acc;
             }
         }
     }
@@ -261,29 +289,22 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
     if (!mine) return;
     T xi = x_zero ? T(0) : xs[lc];
     T delta = T(0);
-    if (in_block) {
-        // block centre and its inverse slot
-        const int bx = tx / S, by = ty / S, bz = (D == 3) ? tz / S : 0;
-        const int ccx = gx0 + bx * S + HB, ccy = gy0 + by * S + HB, ccz = (D == 3) ? gz0 + bz * S + HB : 0;
-        const bool covered = ccx >= 0 && ccx < n1 && ccy >= 0 && ccy < n1 && (D == 2 || (ccz >= 0 && ccz < n1));
-        if (covered) {
-            int64_t slot = cls[ccx] + int64_t(ncls1) * cls[ccy];
-            if (D == 3) slot += int64_t(ncls1) * ncls1 * cls[ccz];
-            const int loc = cx + B * cy + ((D == 3) ? B * B * cz : 0);
-            const T *row = inv + (slot * BD + loc) * BD;
-            const int base = ((bz * S) * TY + by * S) * TX + bx * S;
+    if (covered) {
+        const int base = ((bz * S) * TY + by * S) * TX + bx * S;
 #pragma unroll
-            for (int l = 0; l < BD; ++l) {
-                const int lx = l % B, ly = (l / B) % B, lz = (D == 3) ? l / (B * B) : 0;
-                delta += row[l] * rs[base + (lz * TY + ly) * TX + lx];
-            }
+        for (int l = 0; l < BD; ++l) {
+            const int lx = l % B, ly = (l / B) % B, lz = (D == 3) ? l / (B * B) : 0;
+            T a;
+            if constexpr (kPreRow) a = irow[l];
+            else a = row[l];
+            delta += a * rs[base + (lz * TY + ly) * TX + lx];
         }
     }
     x_dst[gi] = xi + delta;
 }
 
 template <int D, int P, int B, class T>
-__global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
+__global__ void __launch_bounds__(kColourThreads) k_colour(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
                                                  int n1, const T *__restrict__ inv, const int *__restrict__ cls,
                                                  int ncls1, const T *__restrict__ x_src, T *__restrict__ x_dst,
                                                  const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz,
@@ -294,8 +315,9 @@ __global__ void __launch_bounds__(1024) k_colour(const T *__restrict__ val, int6
     extern __shared__ unsigned char smem_raw[];
     int bx = blockIdx.x, by = blockIdx.y;
     if (D == 2) xcd_tile_2d(bx, by);
-    colour_body<D, P, B, T>(val, npad, pitch1, pitch2, n1, inv, cls, ncls1, x_src, x_dst, rhs, x_zero, ox, oy, oz, S,
-                            NBX, NBY, NBZ, cs, ulo, uhi, skip, r64, scal, rhs_out, bx, by, int(blockIdx.z), smem_raw);
+    colour_body<D, P, B, T, true>(val, npad, pitch1, pitch2, n1, inv, cls, ncls1, x_src, x_dst, rhs, x_zero, ox, oy,
+                                  oz, S, NBX, NBY, NBZ, cs, ulo, uhi, skip, r64, scal, rhs_out, bx, by,
+                                  int(blockIdx.z), smem_raw);
 }
 
 // ------------------------------------------------------------------------
@@ -596,15 +618,15 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
     constexpr int pr = std::is_same<T, double>::value ? 0 : 1;
     int nbx = tile_nbx >= 1 ? tile_nbx : Pb.tile_bx[pr], nby = tile_nby >= 1 ? tile_nby : Pb.tile_by[pr];
     int nbz = (D == 3) ? Pb.tile_bz : 1;
-    // keep the tile within one workgroup of at most 1024 threads
-    while (nbx * S * nby * S * ((D == 3) ? nbz * S : 1) > 1024) {
+    // keep the tile within one workgroup of at most kColourThreads threads
+    while (nbx * S * nby * S * ((D == 3) ? nbz * S : 1) > kColourThreads) {
         if (nby > 1) --nby;
         else if (nbx > 1) --nbx;
         else if (nbz > 1) --nbz;
         else break;
     }
     const int TX = nbx * S, TY = nby * S, TZ = (D == 3) ? nbz * S : 1;
-    IGA2L_REQUIRE(TX * TY * TZ <= 1024, IGA2L_EUNSUPPORTED, "colour period too large for one workgroup");
+    IGA2L_REQUIRE(TX * TY * TZ <= kColourThreads, IGA2L_EUNSUPPORTED, "colour period too large for one workgroup");
     // tile origins: aligned with the colour's blocks and at or before index 0
     int ox = cx - HB, oy = cy - HB, oz = (D == 3) ? cz - HB : 0;
     if (ox > 0) ox -= S;
@@ -705,7 +727,7 @@ __global__ void kb_solve_init(const BatchProb *__restrict__ bp, int nprob, doubl
 // colour (cx, cy) of period S; the tile grid of every problem covers the
 // grids of all colours, so tiles past the end of a colour's grid do nothing
 template <int P, int B, class T>
-__global__ void __launch_bounds__(1024) kb_colour(const BatchProb *__restrict__ bp, const int2 *__restrict__ map,
+__global__ void __launch_bounds__(kColourThreads) kb_colour(const BatchProb *__restrict__ bp, const int2 *__restrict__ map,
                                                   int nbx, int nby, int cx, int cy, int S, int role_src, int role_dst,
                                                   int role_rhs, int x_zero, int fuse, int use_skip) {
     extern __shared__ unsigned char smem_raw[];
@@ -718,7 +740,7 @@ __global__ void __launch_bounds__(1024) kb_colour(const BatchProb *__restrict__ 
     const int bx = m.y % q.col_ntx, by = m.y / q.col_ntx;
     if (ox + bx * nbx * S >= q.n1 || oy + by * nby * S >= q.n1) return;
     constexpr int pr = prec_slot<T>();
-    colour_body<2, P, B, T>(static_cast<const T *>(q.val[pr]), q.npad, q.pitch1, 0, q.n1,
+    colour_body<2, P, B, T, false>(static_cast<const T *>(q.val[pr]), q.npad, q.pitch1, 0, q.n1,
                             static_cast<const T *>(q.inv[pr]), q.cls, q.ncls1, static_cast<const T *>(q.vec[role_src]),
                             static_cast<T *>(q.vec[role_dst]), static_cast<const T *>(q.vec[role_rhs]), x_zero, ox, oy,
                             0, S, nbx, nby, 1, static_cast<const T *>(q.cs[pr]), q.ulo, q.uhi,
@@ -831,7 +853,7 @@ void launch_block_inverse(Problem &Pb, const std::vector<int64_t> &reps, hipStre
 
 // ------------------------------------------------------- batched launchers --
 void colour_tile_clamp(int S, int &nbx, int &nby) {
-    while (nbx * S * nby * S > 1024) {
+    while (nbx * S * nby * S > kColourThreads) {
         if (nby > 1) --nby;
         else if (nbx > 1) --nbx;
         else break;
@@ -925,14 +947,22 @@ template void launch_colour_batch<float>(const BatchProb *, const int2 *, int, i
                                          int, int, bool, bool, hipStream_t, bool);
 
 // -------------------------------------------------------------- autotuner --
+bool tune_log() {
+    static const bool on = [] {
+        const char *v = std::getenv("IGA2L_TUNE_LOG");
+        return v && *v && *v != '0';
+    }();
+    return on;
+}
+
 std::vector<std::pair<int, int>> colour_tile_candidates(int S, int n1) {
-    static const int shapes[][2] = {{4, 4}, {8, 2}, {8, 4}, {16, 1}, {16, 2}, {16, 4}, {32, 1}, {32, 2},
-                                    {4, 8},  {2, 16}, {11, 3}, {22, 2}};
+    static const int shapes[][2] = {{4, 4}, {8, 2}, {8, 4},  {16, 1}, {16, 2}, {16, 4}, {32, 1}, {32, 2},
+                                    {4, 8}, {11, 3}, {22, 2}, {28, 2}, {43, 1}, {12, 4}, {64, 1}};
     std::vector<std::pair<int, int>> out;
     const int cells = (n1 + 2 * S - 1) / S;   // cells a colour's grid spans per direction
     for (auto &sh : shapes) {
         const int bx = sh[0], by = sh[1];
-        if (bx * S * by * S > 1024 || bx * S * by * S < 64) continue;
+        if (bx * S * by * S > kColourThreads || bx * S * by * S < 64) continue;
         if (bx > cells + 1 && !(bx == 4 && by == 4)) continue;   // wider than the grid
         out.emplace_back(bx, by);
     }
@@ -968,6 +998,9 @@ void autotune_colour_tile(Problem &Pb, int S, hipStream_t s) {
             IGA2L_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
             IGA2L_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (tune_log())
+                std::fprintf(stderr, "[iga2l tune] p=%d n1=%d s=%d %s: tile %dx%d blocks %.2f us\n", Pb.p, Pb.fine.n1,
+                             S, pr ? "fp32" : "fp64", cbx, cby, 1e3f * ms / reps);
             if (ms < best) {
                 best = ms;
                 bbx = cbx;

@@ -168,6 +168,12 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
 // holds the smoothed iterate.  The input is (zero_src ? 0 : e_src) + P ec.
 // RESTRICT: additionally rc[I] = (P^T (rhs - A e))[I] for the coarse points I
 // whose centre child 2I+1 lies in the tile.
+// threads of a fused red-black workgroup (tile 32 x 8 plus halo): launches
+// with few tiles are latency-bound and take 1024 threads per tile (the halo
+// ring's half steps then need one pass), launches with many tiles take 256
+// (two instantiations, each compiled for its own register budget)
+inline bool rb_wide(int64_t tiles) { return tiles < 1024; }
+
 // The body serves the single-problem kernel and the batched one (tile bx, by).
 template <class T, int NU, bool RESTRICT>
 __device__ __forceinline__ void rb_multi2_body(const LevelDev<T> &L, const T *__restrict__ e_src, int zero_src,
@@ -266,8 +272,8 @@ __device__ __forceinline__ void rb_multi2_body(const LevelDev<T> &L, const T *__
     }
 }
 
-template <class T, int NU, bool RESTRICT>
-__global__ void __launch_bounds__(256) k_rb_multi2(LevelDev<T> L, const T *__restrict__ e_src, int zero_src,
+template <class T, int NU, bool RESTRICT, int NT>
+__global__ void __launch_bounds__(NT) k_rb_multi2(LevelDev<T> L, const T *__restrict__ e_src, int zero_src,
                                                    const T *__restrict__ ec, int n1c_interp,
                                                    const T *__restrict__ rhs, T *__restrict__ e_dst,
                                                    T *__restrict__ rc, int n1c, const int *__restrict__ skip) {
@@ -278,8 +284,8 @@ __global__ void __launch_bounds__(256) k_rb_multi2(LevelDev<T> L, const T *__res
 
 // batched: pre-smoothing + residual restriction (RESTRICT) or prolongation +
 // post-smoothing of level l of every problem of the table
-template <class T, int NU, bool RESTRICT>
-__global__ void __launch_bounds__(256) kb_rb_multi2(const BatchLevel<T> *__restrict__ bl,
+template <class T, int NU, bool RESTRICT, int NT>
+__global__ void __launch_bounds__(NT) kb_rb_multi2(const BatchLevel<T> *__restrict__ bl,
                                                     const int2 *__restrict__ map, int zero_src) {
     const int2 m = map[blockIdx.x];
     const BatchLevel<T> &q = bl[m.x];
@@ -393,10 +399,12 @@ __device__ __forceinline__ int64_t padded_size(int n1) {
 // thread layout of the one-workgroup kernel: 32 x 32 (2-D) or 16 x 8 x 8 (3-D)
 template <int D>
 struct BT;
+// one point per thread in 2-D: levels up to 32 x 32 (larger levels run faster
+// on the multi-workgroup kernels than as several points per thread here)
 template <>
 struct BT<2> {
     static constexpr int X = 32, Y = 32, Z = 1;
-    static constexpr int KX = 2, KY = 2, KZ = 1;   // levels up to 64 x 64
+    static constexpr int KX = 1, KY = 1, KZ = 1;
 };
 template <>
 struct BT<3> {
@@ -423,6 +431,8 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
     __shared__ int64_t s_n[16];
     const int tid = threadIdx.x;
     const int tx = tid % BT<D>::X, ty = (tid / BT<D>::X) % BT<D>::Y, tz = (D == 3) ? tid / (BT<D>::X * BT<D>::Y) : 0;
+    // level descriptors: one thread per level (independent loads), then the
+    // LDS offsets from the staged sizes
     if (tid < A.nlev) {
         const LevelDev<T> &L = A.levels[tid];
         for (int w = 0; w < W3; ++w) s_c[tid][w] = L.c[w];
@@ -430,15 +440,16 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
         s_S[tid] = L.S;
         s_invd[tid] = L.invd;
         s_n[tid] = L.n;
+        s_n1[tid] = L.n1;
+        s_cst[tid] = L.cst;
         if (tid == A.nlev - 1) s_Zinv = L.Zinv;
     }
+    __syncthreads();
     if (tid == 0) {
         int acc = 0;
         for (int l = 0; l < A.nlev; ++l) {
-            const int n1 = A.levels[l].n1;
+            const int n1 = s_n1[l];
             const int ps = (D == 3) ? (n1 + 2) * (n1 + 2) * (n1 + 2) : (n1 + 2) * (n1 + 2);
-            s_n1[l] = n1;
-            s_cst[l] = A.levels[l].cst;
             off_e[l] = acc;
             acc += ps;
             off_r[l] = acc;
@@ -590,7 +601,7 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
             const int i = w % n, sg = w / n;
             const int j0 = sg * seg_len, j1 = min(n, j0 + seg_len);
             T acc = T(0);
-#pragma unroll 8
+#pragma unroll 16
             for (int j = j0; j < j1; ++j) acc += Zi[int64_t(j) * n + i] * rflat[j];
             if (nseg == 1) {
                 const int x = i % n1, y = (i / n1) % n1, z = (D == 3) ? i / (n1 * n1) : 0;
@@ -690,8 +701,12 @@ template <class T, int NU, bool RESTRICT>
 void launch_rb_multi2(const Problem &P, const LevelDev<T> &Ld, const T *e_src, bool zero_src, const T *ec,
                       int n1c_interp, const T *rhs, T *e_dst, T *rc, int n1c, hipStream_t s) {
     const dim3 grid(nblk(Ld.n1, 32), nblk(Ld.n1, 8), 1);
-    hipLaunchKernelGGL((k_rb_multi2<T, NU, RESTRICT>), grid, dim3(256), 0, s, Ld, e_src, zero_src ? 1 : 0, ec,
-                       n1c_interp, rhs, e_dst, rc, n1c, P.skip);
+    if (rb_wide(grid.x * grid.y))
+        hipLaunchKernelGGL((k_rb_multi2<T, NU, RESTRICT, 1024>), grid, dim3(1024), 0, s, Ld, e_src, zero_src ? 1 : 0,
+                           ec, n1c_interp, rhs, e_dst, rc, n1c, P.skip);
+    else
+        hipLaunchKernelGGL((k_rb_multi2<T, NU, RESTRICT, 256>), grid, dim3(256), 0, s, Ld, e_src, zero_src ? 1 : 0,
+                           ec, n1c_interp, rhs, e_dst, rc, n1c, P.skip);
 }
 
 template <class T, bool RESTRICT>
@@ -815,11 +830,19 @@ bool vcycle_bottom_fits(const Problem &P, size_t lb) {
 template <class T>
 void launch_rb_multi2_batch(const BatchLevel<T> *bl, const int2 *map, int nwg, int nu, bool restrict_, bool zero_src,
                             hipStream_t s) {
-    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), 0, s, bl, map, zero_src ? 1 : 0); };
-#define IGA2L_RBB(NU)                                   \
-    case NU:                                            \
-        if (restrict_) go(kb_rb_multi2<T, NU, true>);   \
-        else go(kb_rb_multi2<T, NU, false>);            \
+    auto go = [&](auto kern, unsigned nt) {
+        hipLaunchKernelGGL(kern, dim3(nwg), dim3(nt), 0, s, bl, map, zero_src ? 1 : 0);
+    };
+    const bool wide = rb_wide(nwg);
+#define IGA2L_RBB(NU)                                                                        \
+    case NU:                                                                                 \
+        if (restrict_) {                                                                     \
+            if (wide) go(kb_rb_multi2<T, NU, true, 1024>, 1024);                             \
+            else go(kb_rb_multi2<T, NU, true, 256>, 256);                                    \
+        } else {                                                                             \
+            if (wide) go(kb_rb_multi2<T, NU, false, 1024>, 1024);                            \
+            else go(kb_rb_multi2<T, NU, false, 256>, 256);                                   \
+        }                                                                                    \
         break;
     switch (nu) {
         IGA2L_RBB(0)
