@@ -64,6 +64,11 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
     const bool active = t < TX * TY * ((D == 3) ? TZ : 1) && gx < n1 && gy < n1 && (D == 2 || gz < n1);
     const int64_t gi = active ? (int64_t(gz) * n1 + gy) * n1 + gx : 0;
     const T bv = active ? b[gi] : T(0);   // issued with the halo loads
+    // the interior stencil (kappa = 1) staged in LDS behind the halo
+    constexpr int W = cpow(2 * P + 1, D);
+    T *css = xs + nh;
+    if (cs)
+        for (int w = threadIdx.x; w < W; w += blockDim.x) css[w] = cs[w];
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
         int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
         int hgx = gx0 + hx - P, hgy = gy0 + hy - P, hgz = (D == 3) ? gz0 + hz - P : 0;
@@ -85,7 +90,7 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
                 for (int oy = -P; oy <= P; ++oy)
 #pragma unroll
                     for (int ox = -P; ox <= P; ++ox)
-                        acc += cs[(oy + P) * (2 * P + 1) + (ox + P)] * xs[lc + oy * HX + ox];
+                        acc += css[(oy + P) * (2 * P + 1) + (ox + P)] * xs[lc + oy * HX + ox];
             } else {
 #pragma unroll
                 for (int oy = -P; oy <= P; ++oy)
@@ -104,7 +109,7 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
                     for (int oy = -P; oy <= P; ++oy)
 #pragma unroll
                         for (int ox = -P; ox <= P; ++ox)
-                            acc += cs[((oz + P) * (2 * P + 1) + (oy + P)) * (2 * P + 1) + (ox + P)] *
+                            acc += css[((oz + P) * (2 * P + 1) + (oy + P)) * (2 * P + 1) + (ox + P)] *
                                    xs[lc + (oz * HY + oy) * HX + ox];
             } else {
 #pragma unroll
@@ -225,7 +230,12 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
             for (int l = 0; l < BD; ++l) irow[l] = row[l];
         }
     }
+    // the interior stencil (kappa = 1) staged in LDS behind the residuals
+    constexpr int W = cpow(2 * P + 1, D);
+    T *css = rs + ntile;
     if (!x_zero) {
+        if (cs)
+            for (int w = threadIdx.x; w < W; w += blockDim.x) css[w] = cs[w];
         for (int h = threadIdx.x; h < nh; h += blockDim.x) {
             int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
             int hgx = gx0 + hx - P, hgy = gy0 + hy - P, hgz = (D == 3) ? gz0 + hz - P : 0;
@@ -254,7 +264,7 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
                         for (int qy = -P; qy <= P; ++qy)
 #pragma unroll
                             for (int qx = -P; qx <= P; ++qx)
-                                acc += cs[(((D == 3) ? (qz + P) * (2 * P + 1) : 0) + (qy + P)) * (2 * P + 1) + (qx + P)] *
+                                acc += css[(((D == 3) ? (qz + P) * (2 * P + 1) : 0) + (qy + P)) * (2 * P + 1) + (qx + P)] *
                                        xs[lc + (qz * HY + qy) * HX + qx];
                 } else if constexpr (D == 2) {
 #pragma unroll
@@ -556,7 +566,8 @@ void residual_launch(const Problem &Pb, const T *val, const T *x, const T *b, T 
     using TS = TileShape<D, P>;
     const int n1 = Pb.fine.n1;
     dim3 grid((n1 + TS::TX - 1) / TS::TX, (n1 + TS::TY - 1) / TS::TY, D == 3 ? (n1 + TS::TZ - 1) / TS::TZ : 1);
-    const size_t shm = size_t(TS::TX + 2 * P) * (TS::TY + 2 * P) * (D == 3 ? TS::TZ + 2 * P : 1) * sizeof(T);
+    const size_t shm = (size_t(TS::TX + 2 * P) * (TS::TY + 2 * P) * (D == 3 ? TS::TZ + 2 * P : 1) +
+                        size_t(cpow(2 * P + 1, D))) * sizeof(T);
     nblocks = int(grid.x * grid.y * grid.z);
     hipLaunchKernelGGL((k_residual<D, P, T, NORM>), grid, dim3(TS::TX * TS::TY * TS::TZ), shm, s, val, Pb.A.npad,
                        Pb.A.pitch[1], Pb.A.pitch[2], n1, TS::TX, TS::TY, TS::TZ, x, b, r, partial,
@@ -634,7 +645,8 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
     if (oz > 0) oz -= S;
     dim3 grid((n1 - ox + TX - 1) / TX, (n1 - oy + TY - 1) / TY, D == 3 ? (n1 - oz + TZ - 1) / TZ : 1);
     const int threads = ((TX * TY * TZ + kWave - 1) / kWave) * kWave;
-    const size_t shm = (size_t(TX + 2 * Pb.p) * (TY + 2 * Pb.p) * (D == 3 ? TZ + 2 * Pb.p : 1) + size_t(TX) * TY * TZ) *
+    const size_t shm = (size_t(TX + 2 * Pb.p) * (TY + 2 * Pb.p) * (D == 3 ? TZ + 2 * Pb.p : 1) + size_t(TX) * TY * TZ +
+                        size_t(cpow(2 * P + 1, D))) *
                        sizeof(T);
     const T *val = std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.A.v64.ptr)
                                                   : reinterpret_cast<const T *>(Pb.A.v32.ptr);
@@ -861,15 +873,15 @@ void colour_tile_clamp(int S, int &nbx, int &nby) {
 }
 
 size_t colour_lds(int p, int S, int nbx, int nby, size_t elem) {
-    const size_t TX = size_t(nbx) * S, TY = size_t(nby) * S;
-    return ((TX + 2 * p) * (TY + 2 * p) + TX * TY) * elem;
+    const size_t TX = size_t(nbx) * S, TY = size_t(nby) * S, W = size_t(2 * p + 1) * (2 * p + 1);
+    return ((TX + 2 * p) * (TY + 2 * p) + TX * TY + W) * elem;
 }
 
 template <int P, class T, bool NORM>
 void launch_residual_batch(const BatchProb *bp, const int2 *map, int nwg, int role_x, int role_b, int role_r,
                            bool use_skip, hipStream_t s) {
     using TS = TileShape<2, P>;
-    const size_t shm = size_t(TS::TX + 2 * P) * (TS::TY + 2 * P) * sizeof(T);
+    const size_t shm = (size_t(TS::TX + 2 * P) * (TS::TY + 2 * P) + size_t(2 * P + 1) * (2 * P + 1)) * sizeof(T);
     hipLaunchKernelGGL((kb_residual<P, T, NORM>), dim3(nwg), dim3(TS::TX * TS::TY), shm, s, bp, map, role_x, role_b,
                        role_r, use_skip ? 1 : 0);
 }

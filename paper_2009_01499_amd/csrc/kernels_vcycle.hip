@@ -412,16 +412,26 @@ struct BT<3> {
     static constexpr int KX = 1, KY = 2, KZ = 2;   // levels up to 16 x 16 x 16
 };
 
+// coarsest-level product: Z^{-1} entries each thread loads before the descent
+// (registers; the rest of a longer segment is read when it is needed)
+template <int D, class T>
+struct ZPre {
+    // 64 FP32 / 32 FP64 values in 2-D; the 3-D tail owns four points per thread
+    static constexpr int K = (D == 2) ? 256 / int(sizeof(T)) : 32 / int(sizeof(T));
+};
+
 template <int D, class T>
 __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, const T *__restrict__ rhs_top,
                                                    T *__restrict__ e_top, int nu1, int nu2,
                                                    const int *__restrict__ skip, unsigned char *smem_raw) {
     if (skip && *skip) return;
     T *sm = reinterpret_cast<T *>(smem_raw);
-    // LDS: for each level: e (padded), rhs (padded); then one residual scratch
-    // (padded, level lb).  A padded level of n1 points per direction has
-    // pitch n1+2 and the point (x,y,z) at ((z+1)(n1+2) + y+1)(n1+2) + x+1.
-    __shared__ int off_e[16], off_r[16], s_n1[16], s_cst[16], off_end;
+    // LDS: for each level two correction buffers (a half step reads one and
+    // writes the other) and the right-hand side, all padded; then one scratch
+    // (level lb's residual, later the coarsest level's flat right-hand side
+    // and segment sums).  A padded level of n1 points per direction has pitch
+    // n1+2 and the point (x,y,z) at ((z+1)(n1+2) + y+1)(n1+2) + x+1.
+    __shared__ int off_e[16][2], off_r[16], s_n1[16], s_cst[16], off_end;
     constexpr int W3 = (D == 3) ? 27 : 9;
     __shared__ T s_c[16][W3];          // constant stencils
     __shared__ T s_cinv[16];
@@ -450,18 +460,33 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
         for (int l = 0; l < A.nlev; ++l) {
             const int n1 = s_n1[l];
             const int ps = (D == 3) ? (n1 + 2) * (n1 + 2) * (n1 + 2) : (n1 + 2) * (n1 + 2);
-            off_e[l] = acc;
-            acc += ps;
-            off_r[l] = acc;
-            acc += ps;
+            off_e[l][0] = acc;
+            off_e[l][1] = acc + ps;
+            off_r[l] = acc + 2 * ps;
+            acc += 3 * ps;
         }
         off_end = acc;
     }
     __syncthreads();
+    const int last = A.nlev - 1;
+    // the coarsest level's product: thread tid < n nseg takes row i of segment sg
+    const int nl1 = s_n1[last];
+    const int nz = (D == 3) ? nl1 * nl1 * nl1 : nl1 * nl1;
+    const int nseg = max(1, kBottomThreads / nz);
+    const int seg_len = (nz + nseg - 1) / nseg;
+    const int zi = tid % nz, zsg = tid / nz;
+    const int zj0 = zsg * seg_len, zj1 = min(nz, zj0 + seg_len);
+    const bool zrow = tid < nz * nseg;
+    const T *Zi = s_Zinv;
+    constexpr int KZ = ZPre<D, T>::K;
+    T zpre[KZ];
+#pragma unroll
+    for (int k = 0; k < KZ; ++k) zpre[k] = (zrow && zj0 + k < zj1) ? Zi[int64_t(zj0 + k) * nz + zi] : T(0);
     T *scr = sm + off_end;
     {
         const int n1 = s_n1[0];
-        const int total = off_end + ((D == 3) ? (n1 + 2) * (n1 + 2) * (n1 + 2) : (n1 + 2) * (n1 + 2));
+        const int ps0 = (D == 3) ? (n1 + 2) * (n1 + 2) * (n1 + 2) : (n1 + 2) * (n1 + 2);
+        const int total = off_end + max(ps0, nz + kBottomThreads);
         for (int i = tid; i < total; i += kBottomThreads) sm[i] = T(0);
     }
     __syncthreads();
@@ -479,6 +504,9 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
         }
     }
     __syncthreads();
+    unsigned cur = 0;   // bit l: buffer of level l holding its current correction
+    auto E = [&](int l) { return sm + off_e[l][(cur >> l) & 1]; };
+    auto Eo = [&](int l) { return sm + off_e[l][((cur >> l) & 1) ^ 1]; };
 
     // operator application at padded position c (unpadded index i) of level l
     auto apply = [&](int l, int cst, const T *e, int n1, int c, int i) -> T {
@@ -506,46 +534,43 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
         return acc;
     };
     // one half step of the given colour on level l: every point of the colour
-    // is updated from the iterate at the start of the half step.  A thread owns
-    // the points (tx + X kx, ty + Y ky, tz + Z kz), kx < KX, ky < KY, kz < KZ
-    // (compile-time slots, so the new values stay in registers).
+    // is updated from the iterate at the start of the half step, read from one
+    // buffer; the result (updated or copied) goes to the other buffer.  A
+    // thread owns the points (tx + X kx, ty + Y ky, tz + Z kz).
     auto half = [&](int l, int colour) {
         const int n1 = s_n1[l], cst = s_cst[l];
         const T cinv = s_cinv[l];
         const T *invd = s_invd[l];
-        T *e = sm + off_e[l];
+        const T *e = E(l);
+        T *eo = Eo(l);
         const T *r = sm + off_r[l];
         constexpr int KX = BT<D>::KX, KY = BT<D>::KY, KZ = BT<D>::KZ;
-        T newv[KX * KY * KZ];
-        int where[KX * KY * KZ];
 #pragma unroll
         for (int k = 0; k < KX * KY * KZ; ++k) {
             const int x = tx + BT<D>::X * (k % KX), y = ty + BT<D>::Y * ((k / KX) % KY),
                       z = (D == 3) ? tz + BT<D>::Z * (k / (KX * KY)) : 0;
-            where[k] = -1;
-            if (x < n1 && y < n1 && (D == 2 || z < n1) && ((x + y + z) & 1) == colour) {
-                const int i = (z * n1 + y) * n1 + x;
+            if (x < n1 && y < n1 && (D == 2 || z < n1)) {
                 const int c = ((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1;
-                const T id = cst ? cinv : invd[i];
-                newv[k] = e[c] + (r[c] - apply(l, cst, e, n1, c, i)) * id;
-                where[k] = c;
+                T v = e[c];
+                if (((x + y + z) & 1) == colour) {
+                    const int i = (z * n1 + y) * n1 + x;
+                    const T id = cst ? cinv : invd[i];
+                    v = e[c] + (r[c] - apply(l, cst, e, n1, c, i)) * id;
+                }
+                eo[c] = v;
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KX * KY * KZ; ++k)
-            if (where[k] >= 0) e[where[k]] = newv[k];
-        __syncthreads();
+        cur ^= 1u << l;
     };
 
-    const int last = A.nlev - 1;
     for (int l = 0; l < last; ++l) {
         for (int k = 0; k < nu1; ++k) {
             half(l, 0);
             half(l, 1);
         }
         const int n1 = s_n1[l], cst = s_cst[l];
-        const T *e = sm + off_e[l];
+        const T *e = E(l);
         const T *r = sm + off_r[l];
         IGA2L_FOR_POINTS(n1) {
             const int i = (z * n1 + y) * n1 + x;
@@ -555,7 +580,7 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
         __syncthreads();
         const int n1c = s_n1[l + 1];
         T *rc = sm + off_r[l + 1];
-        T *ecl = sm + off_e[l + 1];
+        T *ecl = E(l + 1);
         IGA2L_FOR_POINTS(n1c) {
             T acc = T(0);
             for (int az = ((D == 3) ? -1 : 0); az <= ((D == 3) ? 1 : 0); ++az)
@@ -579,42 +604,35 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
         // array; each row's dot product is split into nseg segments handled by
         // different threads (Z^{-1} is symmetric: row i is read as column i, so
         // consecutive threads read consecutive words), then summed in LDS.
-        // The residual scratch of level lb is free at this point.
-        const int n1 = s_n1[last];
-        const int n = (D == 3) ? n1 * n1 * n1 : n1 * n1;
-        const int scr_len = (D == 3) ? (s_n1[0] + 2) * (s_n1[0] + 2) * (s_n1[0] + 2) : (s_n1[0] + 2) * (s_n1[0] + 2);
-        int nseg = kBottomThreads / n;
-        if (nseg > (scr_len - n) / n) nseg = (scr_len - n) / n;
-        if (nseg < 1) nseg = 1;
+        const int n1 = nl1;
         const T *r = sm + off_r[last];
-        T *e = sm + off_e[last];
+        T *e = E(last);
         T *rflat = scr;
-        T *part = scr + n;
-        for (int i = tid; i < n; i += kBottomThreads) {
+        T *part = scr + nz;
+        for (int i = tid; i < nz; i += kBottomThreads) {
             const int x = i % n1, y = (i / n1) % n1, z = (D == 3) ? i / (n1 * n1) : 0;
             rflat[i] = r[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1];
         }
         __syncthreads();
-        const T *Zi = s_Zinv;
-        const int seg_len = (n + nseg - 1) / nseg;
-        for (int w = tid; w < n * nseg; w += kBottomThreads) {
-            const int i = w % n, sg = w / n;
-            const int j0 = sg * seg_len, j1 = min(n, j0 + seg_len);
+        if (zrow) {
             T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < KZ; ++k)
+                if (zj0 + k < zj1) acc += zpre[k] * rflat[zj0 + k];
 #pragma unroll 16
-            for (int j = j0; j < j1; ++j) acc += Zi[int64_t(j) * n + i] * rflat[j];
+            for (int j = zj0 + KZ; j < zj1; ++j) acc += Zi[int64_t(j) * nz + zi] * rflat[j];
             if (nseg == 1) {
-                const int x = i % n1, y = (i / n1) % n1, z = (D == 3) ? i / (n1 * n1) : 0;
+                const int x = zi % n1, y = (zi / n1) % n1, z = (D == 3) ? zi / (n1 * n1) : 0;
                 e[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1] = acc;
             } else {
-                part[sg * n + i] = acc;
+                part[zsg * nz + zi] = acc;
             }
         }
         __syncthreads();
         if (nseg > 1) {
-            for (int i = tid; i < n; i += kBottomThreads) {
+            for (int i = tid; i < nz; i += kBottomThreads) {
                 T acc = T(0);
-                for (int sg = 0; sg < nseg; ++sg) acc += part[sg * n + i];
+                for (int sg = 0; sg < nseg; ++sg) acc += part[sg * nz + i];
                 const int x = i % n1, y = (i / n1) % n1, z = (D == 3) ? i / (n1 * n1) : 0;
                 e[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1] = acc;
             }
@@ -623,18 +641,18 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
     }
     for (int l = last - 1; l >= 0; --l) {
         const int n1 = s_n1[l], n1c = s_n1[l + 1];
-        T *e = sm + off_e[l];
-        const T *ecl = sm + off_e[l + 1];
+        T *e = E(l);
+        const T *ecl = E(l + 1);
         IGA2L_FOR_POINTS(n1) {
             int Ix[2], Iy[2], Iz[2];
             T wx[2], wy[2], wz[2];
             const int nx = parents<T>(x, n1c, Ix, wx), ny = parents<T>(y, n1c, Iy, wy);
-            int nz = 1;
+            int nzp = 1;
             Iz[0] = 0;
             wz[0] = T(1);
-            if (D == 3) nz = parents<T>(z, n1c, Iz, wz);
+            if (D == 3) nzp = parents<T>(z, n1c, Iz, wz);
             T acc = T(0);
-            for (int cc = 0; cc < nz; ++cc)
+            for (int cc = 0; cc < nzp; ++cc)
                 for (int bb = 0; bb < ny; ++bb)
                     for (int aa = 0; aa < nx; ++aa) {
                         const int q = ((D == 3) ? ((Iz[cc] + 1) * (n1c + 2) + Iy[bb] + 1) : (Iy[bb] + 1)) * (n1c + 2) +
@@ -651,7 +669,7 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
     }
     {
         const int n1 = s_n1[0];
-        const T *e0 = sm + off_e[0];
+        const T *e0 = E(0);
         IGA2L_FOR_POINTS(n1) {
             e_top[(z * n1 + y) * n1 + x] = e0[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1];
         }
@@ -813,8 +831,13 @@ int64_t vcycle_bottom_lds(const Problem &P, size_t lb) {
         return r;
     };
     int64_t tot = 0;
-    for (size_t l = lb; l < P.levels.size(); ++l) tot += 2 * ps(P.levels[l].g.n1);
-    return tot + ps(P.levels[lb].g.n1);
+    for (size_t l = lb; l < P.levels.size(); ++l) tot += 3 * ps(P.levels[l].g.n1);
+    // scratch: level lb's residual, or the coarsest level's flat right-hand side
+    // and its segment sums (at most kBottomThreads of them)
+    const int n1c = P.levels.back().g.n1;
+    int64_t nz = 1;
+    for (int k = 0; k < P.dim; ++k) nz *= n1c;
+    return tot + std::max<int64_t>(ps(P.levels[lb].g.n1), nz + kBottomThreads);
 }
 
 // points one thread owns in the bottom kernel (strided 32x32 or 16x8x8 layout)
