@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -345,6 +346,15 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
         IGA2L_REQUIRE(bw >= 1 && bw <= 7 && (bw & 1), IGA2L_EINVAL, "block width must be odd, 1..7");
         IGA2L_REQUIRE(P.dim == 2 || bw <= 3, IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3");
         hipStream_t s = nullptr;
+        auto tprev = std::chrono::steady_clock::now();
+        auto stage = [&](const char *what) {   // IGA2L_TUNE_LOG=1: set-up stage times
+            if (!tune_log()) return;
+            IGA2L_HIP(hipDeviceSynchronize());
+            const auto now = std::chrono::steady_clock::now();
+            std::fprintf(stderr, "[iga2l setup] %s %.2f ms\n", what,
+                         std::chrono::duration<double, std::milli>(now - tprev).count());
+            tprev = now;
+        };
         if (!P.blocks_ready || P.bw != bw) {
             P.blocks_ready = false;
             P.fp32_ready = false;
@@ -358,9 +368,11 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             P.cls_d.alloc(cls1.size() * sizeof(int));
             IGA2L_HIP(hipMemcpy(P.cls_d.ptr, cls1.data(), cls1.size() * sizeof(int), hipMemcpyHostToDevice));
             P.Inv64.alloc(size_t(P.nslots) * P.bd * P.bd * sizeof(double));
+            stage("block classes");
             launch_block_inverse(P, reps, s);
             P.lex_off.clear();   // the lexicographic schedule is built on first use
             P.blocks_ready = true;
+            stage("block inverses");
         }
         check_opts(P, o);
         if (o.precision == IGA2L_MIXED_FP32 && !P.fp32_ready) {
@@ -374,8 +386,12 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             P.ec64.alloc(size_t(P.coarse.n) * sizeof(double));
             IGA2L_HIP(hipStreamSynchronize(s));
             P.fp32_ready = true;
+            stage("FP32 copies");
         }
-        if (o.coarse == IGA2L_COARSE_VCYCLE && !P.vcycle_ready) host_build_levels(P);
+        if (o.coarse == IGA2L_COARSE_VCYCLE && !P.vcycle_ready) {
+            host_build_levels(P);
+            stage("V-cycle levels");
+        }
         if (o.coarse == IGA2L_COARSE_DIRECT && !P.direct_ready) {
             IGA2L_REQUIRE(P.kappa_one, IGA2L_EUNSUPPORTED,
                           "the exact coarse solve needs kappa = 1; use the V-cycle for variable kappa");
@@ -392,6 +408,7 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             autotune_colour_tile<float>(P, S, s);
             P.tuned[1] = true;
         }
+        stage("tile autotuning");
         P.layout_id = next_layout_id();
     });
 }

@@ -354,5 +354,11 @@ void launch_convert(const void *src, void *dst, int64_t n, bool to_fp32, hipStre
 void launch_fill_zero(void *x, int64_t n_elems, bool fp32, hipStream_t s, const int *skip);
 // gradient
 void launch_grad_kappa(const Problem &P, const double *u, const double *lam, double *g, hipStream_t s);
+// operator of a variable coefficient (upper diagonals, padded), from P.Ke_d and P.kappa_d
+void launch_assemble_dia(Problem &P, hipStream_t s);
+// V-cycle hierarchy: degree-1 operator on the fine knots ([3^d][n], from 1-D
+// element matrices [m][2][4] and kappa), and one Galerkin coarsening step
+void launch_assemble_q1(int dim, const double *KM1, const double *kappa, int m, double *S, hipStream_t s);
+void launch_galerkin(int dim, const double *Sf, int nf1, double *Sc, int nc1, hipStream_t s);
 
 }  // namespace iga2l

@@ -175,6 +175,147 @@ __global__ void k_grad_kappa(const double *__restrict__ KM, int p, int m, int n1
     g[el] = -acc;
 }
 
+// --------------------------------------------------------------- assembly --
+// Upper diagonals of A = sum_e kappa_e A_e in the symmetric padded-diagonal
+// form, one thread per (row, offset).  In each direction the elements shared
+// by the supports of B-splines i and j = i + o are e = max(i,j)+1-p .. min(i,j)+1
+// (0-based interior indices, element e covers [e/m, (e+1)/m]); the local
+// indices are i+1-e and j+1-e, and the element matrix is the tensor product
+// of the 1-D stiffness and mass matrices K1_e, M1_e (sum over the direction
+// that carries the derivative).  Elements are summed in increasing index
+// order.  val must be zero on entry (entries outside the grid stay zero).
+template <int D>
+__global__ void k_assemble_dia(const double *__restrict__ KM, const double *__restrict__ kappa, int p, int m, int n1,
+                               int64_t npad, int pitch1, int pitch2, int c0, double *__restrict__ val) {
+    const int64_t n = (D == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int wu = int(blockIdx.y);            // upper offset index (0 = centre)
+    const int w1 = 2 * p + 1, w = c0 + wu;
+    const int o[3] = {w % w1 - p, (w / w1) % w1 - p, (D == 3) ? w / (w1 * w1) - p : 0};
+    const int ic[3] = {int(i % n1), int((i / n1) % n1), (D == 3) ? int(i / (int64_t(n1) * n1)) : 0};
+    int elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0};
+    for (int k = 0; k < D; ++k) {
+        const int j = ic[k] + o[k];
+        if (j < 0 || j >= n1) return;
+        elo[k] = max(max(ic[k], j) + 1 - p, 0);
+        ehi[k] = min(min(ic[k], j) + 1, m - 1);
+    }
+    const int nl = p + 1, nl2 = nl * nl;
+    double acc = 0.0;
+    for (int ez = elo[2]; ez <= ehi[2]; ++ez)
+        for (int ey = elo[1]; ey <= ehi[1]; ++ey)
+            for (int ex = elo[0]; ex <= ehi[0]; ++ex) {
+                const int e[3] = {ex, ey, ez};
+                double term = 0.0;
+                for (int c = 0; c < D; ++c) {
+                    double prod = 1.0;
+                    for (int k = 0; k < D; ++k) {
+                        const int a = ic[k] + 1 - e[k], b = ic[k] + o[k] + 1 - e[k];
+                        prod *= KM[(int64_t(e[k]) * 2 + (k == c ? 0 : 1)) * nl2 + a * nl + b];
+                    }
+                    term += prod;
+                }
+                const int64_t el = (D == 3) ? (int64_t(ez) * m + ey) * m + ex : int64_t(ey) * m + ex;
+                acc += kappa[el] * term;
+            }
+    const int64_t padi = int64_t(ic[0] + p) + int64_t(ic[1] + p) * pitch1 + ((D == 3) ? int64_t(ic[2] + p) * pitch2 : 0);
+    val[int64_t(wu) * npad + padi] = acc;
+}
+
+// Full 3^d stencil of the degree-1 operator on the same knots, S[w][i]
+// (w = offset index, x fastest), from the 1-D degree-1 element matrices KM1
+// ([m][2][4], K then M) and kappa; same element rule as k_assemble_dia.
+template <int D>
+__global__ void k_assemble_q1(const double *__restrict__ KM1, const double *__restrict__ kappa, int m,
+                              double *__restrict__ S) {
+    const int n1 = m - 1;
+    const int64_t n = (D == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int w = int(blockIdx.y);
+    const int o[3] = {w % 3 - 1, (w / 3) % 3 - 1, (D == 3) ? w / 9 - 1 : 0};
+    const int ic[3] = {int(i % n1), int((i / n1) % n1), (D == 3) ? int(i / (int64_t(n1) * n1)) : 0};
+    int elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0};
+    bool in = true;
+    for (int k = 0; k < D; ++k) {
+        const int j = ic[k] + o[k];
+        if (j < 0 || j >= n1) in = false;
+        elo[k] = max(ic[k], j);
+        ehi[k] = min(min(ic[k], j) + 1, m - 1);
+    }
+    double acc = 0.0;
+    if (in)
+        for (int ez = elo[2]; ez <= ehi[2]; ++ez)
+            for (int ey = elo[1]; ey <= ehi[1]; ++ey)
+                for (int ex = elo[0]; ex <= ehi[0]; ++ex) {
+                    const int e[3] = {ex, ey, ez};
+                    double term = 0.0;
+                    for (int c = 0; c < D; ++c) {
+                        double prod = 1.0;
+                        for (int k = 0; k < D; ++k) {
+                            const int a = ic[k] + 1 - e[k], b = ic[k] + o[k] + 1 - e[k];
+                            prod *= KM1[(int64_t(e[k]) * 2 + (k == c ? 0 : 1)) * 4 + a * 2 + b];
+                        }
+                        term += prod;
+                    }
+                    const int64_t el = (D == 3) ? (int64_t(ez) * m + ey) * m + ex : int64_t(ey) * m + ex;
+                    acc += kappa[el] * term;
+                }
+    S[int64_t(w) * n + i] = acc;
+}
+
+// Galerkin coarse stencil Sc = P^T Sf P for linear interpolation from the
+// odd-indexed fine nodes: coarse node J has the fine children 2J, 2J+1, 2J+2
+// (weights 1/2, 1, 1/2 per direction, inside the fine grid).  One thread per
+// (coarse row I, coarse offset W).
+template <int D>
+__global__ void k_galerkin(const double *__restrict__ Sf, int nf1, double *__restrict__ Sc, int nc1) {
+    const int64_t nc = (D == 3) ? int64_t(nc1) * nc1 * nc1 : int64_t(nc1) * nc1;
+    const int64_t nf = (D == 3) ? int64_t(nf1) * nf1 * nf1 : int64_t(nf1) * nf1;
+    const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int W = int(blockIdx.y);
+    const int Ic[3] = {int(I % nc1), int((I / nc1) % nc1), (D == 3) ? int(I / (int64_t(nc1) * nc1)) : 0};
+    const int O[3] = {W % 3 - 1, (W / 3) % 3 - 1, (D == 3) ? W / 9 - 1 : 0};
+    int Jc[3] = {0, 0, 0};
+    bool in = true;
+    for (int k = 0; k < D; ++k) {
+        Jc[k] = Ic[k] + O[k];
+        if (Jc[k] < 0 || Jc[k] >= nc1) in = false;
+    }
+    double acc = 0.0;
+    if (in) {
+        const double cw[3] = {0.5, 1.0, 0.5};
+        for (int iz = 0; iz < ((D == 3) ? 3 : 1); ++iz)
+            for (int iy = 0; iy < 3; ++iy)
+                for (int ix = 0; ix < 3; ++ix) {
+                    const int fi[3] = {2 * Ic[0] + ix, 2 * Ic[1] + iy, (D == 3) ? 2 * Ic[2] + iz : 0};
+                    if (fi[0] >= nf1 || fi[1] >= nf1 || (D == 3 && fi[2] >= nf1)) continue;
+                    const double wi = cw[ix] * cw[iy] * ((D == 3) ? cw[iz] : 1.0);
+                    const int64_t fidx = (D == 3) ? (int64_t(fi[2]) * nf1 + fi[1]) * nf1 + fi[0]
+                                                  : int64_t(fi[1]) * nf1 + fi[0];
+                    for (int jz = 0; jz < ((D == 3) ? 3 : 1); ++jz)
+                        for (int jy = 0; jy < 3; ++jy)
+                            for (int jx = 0; jx < 3; ++jx) {
+                                const int fj[3] = {2 * Jc[0] + jx, 2 * Jc[1] + jy, (D == 3) ? 2 * Jc[2] + jz : 0};
+                                bool ok = true;
+                                int wf = 0, mul = 1;
+                                for (int k = 0; k < D; ++k) {
+                                    const int dk = fj[k] - fi[k];
+                                    if (fj[k] >= nf1 || dk < -1 || dk > 1) ok = false;
+                                    wf += (dk + 1) * mul;
+                                    mul *= 3;
+                                }
+                                if (!ok) continue;
+                                const double wj = cw[jx] * cw[jy] * ((D == 3) ? cw[jz] : 1.0);
+                                acc += wi * Sf[int64_t(wf) * nf + fidx] * wj;
+                            }
+                }
+    }
+    Sc[int64_t(W) * nc + I] = acc;
+}
+
 template <class T>
 const T *R1_of(const Problem &P) {
     return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.R1d64.ptr)
@@ -275,6 +416,37 @@ void launch_grad_kappa(const Problem &P, const double *u, const double *lam, dou
     else
         hipLaunchKernelGGL((k_grad_kappa<3>), dim3(nblocks(P.ne, 128)), dim3(128), 0, s, P.Ke_d.as<double>(), P.p, P.m,
                            P.fine.n1, u, lam, g);
+}
+
+void launch_assemble_dia(Problem &P, hipStream_t s) {
+    SymDia &A = P.A;
+    const int c0 = (A.W - 1) / 2;
+    IGA2L_HIP(hipMemsetAsync(A.v64.ptr, 0, size_t(A.Wh) * A.npad * sizeof(double), s));
+    const dim3 grid(nblocks(P.fine.n, 256), unsigned(A.Wh));
+    if (P.dim == 2)
+        hipLaunchKernelGGL((k_assemble_dia<2>), grid, dim3(256), 0, s, P.Ke_d.as<double>(), P.kappa_d.as<double>(), P.p,
+                           P.m, P.fine.n1, A.npad, A.pitch[1], A.pitch[2], c0, A.v64.as<double>());
+    else
+        hipLaunchKernelGGL((k_assemble_dia<3>), grid, dim3(256), 0, s, P.Ke_d.as<double>(), P.kappa_d.as<double>(), P.p,
+                           P.m, P.fine.n1, A.npad, A.pitch[1], A.pitch[2], c0, A.v64.as<double>());
+    IGA2L_HIP(hipGetLastError());
+}
+
+void launch_assemble_q1(int dim, const double *KM1, const double *kappa, int m, double *S, hipStream_t s) {
+    const int n1 = m - 1;
+    const int64_t n = (dim == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
+    const dim3 grid(nblocks(n, 256), dim == 3 ? 27 : 9);
+    if (dim == 2) hipLaunchKernelGGL((k_assemble_q1<2>), grid, dim3(256), 0, s, KM1, kappa, m, S);
+    else hipLaunchKernelGGL((k_assemble_q1<3>), grid, dim3(256), 0, s, KM1, kappa, m, S);
+    IGA2L_HIP(hipGetLastError());
+}
+
+void launch_galerkin(int dim, const double *Sf, int nf1, double *Sc, int nc1, hipStream_t s) {
+    const int64_t nc = (dim == 3) ? int64_t(nc1) * nc1 * nc1 : int64_t(nc1) * nc1;
+    const dim3 grid(nblocks(nc, 256), dim == 3 ? 27 : 9);
+    if (dim == 2) hipLaunchKernelGGL((k_galerkin<2>), grid, dim3(256), 0, s, Sf, nf1, Sc, nc1);
+    else hipLaunchKernelGGL((k_galerkin<3>), grid, dim3(256), 0, s, Sf, nf1, Sc, nc1);
+    IGA2L_HIP(hipGetLastError());
 }
 
 }  // namespace iga2l

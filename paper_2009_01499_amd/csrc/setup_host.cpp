@@ -194,6 +194,21 @@ void host_assemble(Problem &P) {
             for (int a = 0; a < p + 2; ++a) P.R1[size_t(I) * (p + 2) + a] = mix[size_t(I) * (p + 2) + a] / lump[I];
     }
 
+    // 1-D element matrices (assembly and gradient kernels): [m][2][(p+1)^2] (K then M)
+    const int nl = p + 1;
+    std::vector<double> km(size_t(m) * 2 * nl * nl);
+    for (int el = 0; el < m; ++el)
+        for (int k = 0; k < nl * nl; ++k) {
+            km[(size_t(el) * 2 + 0) * nl * nl + k] = P.Ke[el][k];
+            km[(size_t(el) * 2 + 1) * nl * nl + k] = P.Me[el][k];
+        }
+    P.Ke_d.alloc(km.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.Ke_d.ptr, km.data(), km.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<double> kap(P.ne, 1.0);
+    if (!P.kappa_one) kap = P.kappa;
+    P.kappa_d.alloc(kap.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.kappa_d.ptr, kap.data(), kap.size() * sizeof(double), hipMemcpyHostToDevice));
+
     // fine operator in symmetric padded-diagonal form
     SymDia &A = P.A;
     A.q = p;
@@ -204,11 +219,8 @@ void host_assemble(Problem &P) {
     A.pitch[1] = np1;
     A.pitch[2] = np1 * np1;
     A.npad = ipow(np1, d);
-    std::vector<double> val(size_t(A.Wh) * A.npad, 0.0);
+    std::vector<double> val(P.kappa_one ? size_t(A.Wh) * A.npad : 0, 0.0);
     const int c0 = (A.W - 1) / 2;
-    const int nl = p + 1;
-    const int64_t nloc = ipow(nl, d);
-    int e[kMaxDim] = {0, 0, 0}, a[kMaxDim] = {0, 0, 0}, b[kMaxDim] = {0, 0, 0};
     if (P.kappa_one) {
         // kappa = 1: A = sum_c (x)_k (k == c ? K1 : M1), entry by entry from the
         // assembled 1-D factors (O(n Wh) instead of the element loop)
@@ -237,45 +249,14 @@ void host_assemble(Problem &P) {
                 val[size_t(w - c0) * A.npad + padi] = term;
             }
         }
+        A.v64.alloc(val.size() * sizeof(double));
+        IGA2L_HIP(hipMemcpy(A.v64.ptr, val.data(), val.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        // variable coefficient: sum over elements on the device
+        A.v64.alloc(size_t(A.Wh) * A.npad * sizeof(double));
+        launch_assemble_dia(P, nullptr);
+        IGA2L_HIP(hipStreamSynchronize(nullptr));
     }
-    for (int64_t el = 0; el < (P.kappa_one ? 0 : P.ne); ++el) {
-        split(el, d, m, e);
-        const double kap = P.kappa_one ? 1.0 : P.kappa[el];
-        for (int64_t la = 0; la < nloc; ++la) {
-            split(la, d, nl, a);
-            bool in = true;
-            int64_t padi = 0;
-            for (int k = 0; k < d; ++k) {
-                int ik = e[k] + a[k] - 1;
-                if (ik < 0 || ik >= n1) in = false;
-                padi += int64_t(ik + p) * A.pitch[k];
-            }
-            if (!in) continue;
-            for (int64_t lb = 0; lb < nloc; ++lb) {
-                split(lb, d, nl, b);
-                bool inb = true;
-                int widx = 0;
-                for (int k = d - 1; k >= 0; --k) {
-                    int jk = e[k] + b[k] - 1;
-                    if (jk < 0 || jk >= n1) inb = false;
-                    widx = widx * w1 + (b[k] - a[k] + p);
-                }
-                if (!inb || widx < c0) continue;  // lower half implied by symmetry
-                double term = 0.0;
-                for (int c = 0; c < d; ++c) {
-                    double prod = 1.0;
-                    for (int k = 0; k < d; ++k) {
-                        const auto &Mk = (k == c) ? P.Ke[e[k]] : P.Me[e[k]];
-                        prod *= Mk[a[k] * nl + b[k]];
-                    }
-                    term += prod;
-                }
-                val[size_t(widx - c0) * A.npad + padi] += kap * term;
-            }
-        }
-    }
-    A.v64.alloc(val.size() * sizeof(double));
-    IGA2L_HIP(hipMemcpy(A.v64.ptr, val.data(), val.size() * sizeof(double), hipMemcpyHostToDevice));
 
     // kappa = 1: rows whose coordinates lie in [2p-1, n1-2p] couple only
     // translates of the cardinal B-spline and carry one common stencil, read
@@ -309,20 +290,6 @@ void host_assemble(Problem &P) {
     P.R1d64.alloc(P.R1.size() * sizeof(double));
     IGA2L_HIP(hipMemcpy(P.R1d64.ptr, P.R1.data(), P.R1.size() * sizeof(double), hipMemcpyHostToDevice));
 
-    // 1-D element matrices for the gradient kernel: [m][2][(p+1)^2] (K then M)
-    std::vector<double> km(size_t(m) * 2 * nl * nl);
-    for (int el = 0; el < m; ++el)
-        for (int k = 0; k < nl * nl; ++k) {
-            km[(size_t(el) * 2 + 0) * nl * nl + k] = P.Ke[el][k];
-            km[(size_t(el) * 2 + 1) * nl * nl + k] = P.Me[el][k];
-        }
-    P.Ke_d.alloc(km.size() * sizeof(double));
-    IGA2L_HIP(hipMemcpy(P.Ke_d.ptr, km.data(), km.size() * sizeof(double), hipMemcpyHostToDevice));
-    std::vector<double> kap(P.ne, 1.0);
-    if (!P.kappa_one) kap = P.kappa;
-    P.kappa_d.alloc(kap.size() * sizeof(double));
-    IGA2L_HIP(hipMemcpy(P.kappa_d.ptr, kap.data(), kap.size() * sizeof(double), hipMemcpyHostToDevice));
-
     // workspaces sized by the fine grid
     const size_t nf = size_t(P.fine.n), nc = size_t(P.coarse.n);
     P.r64.alloc(nf * sizeof(double));
@@ -350,111 +317,43 @@ void host_assemble(Problem &P) {
 void host_build_levels(Problem &P) {
     const int d = P.dim, m = P.m;
     const int W3 = int(ipow(3, d));
-    std::vector<std::vector<double>> ops;
+    // stencils of every level, built on the device: the degree-1 operator on
+    // the fine knots, then Galerkin products down to the first level with at
+    // most kCoarsestMax unknowns; host copies for the per-level book-keeping
+    std::vector<DevBuf> dops;
     std::vector<int> sizes;
+    DevBuf km1_d;
     {
         // degree-1 element matrices: K = (1/h)[1 -1; -1 1], M = (h/6)[2 1; 1 2]
         std::vector<std::vector<double>> Kc, Mc;
         element_matrices(1, m, Kc, Mc);
-        int n1 = m - 1;
-        std::vector<double> S(size_t(W3) * ipow(n1, d), 0.0);
-        int e[kMaxDim] = {0, 0, 0}, a[kMaxDim] = {0, 0, 0}, b[kMaxDim] = {0, 0, 0};
-        const int64_t n = ipow(n1, d);
-        for (int64_t el = 0; el < P.ne; ++el) {
-            split(el, d, m, e);
-            double kap = P.kappa_one ? 1.0 : P.kappa[el];
-            for (int la = 0; la < (1 << d); ++la) {
-                for (int k = 0; k < d; ++k) a[k] = (la >> k) & 1;
-                int64_t row = 0;
-                bool in = true;
-                for (int k = d - 1; k >= 0; --k) {
-                    int ik = e[k] + a[k] - 1;
-                    if (ik < 0 || ik >= n1) in = false;
-                    row = row * n1 + ik;
-                }
-                if (!in) continue;
-                for (int lb = 0; lb < (1 << d); ++lb) {
-                    for (int k = 0; k < d; ++k) b[k] = (lb >> k) & 1;
-                    bool inb = true;
-                    int w = 0;
-                    for (int k = d - 1; k >= 0; --k) {
-                        int jk = e[k] + b[k] - 1;
-                        if (jk < 0 || jk >= n1) inb = false;
-                        w = w * 3 + (b[k] - a[k] + 1);
-                    }
-                    if (!inb) continue;
-                    double term = 0.0;
-                    for (int c = 0; c < d; ++c) {
-                        double prod = 1.0;
-                        for (int k = 0; k < d; ++k) prod *= ((k == c) ? Kc[e[k]] : Mc[e[k]])[a[k] * 2 + b[k]];
-                        term += prod;
-                    }
-                    S[size_t(w) * n + row] += kap * term;
-                }
+        std::vector<double> km1(size_t(m) * 8);
+        for (int el = 0; el < m; ++el)
+            for (int k = 0; k < 4; ++k) {
+                km1[(size_t(el) * 2 + 0) * 4 + k] = Kc[el][k];
+                km1[(size_t(el) * 2 + 1) * 4 + k] = Mc[el][k];
             }
-        }
-        ops.push_back(std::move(S));
+        km1_d.alloc(km1.size() * sizeof(double));
+        IGA2L_HIP(hipMemcpy(km1_d.ptr, km1.data(), km1.size() * sizeof(double), hipMemcpyHostToDevice));
+        const int n1 = m - 1;
+        DevBuf S0;
+        S0.alloc(size_t(W3) * ipow(n1, d) * sizeof(double));
+        launch_assemble_q1(d, km1_d.as<double>(), P.kappa_d.as<double>(), m, S0.as<double>(), nullptr);
+        dops.push_back(std::move(S0));
         sizes.push_back(n1);
     }
     while (ipow(sizes.back(), d) > kCoarsestMax) {
         const int nf1 = sizes.back(), nc1 = nf1 / 2;
-        const int64_t nf = ipow(nf1, d), nc = ipow(nc1, d);
-        const std::vector<double> &Sf = ops.back();
-        std::vector<double> Sc(size_t(W3) * nc, 0.0);
-        // parents of a fine 1-D index: odd i -> (i-1)/2 weight 1; even i -> i/2-1, i/2 weight 1/2
-        auto parents = [nc1](int i, int *I, double *w) {
-            int cnt = 0;
-            if (i & 1) {
-                I[cnt] = (i - 1) / 2; w[cnt++] = 1.0;
-            } else {
-                if (i / 2 - 1 >= 0) { I[cnt] = i / 2 - 1; w[cnt++] = 0.5; }
-                if (i / 2 < nc1) { I[cnt] = i / 2; w[cnt++] = 0.5; }
-            }
-            return cnt;
-        };
-        int ix[kMaxDim] = {0, 0, 0}, o[kMaxDim] = {0, 0, 0}, jx[kMaxDim] = {0, 0, 0};
-        int PI[kMaxDim][2], PJ[kMaxDim][2], npi[kMaxDim], npj[kMaxDim];
-        double WI[kMaxDim][2], WJ[kMaxDim][2];
-        for (int64_t i = 0; i < nf; ++i) {
-            split(i, d, nf1, ix);
-            for (int k = 0; k < d; ++k) npi[k] = parents(ix[k], PI[k], WI[k]);
-            for (int w = 0; w < W3; ++w) {
-                double aij = Sf[size_t(w) * nf + i];
-                if (aij == 0.0) continue;
-                split(w, d, 3, o);
-                bool in = true;
-                for (int k = 0; k < d; ++k) {
-                    jx[k] = ix[k] + o[k] - 1;
-                    if (jx[k] < 0 || jx[k] >= nf1) in = false;
-                }
-                if (!in) continue;
-                for (int k = 0; k < d; ++k) npj[k] = parents(jx[k], PJ[k], WJ[k]);
-                // all combinations of parents per direction
-                int ci[kMaxDim] = {0, 0, 0};
-                int64_t combos_i = 1;
-                for (int k = 0; k < d; ++k) combos_i *= npi[k];
-                for (int64_t ca = 0; ca < combos_i; ++ca) {
-                    int64_t t = ca;
-                    double wi = 1.0;
-                    int64_t I = 0;
-                    for (int k = 0; k < d; ++k) { ci[k] = int(t % npi[k]); t /= npi[k]; wi *= WI[k][ci[k]]; }
-                    for (int k = d - 1; k >= 0; --k) I = I * nc1 + PI[k][ci[k]];
-                    int64_t combos_j = 1;
-                    for (int k = 0; k < d; ++k) combos_j *= npj[k];
-                    for (int64_t cb = 0; cb < combos_j; ++cb) {
-                        int64_t tt = cb;
-                        double wj = 1.0;
-                        int wc = 0;
-                        int cj[kMaxDim];
-                        for (int k = 0; k < d; ++k) { cj[k] = int(tt % npj[k]); tt /= npj[k]; wj *= WJ[k][cj[k]]; }
-                        for (int k = d - 1; k >= 0; --k) wc = wc * 3 + (PJ[k][cj[k]] - PI[k][ci[k]] + 1);
-                        Sc[size_t(wc) * nc + I] += wi * aij * wj;
-                    }
-                }
-            }
-        }
-        ops.push_back(std::move(Sc));
+        DevBuf Sc;
+        Sc.alloc(size_t(W3) * ipow(nc1, d) * sizeof(double));
+        launch_galerkin(d, dops.back().as<double>(), nf1, Sc.as<double>(), nc1, nullptr);
+        dops.push_back(std::move(Sc));
         sizes.push_back(nc1);
+    }
+    std::vector<std::vector<double>> ops(dops.size());
+    for (size_t l = 0; l < dops.size(); ++l) {
+        ops[l].resize(size_t(W3) * ipow(sizes[l], d));
+        IGA2L_HIP(hipMemcpy(ops[l].data(), dops[l].ptr, ops[l].size() * sizeof(double), hipMemcpyDeviceToHost));
     }
     P.levels.clear();
     P.levels.resize(ops.size());
@@ -467,8 +366,7 @@ void host_build_levels(Problem &P) {
         const auto &S = ops[l];
         const int64_t n = L.g.n;
         const int n1 = L.g.n1;
-        L.S64.alloc(S.size() * sizeof(double));
-        IGA2L_HIP(hipMemcpy(L.S64.ptr, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+        L.S64 = std::move(dops[l]);
         std::vector<float> s32(S.begin(), S.end());
         L.S32.alloc(s32.size() * sizeof(float));
         IGA2L_HIP(hipMemcpy(L.S32.ptr, s32.data(), s32.size() * sizeof(float), hipMemcpyHostToDevice));
