@@ -76,9 +76,10 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
         xs[h] = in ? x[(int64_t(hgz) * n1 + hgy) * n1 + hgx] : T(0);
     }
     __syncthreads();
-    // rows of the interior stencil read it instead of the diagonals (per point:
-    // only the rows next to the boundary of the grid read the operator)
-    const bool uni = cs != nullptr && point_uniform(gx, gy, gz, ulo, uhi, D);
+    // a wavefront whose rows all carry the interior stencil reads it instead of
+    // the diagonals (one path per wavefront; only wavefronts touching the rows
+    // next to the grid boundary read the operator)
+    const bool uni = cs != nullptr && __all(!active || point_uniform(gx, gy, gz, ulo, uhi, D));
     double rr = 0.0;
     if (active) {
         const int64_t padi = int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
@@ -102,8 +103,9 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
                     }
             }
         } else {
+            // 3-D: the z loop stays rolled (a fully unrolled (2p+1)^3 body holds too many registers)
             if (uni) {
-#pragma unroll
+#pragma unroll 1
                 for (int oz = -P; oz <= P; ++oz)
 #pragma unroll
                     for (int oy = -P; oy <= P; ++oy)
@@ -112,7 +114,7 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
                             acc += css[((oz + P) * (2 * P + 1) + (oy + P)) * (2 * P + 1) + (ox + P)] *
                                    xs[lc + (oz * HY + oy) * HX + ox];
             } else {
-#pragma unroll
+#pragma unroll 1
                 for (int oz = -P; oz <= P; ++oz)
 #pragma unroll
                     for (int oy = -P; oy <= P; ++oy)
@@ -244,7 +246,8 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
         }
         __syncthreads();
     }
-    const bool uni = cs != nullptr && point_uniform(gx, gy, gz, ulo, uhi, D);
+    // one path per wavefront: the interior stencil when all its rows carry it
+    const bool uni = cs != nullptr && __all(!mine || point_uniform(gx, gy, gz, ulo, uhi, D));
     const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
     T res = T(0);
     T cast_rhs = T(0);
@@ -257,14 +260,21 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
                 const int64_t padi =
                     int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
                 T acc = T(0);
-                if (uni) {
+                if (uni && D == 2) {
 #pragma unroll
-                    for (int qz = ((D == 3) ? -P : 0); qz <= ((D == 3) ? P : 0); ++qz)
+                    for (int qy = -P; qy <= P; ++qy)
+#pragma unroll
+                        for (int qx = -P; qx <= P; ++qx)
+                            acc += css[(qy + P) * (2 * P + 1) + (qx + P)] * xs[lc + qy * HX + qx];
+                } else if (uni) {
+                    // 3-D: the z loop stays rolled (register budget)
+#pragma unroll 1
+                    for (int qz = -P; qz <= P; ++qz)
 #pragma unroll
                         for (int qy = -P; qy <= P; ++qy)
 #pragma unroll
                             for (int qx = -P; qx <= P; ++qx)
-                                acc += css[(((D == 3) ? (qz + P) * (2 * P + 1) : 0) + (qy + P)) * (2 * P + 1) + (qx + P)] *
+                                acc += css[((qz + P) * (2 * P + 1) + (qy + P)) * (2 * P + 1) + (qx + P)] *
                                        xs[lc + (qz * HY + qy) * HX + qx];
                 } else if constexpr (D == 2) {
 #pragma unroll
@@ -276,7 +286,7 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
                                    xs[lc + qy * HX + qx];
                         }
                 } else {
-#pragma unroll
+#pragma unroll 1
                     for (int qz = -P; qz <= P; ++qz)
 #pragma unroll
                         for (int qy = -P; qy <= P; ++qy)
