@@ -251,6 +251,7 @@ std::unique_ptr<Plan> build_plan(const std::vector<Problem *> &probs, const iga2
         q.R1[0] = P.R1d64.ptr;
         q.R1[1] = P.R1d32.ptr;
         q.cls = P.cls_d.as<int>();
+        q.clsL = class_split(P);
         q.npad = P.A.npad;
         q.pitch1 = P.A.pitch[1];
         q.n1 = P.fine.n1;

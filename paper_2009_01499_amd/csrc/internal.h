@@ -208,6 +208,11 @@ __device__ __forceinline__ void xcd_tile_2d(int &bx, int &by) {
     xcd_relabel(int(blockIdx.y * gridDim.x + blockIdx.x), int(gridDim.x), int(gridDim.x * gridDim.y), bx, by);
 }
 
+// block classes of the Schwarz inverses, as the kernels compute them: the
+// number L of boundary classes on each side with shared inverses, -1 when
+// every position has its own inverse (must match host_block_classes)
+inline int class_split(const Problem &P) { return P.shared_inverses ? (P.ncls1 - 1) / 2 : -1; }
+
 // views into the status block
 inline int *dev_flags(const Problem &P) { return reinterpret_cast<int *>(P.scal.as<double>() + kScalCount); }
 inline double *dev_hist(const Problem &P) { return P.scal.as<double>() + kScalCount + kFlagCount / 2; }
@@ -224,6 +229,7 @@ enum VecRole { kVecU, kVecB, kVecR64, kVecE0, kVecE1, kVecRhsW, kVecDFine, kVecD
 struct BatchProb {
     const void *val[2], *inv[2], *cs[2], *R1[2];   // [0] FP64, [1] FP32 (null if not set up)
     const int *cls;
+    int clsL;                                      // block classes: L of shared inverses, -1 = one per position
     int64_t npad;
     int pitch1, n1, n1c, p, ncls1, ulo, uhi;
     int hist_cap;

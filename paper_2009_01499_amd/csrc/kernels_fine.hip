@@ -34,6 +34,17 @@ __device__ __forceinline__ T dia_entry(const T *__restrict__ val, int64_t npad, 
 }
 
 // ------------------------------------------------------------------------
+// 1-D class of a block centre j (the index of its inverse along one
+// direction): with shared inverses (kappa = 1, L = p-1+h_b) the first and
+// last L positions have their own classes and all others share class L;
+// otherwise (L < 0) every position is its own class.  Computed instead of
+// looked up, so the inverse rows can be loaded together with the halo.
+__device__ __forceinline__ int block_class(int j, int n1, int L) {
+    if (L < 0) return j;
+    return j < L ? j : (j > n1 - 1 - L ? L + 1 + (j - (n1 - L)) : L);
+}
+
+// ------------------------------------------------------------------------
 // Interior rows of the kappa = 1 operator are translation invariant: rows whose
 // coordinates all lie in [ulo, uhi] carry the (2p+1)^d stencil cs (bit for
 // bit: the interior element matrices are one copy).  Such rows read cs
@@ -175,7 +186,7 @@ __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int
 // (tbx, tby, tbz) of the colour, smem = LDS of the tile.
 template <int D, int P, int B, class T, bool PRE>
 __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2, int n1,
-                                            const T *__restrict__ inv, const int *__restrict__ cls, int ncls1,
+                                            const T *__restrict__ inv, int clsL, int ncls1,
                                             const T *__restrict__ x_src, T *__restrict__ x_dst,
                                             const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz, int S,
                                             int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo, int uhi,
@@ -223,8 +234,8 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
     T irow[NR];
     const T *row = nullptr;
     if (mine && covered) {
-        int64_t slot = cls[ccx] + int64_t(ncls1) * cls[ccy];
-        if (D == 3) slot += int64_t(ncls1) * ncls1 * cls[ccz];
+        int64_t slot = block_class(ccx, n1, clsL) + int64_t(ncls1) * block_class(ccy, n1, clsL);
+        if (D == 3) slot += int64_t(ncls1) * ncls1 * block_class(ccz, n1, clsL);
         const int loc = cx + B * cy + ((D == 3) ? B * B * cz : 0);
         row = inv + (slot * BD + loc) * BD;
         if constexpr (kPreRow) {
@@ -325,8 +336,7 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
 
 template <int D, int P, int B, class T>
 __global__ void __launch_bounds__(kColourThreads) k_colour(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
-                                                 int n1, const T *__restrict__ inv, const int *__restrict__ cls,
-                                                 int ncls1, const T *__restrict__ x_src, T *__restrict__ x_dst,
+                                                 int n1, const T *__restrict__ inv, int clsL, int ncls1, const T *__restrict__ x_src, T *__restrict__ x_dst,
                                                  const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz,
                                                  int S, int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo,
                                                  int uhi, const int *__restrict__ skip,
@@ -335,7 +345,7 @@ __global__ void __launch_bounds__(kColourThreads) k_colour(const T *__restrict__
     extern __shared__ unsigned char smem_raw[];
     int bx = blockIdx.x, by = blockIdx.y;
     if (D == 2) xcd_tile_2d(bx, by);
-    colour_body<D, P, B, T, true>(val, npad, pitch1, pitch2, n1, inv, cls, ncls1, x_src, x_dst, rhs, x_zero, ox, oy,
+    colour_body<D, P, B, T, true>(val, npad, pitch1, pitch2, n1, inv, clsL, ncls1, x_src, x_dst, rhs, x_zero, ox, oy,
                                   oz, S, NBX, NBY, NBZ, cs, ulo, uhi, skip, r64, scal, rhs_out, bx, by,
                                   int(blockIdx.z), smem_raw);
 }
@@ -663,7 +673,7 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
     const T *inv = std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.Inv64.ptr)
                                                   : reinterpret_cast<const T *>(Pb.Inv32.ptr);
     hipLaunchKernelGGL((k_colour<D, P, B, T>), grid, dim3(threads), shm, s, val, Pb.A.npad, Pb.A.pitch[1],
-                       Pb.A.pitch[2], n1, inv, Pb.cls_d.as<int>(), Pb.ncls1, x_src, x_dst, rhs, x_zero ? 1 : 0, ox,
+                       Pb.A.pitch[2], n1, inv, class_split(Pb), Pb.ncls1, x_src, x_dst, rhs, x_zero ? 1 : 0, ox,
                        oy, oz, S, nbx, nby, nbz, uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, r64,
                        Pb.scal.as<double>(), rhs_out);
 }
@@ -763,7 +773,7 @@ __global__ void __launch_bounds__(kColourThreads) kb_colour(const BatchProb *__r
     if (ox + bx * nbx * S >= q.n1 || oy + by * nby * S >= q.n1) return;
     constexpr int pr = prec_slot<T>();
     colour_body<2, P, B, T, false>(static_cast<const T *>(q.val[pr]), q.npad, q.pitch1, 0, q.n1,
-                            static_cast<const T *>(q.inv[pr]), q.cls, q.ncls1, static_cast<const T *>(q.vec[role_src]),
+                            static_cast<const T *>(q.inv[pr]), q.clsL, q.ncls1, static_cast<const T *>(q.vec[role_src]),
                             static_cast<T *>(q.vec[role_dst]), static_cast<const T *>(q.vec[role_rhs]), x_zero, ox, oy,
                             0, S, nbx, nby, 1, static_cast<const T *>(q.cs[pr]), q.ulo, q.uhi,
                             use_skip ? q.flags : nullptr,
