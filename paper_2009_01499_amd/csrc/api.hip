@@ -147,8 +147,11 @@ void correction_cycle(Problem &P, const iga2l_opts &o, double *u, hipStream_t s)
     } else {
         // lexicographic: FP64 only, in place on a zeroed correction
         launch_fill_zero(P.ework[0].ptr, P.fine.n, false, s, P.skip);
-        for (size_t st = 0; st + 1 < P.lex_off.size(); ++st)
-            launch_lex_step(P, int(st), P.ework[0].as<double>(), P.r64.as<double>(), s);
+        if (lex_sweep_fits(P))
+            launch_lex_sweep(P, P.ework[0].as<double>(), P.r64.as<double>(), s);
+        else
+            for (size_t st = 0; st + 1 < P.lex_off.size(); ++st)
+                launch_lex_step(P, int(st), P.ework[0].as<double>(), P.r64.as<double>(), s);
         cur = 0;
     }
     T *e = P.ework[cur].as<T>();
@@ -165,6 +168,8 @@ void correction_cycle(Problem &P, const iga2l_opts &o, double *u, hipStream_t s)
         if (o.ordering == IGA2L_COLOUR) {
             const int S = o.colour_period ? o.colour_period : P.bw;
             cur = sweep_colour<T>(P, S, rhs, cur, false, s);
+        } else if (lex_sweep_fits(P)) {
+            launch_lex_sweep(P, P.ework[0].as<double>(), P.r64.as<double>(), s);
         } else {
             for (size_t st = 0; st + 1 < P.lex_off.size(); ++st)
                 launch_lex_step(P, int(st), P.ework[0].as<double>(), P.r64.as<double>(), s);
@@ -448,7 +453,9 @@ int iga2l_smooth(const iga2l_problem *prob, double *u, const double *b, int nswe
         if (o.ordering == IGA2L_LEX && P.lex_off.empty()) host_lex_schedule(P);
         for (int k = 0; k < nsweeps; ++k) {
             if (o.ordering == IGA2L_LEX) {
-                for (size_t st = 0; st + 1 < P.lex_off.size(); ++st) launch_lex_step(P, int(st), u, b, s);
+                if (lex_sweep_fits(P)) launch_lex_sweep(P, u, b, s);
+                else
+                    for (size_t st = 0; st + 1 < P.lex_off.size(); ++st) launch_lex_step(P, int(st), u, b, s);
             } else {
                 const int S = o.colour_period ? o.colour_period : P.bw;
                 const int ncol = (P.dim == 3) ? S * S * S : S * S;

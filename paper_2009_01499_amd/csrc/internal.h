@@ -140,6 +140,8 @@ struct Problem {
     // lexicographic schedule: hyperplane steps
     std::vector<int> lex_off;     // host [nsteps+1]
     DevBuf lex_blocks;            // int [n]
+    DevBuf lex_off_d;             // the step offsets on the device
+    int lex_maxcnt = 0;           // most blocks in one step
 
     // coarse
     std::vector<Level> levels;    // V-cycle hierarchy, level 0 = A_1 on the same knots
@@ -325,6 +327,9 @@ template <class T>
 void launch_colour_step(const Problem &P, int cx, int cy, int cz, int s_period, const T *x_src, T *x_dst,
                         const T *rhs, bool x_zero, hipStream_t s, const double *r64 = nullptr, T *rhs_out = nullptr);
 void launch_lex_step(const Problem &P, int step, double *u, const double *b, hipStream_t s);
+// the whole lexicographic sweep in one workgroup (iterate in LDS) when it fits
+bool lex_sweep_fits(const Problem &P);
+void launch_lex_sweep(const Problem &P, double *u, const double *b, hipStream_t s);
 // times the coloured Schwarz kernel for candidate tile shapes on the problem's
 // own workspaces (2-D) and keeps the fastest in P.tile_bx / P.tile_by
 template <class T>

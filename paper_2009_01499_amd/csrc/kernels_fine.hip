@@ -405,6 +405,133 @@ __global__ void __launch_bounds__(128) k_lex_step(const double *__restrict__ val
 }
 
 // ------------------------------------------------------------------------
+// The whole lexicographic sweep in one workgroup (small grids): the iterate,
+// the right-hand side and the step schedule live in LDS, the steps run one
+// after the other with a barrier between them, each step's blocks in
+// parallel, one thread per block point.  A thread issues the loads of its
+// inverse row and, next to the grid boundary, of its operator row before it
+// forms the block residual, so a step waits for one round trip to memory.
+// Same arithmetic as k_lex_step (interior rows read the interior stencil,
+// which equals their diagonals bit for bit; out-of-grid neighbours are
+// skipped), so the result equals the step-by-step launches.
+constexpr int kLexThreads = 256;
+
+template <int D, int P, int B>
+__global__ void __launch_bounds__(kLexThreads) k_lex_sweep(const double *__restrict__ val, int64_t npad, int pitch1,
+                                                           int pitch2, int n1, const double *__restrict__ inv,
+                                                           int clsL, int ncls1, const int *__restrict__ blocks,
+                                                           const int *__restrict__ offs, int nsteps, double *u,
+                                                           const double *__restrict__ b,
+                                                           const double *__restrict__ cs, int ulo, int uhi,
+                                                           const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    constexpr int BD = cpow(B, D);
+    constexpr int HB = (B - 1) / 2;
+    constexpr int W = cpow(2 * P + 1, D);
+    constexpr int WP = cpow(2 * P + 1, 2);  // one z plane of the stencil
+    extern __shared__ unsigned char smem_raw[];
+    const int n = (D == 3) ? n1 * n1 * n1 : n1 * n1;
+    double *us = reinterpret_cast<double *>(smem_raw);
+    double *bs = us + n;
+    double *css = bs + n;
+    double *rs = css + W;                                           // one step's block residuals
+    int *blk = reinterpret_cast<int *>(rs + kLexThreads);           // the schedule
+    int *off = blk + n;                                             // step offsets
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        us[i] = u[i];
+        bs[i] = b[i];
+        blk[i] = blocks[i];
+    }
+    for (int i = threadIdx.x; i <= nsteps; i += blockDim.x) off[i] = offs[i];
+    if (cs)
+        for (int w = threadIdx.x; w < W; w += blockDim.x) css[w] = cs[w];
+    __syncthreads();
+    const int idx = threadIdx.x;
+    const int l = idx % BD;
+    for (int st = 0; st < nsteps; ++st) {
+        const int first = off[st], cnt = off[st + 1] - first;
+        const bool act = idx < cnt * BD;
+        bool in = false;
+        int gi = 0;
+        double row[BD];
+        if (act) {
+            const int j = blk[first + idx / BD];
+            const int jx = j % n1, jy = (j / n1) % n1, jz = (D == 3) ? j / (n1 * n1) : 0;
+            const int gx = jx + l % B - HB, gy = jy + (l / B) % B - HB, gz = (D == 3) ? jz + l / (B * B) - HB : 0;
+            in = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
+            double r = 0.0;
+            if (in) {
+                gi = (gz * n1 + gy) * n1 + gx;
+                int64_t slot = block_class(jx, n1, clsL) + int64_t(ncls1) * block_class(jy, n1, clsL);
+                if (D == 3) slot += int64_t(ncls1) * ncls1 * block_class(jz, n1, clsL);
+                const double *ir = inv + (slot * BD + l) * BD;
+#pragma unroll
+                for (int k = 0; k < BD; ++k) row[k] = ir[k];
+                double acc = 0.0;
+                if (cs && point_uniform(gx, gy, gz, ulo, uhi, D)) {
+                    // every neighbour lies inside the grid
+#pragma unroll 1
+                    for (int qz = ((D == 3) ? -P : 0); qz <= ((D == 3) ? P : 0); ++qz)
+#pragma unroll
+                        for (int qy = -P; qy <= P; ++qy)
+#pragma unroll
+                            for (int qx = -P; qx <= P; ++qx)
+                                acc += css[(D == 3 ? (qz + P) * WP : 0) + (qy + P) * (2 * P + 1) + (qx + P)] *
+                                       us[gi + (qz * n1 + qy) * n1 + qx];
+                } else {
+                    const int64_t padi =
+                        int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
+                    // operator entries fetched RY stencil rows at a time (all of a
+                    // z plane for p <= 3), then accumulated in the skip order
+                    constexpr int RY = (P <= 3) ? 2 * P + 1 : 1;
+#pragma unroll 1
+                    for (int qz = ((D == 3) ? -P : 0); qz <= ((D == 3) ? P : 0); ++qz) {
+                        const bool zok = D == 2 || (gz + qz >= 0 && gz + qz < n1);
+#pragma unroll 1
+                        for (int qy0 = -P; qy0 <= P; qy0 += RY) {
+                            double a[RY * (2 * P + 1)];
+#pragma unroll
+                            for (int ry = 0; ry < RY; ++ry)
+#pragma unroll
+                                for (int qx = -P; qx <= P; ++qx) {
+                                    const int qy = qy0 + ry, hx = gx + qx, hy = gy + qy;
+                                    const bool ok = zok && hx >= 0 && hx < n1 && hy >= 0 && hy < n1;
+                                    const int w = (D == 3 ? (qz + P) * WP : 0) + (qy + P) * (2 * P + 1) + (qx + P);
+                                    a[ry * (2 * P + 1) + (qx + P)] =
+                                        ok ? dia_entry<D, P, double>(val, npad, padi, w,
+                                                                     int64_t(qx) + int64_t(qy) * pitch1 +
+                                                                         int64_t(qz) * pitch2)
+                                           : 0.0;
+                                }
+#pragma unroll
+                            for (int ry = 0; ry < RY; ++ry)
+#pragma unroll
+                                for (int qx = -P; qx <= P; ++qx) {
+                                    const int qy = qy0 + ry, hx = gx + qx, hy = gy + qy;
+                                    const bool ok = zok && hx >= 0 && hx < n1 && hy >= 0 && hy < n1;
+                                    if (ok) acc += a[ry * (2 * P + 1) + (qx + P)] * us[gi + (qz * n1 + qy) * n1 + qx];
+                                }
+                        }
+                    }
+                }
+                r = bs[gi] - acc;
+            }
+            rs[idx] = r;
+        }
+        __syncthreads();
+        if (act && in) {
+            const double *rb = rs + (idx / BD) * BD;
+            double delta = 0.0;
+#pragma unroll
+            for (int k = 0; k < BD; ++k) delta += row[k] * rb[k];
+            us[gi] += delta;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = us[i];
+}
+
+// ------------------------------------------------------------------------
 // Inverse of every block matrix A^{B_j} = V_j A V_j^T (one per slot) by
 // in-place Gauss-Jordan elimination without pivoting (the block matrices are
 // symmetric positive definite).  Block members outside the grid get identity
@@ -708,6 +835,42 @@ void lex_launch(const Problem &Pb, int step, double *u, const double *b, hipStre
                        Pb.lex_blocks.as<int>(), first, u, b, Pb.skip);
 }
 
+// iterate, right-hand side, interior stencil, one step's block residuals,
+// schedule and step offsets
+size_t lex_sweep_lds(const Problem &Pb) {
+    const int64_t w = (Pb.dim == 3) ? int64_t(2 * Pb.p + 1) * (2 * Pb.p + 1) * (2 * Pb.p + 1)
+                                    : int64_t(2 * Pb.p + 1) * (2 * Pb.p + 1);
+    return size_t(2 * Pb.fine.n + w + kLexThreads) * sizeof(double) +
+           size_t(Pb.fine.n + int64_t(Pb.lex_off.size())) * sizeof(int);
+}
+
+template <int D, int P, int B>
+void lex_sweep_launch(const Problem &Pb, double *u, const double *b, hipStream_t s) {
+    const size_t shm = lex_sweep_lds(Pb);
+    const int nsteps = int(Pb.lex_off.size()) - 1;
+    hipLaunchKernelGGL((k_lex_sweep<D, P, B>), dim3(1), dim3(kLexThreads), shm, s, Pb.A.v64.as<double>(), Pb.A.npad,
+                       Pb.A.pitch[1], Pb.A.pitch[2], Pb.fine.n1, Pb.Inv64.as<double>(), class_split(Pb), Pb.ncls1,
+                       Pb.lex_blocks.as<int>(), Pb.lex_off_d.as<int>(), nsteps, u, b, uniform_stencil<double>(Pb),
+                       Pb.ulo, Pb.uhi, Pb.skip);
+}
+
+template <int D, int P>
+void lex_sweep_dp(const Problem &Pb, double *u, const double *b, hipStream_t s) {
+    switch (Pb.bw) {
+        case 1: lex_sweep_launch<D, P, 1>(Pb, u, b, s); break;
+        case 3: lex_sweep_launch<D, P, 3>(Pb, u, b, s); break;
+        case 5:
+            if constexpr (D == 2) lex_sweep_launch<D, P, 5>(Pb, u, b, s);
+            else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
+            break;
+        case 7:
+            if constexpr (D == 2) lex_sweep_launch<D, P, 7>(Pb, u, b, s);
+            else throw Error{IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3"};
+            break;
+        default: throw Error{IGA2L_EUNSUPPORTED, "block width must be 1, 3, 5 or 7"};
+    }
+}
+
 template <int D, int P>
 void lex_dp(const Problem &Pb, int step, double *u, const double *b, hipStream_t s) {
     switch (Pb.bw) {
@@ -831,6 +994,20 @@ template void launch_colour_step<double>(const Problem &, int, int, int, int, co
                                          const double *, bool, hipStream_t, const double *, double *);
 template void launch_colour_step<float>(const Problem &, int, int, int, int, const float *, float *, const float *,
                                         bool, hipStream_t, const double *, float *);
+
+bool lex_sweep_fits(const Problem &Pb) {
+    const int64_t bd = (Pb.dim == 3) ? int64_t(Pb.bw) * Pb.bw * Pb.bw : int64_t(Pb.bw) * Pb.bw;
+    return !Pb.lex_off.empty() && int64_t(Pb.lex_maxcnt) * bd <= kLexThreads && lex_sweep_lds(Pb) <= 64 * 1024;
+}
+
+void launch_lex_sweep(const Problem &Pb, double *u, const double *b, hipStream_t s) {
+    IGA2L_REQUIRE(lex_sweep_fits(Pb), IGA2L_EUNSUPPORTED, "grid too large for the one-workgroup sweep");
+    if (Pb.dim == 2) {
+        IGA2L_DISPATCH_P2(lex_sweep_dp, Pb, u, b, s);
+    } else {
+        IGA2L_DISPATCH_P3(lex_sweep_dp, Pb, u, b, s);
+    }
+}
 
 void launch_lex_step(const Problem &Pb, int step, double *u, const double *b, hipStream_t s) {
     if (Pb.dim == 2) {

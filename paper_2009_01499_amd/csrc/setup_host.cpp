@@ -614,6 +614,10 @@ void host_lex_schedule(Problem &P) {
     std::vector<int> blocks(order.begin(), order.end());
     P.lex_blocks.alloc(blocks.size() * sizeof(int));
     IGA2L_HIP(hipMemcpy(P.lex_blocks.ptr, blocks.data(), blocks.size() * sizeof(int), hipMemcpyHostToDevice));
+    P.lex_off_d.alloc(off.size() * sizeof(int));
+    IGA2L_HIP(hipMemcpy(P.lex_off_d.ptr, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+    P.lex_maxcnt = 0;
+    for (size_t k = 0; k + 1 < off.size(); ++k) P.lex_maxcnt = std::max(P.lex_maxcnt, off[k + 1] - off[k]);
 }
 
 }  // namespace iga2l

@@ -96,6 +96,20 @@ def test_one_sweep_parity(d, p, m, kap, period):
     assert e < sweep_tolerance(orc), e
 
 
+@pytest.mark.parametrize("d,p,m", [(2, 2, 100), (3, 2, 24)])
+def test_lex_sweep_large_grid(d, p, m):
+    """Lexicographic sweep on grids whose iterate exceeds one workgroup's
+    LDS: the sweep runs as one launch per hyperplane step instead."""
+    G, orc, gp = _pair(d, p, m, vcycle=False, direct=False)
+    u = synth.initial_guess(d, p, m, seed=1)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    ref = orc.sweep(u, b, ordering=O.LEX)
+    ug = dev(u)
+    gp.smooth(ug, dev(b), 1, G.Opts(ordering=G.LEX))
+    e = rel(host(ug), ref)
+    assert e < sweep_tolerance(orc), e
+
+
 @pytest.mark.parametrize("d,p,m", [(2, 3, 32), (2, 4, 25), (2, 8, 12), (3, 3, 6)])
 def test_transfer_parity(d, p, m):
     G, orc, gp = _pair(d, p, m, vcycle=False, direct=False)
