@@ -210,6 +210,28 @@ __device__ __forceinline__ void xcd_tile_2d(int &bx, int &by) {
     xcd_relabel(int(blockIdx.y * gridDim.x + blockIdx.x), int(gridDim.x), int(gridDim.x * gridDim.y), bx, by);
 }
 
+// LDS staging of a window of a grid: dst[h] = get(h) for h < nh, thread t
+// taking h = t, t + blockDim, ...  Each thread issues U loads before its
+// first LDS store, so U memory round trips overlap instead of following one
+// another (a plain strided loop waits for every load before the next).
+template <int U, class T, class Get>
+__device__ __forceinline__ void stage_lds(T *dst, int nh, Get get) {
+    const int nt = int(blockDim.x);
+    for (int base = int(threadIdx.x); base < nh; base += U * nt) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int hh = base + u * nt;
+            v[u] = hh < nh ? get(hh) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int hh = base + u * nt;
+            if (hh < nh) dst[hh] = v[u];
+        }
+    }
+}
+
 // block classes of the Schwarz inverses, as the kernels compute them: the
 // number L of boundary classes on each side with shared inverses, -1 when
 // every position has its own inverse (must match host_block_classes)

@@ -24,9 +24,9 @@ inline unsigned nblk(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 // ------------------------------------------------------------------------
 // r = b - A x on tiles of 64 x (4*RY) points.  Each thread owns a column of
 // RY consecutive points (x fixed); the LDS rows it needs are read once into
-// registers and reused by every output of the column they touch.  Tiles whose
-// rows all carry the interior stencil (kappa = 1) take it from cs; other tiles
-// read the diagonals of the symmetric padded-diagonal operator.
+// registers and reused by every output of the column they touch.  Columns
+// whose rows all carry the interior stencil (kappa = 1) take it from cs; the
+// others read the diagonals of the symmetric padded-diagonal operator.
 constexpr int kResTX = 64, kResTYT = 4, kResRY = 8;
 
 template <int P, class T, bool NORM>
@@ -39,21 +39,24 @@ __global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d(const T *__restr
     constexpr int TX = kResTX, TY = kResTYT * kResRY, RY = kResRY;
     constexpr int HX = TX + 2 * P, HY = TY + 2 * P;
     constexpr int W1 = 2 * P + 1, W = W1 * W1, C0 = (W - 1) / 2;
+    constexpr int NT = kResTX * kResTYT;
     __shared__ T xs[HX * HY];
     const int stop = skip ? *skip : 0;
     int bx, by;
     xcd_tile_2d(bx, by);
     const int gx0 = bx * TX, gy0 = by * TY;
-    for (int h = threadIdx.x; h < HX * HY; h += blockDim.x) {
-        const int hx = h % HX, hy = h / HX;
-        const int gx = gx0 + hx - P, gy = gy0 + hy - P;
-        xs[h] = (gx >= 0 && gx < n1 && gy >= 0 && gy < n1) ? x[int64_t(gy) * n1 + gx] : T(0);
-    }
-    __syncthreads();
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int gx = gx0 + tx, gyb = gy0 + ty * RY;
-    const bool uni = cs != nullptr && gx0 >= ulo && min(gx0 + TX, n1) - 1 <= uhi && gy0 >= ulo &&
-                     min(gy0 + TY, n1) - 1 <= uhi;
+    // the whole halo in one round trip
+    stage_lds<(HX * HY + NT - 1) / NT>(xs, HX * HY, [&](int h) {
+        const int hx = h % HX, hy = h / HX;
+        const int hgx = gx0 + hx - P, hgy = gy0 + hy - P;
+        return (hgx >= 0 && hgx < n1 && hgy >= 0 && hgy < n1) ? x[int64_t(hgy) * n1 + hgx] : T(0);
+    });
+    __syncthreads();
+    // per column: the interior stencil when all its rows carry it (columns next
+    // to the grid boundary read the operator; a wavefront holds one row band)
+    const bool uni = cs != nullptr && gx >= ulo && gx <= uhi && gyb >= ulo && min(gyb + RY, n1) - 1 <= uhi;
     T acc[RY];
 #pragma unroll
     for (int k = 0; k < RY; ++k) acc[k] = T(0);
@@ -198,11 +201,11 @@ __device__ __forceinline__ void prolong2d_body(const T *__restrict__ R1, int p, 
     T *ry = rx + KX * w;                           // [KY][w]
     const int stop = skip ? *skip : 0;
     const int i0 = bx * TX, j0 = by * TY;
-    for (int h = threadIdx.x; h < KX * KY; h += blockDim.x) {
+    stage_lds<4>(es, KX * KY, [&](int h) {
         const int hx = h % KX, hy = h / KX;
         const int Ix = i0 - p + hx, Iy = j0 - p + hy;
-        es[h] = (Ix >= 0 && Ix < n1c && Iy >= 0 && Iy < n1c) ? ec[int64_t(Iy) * n1c + Ix] : T(0);
-    }
+        return (Ix >= 0 && Ix < n1c && Iy >= 0 && Iy < n1c) ? ec[int64_t(Iy) * n1c + Ix] : T(0);
+    });
     for (int h = threadIdx.x; h < KX * w; h += blockDim.x) {
         const int I = i0 - p + h / w;
         rx[h] = (I >= 0 && I < n1c) ? R1[int64_t(I) * w + h % w] : T(0);
@@ -225,21 +228,41 @@ __device__ __forceinline__ void prolong2d_body(const T *__restrict__ R1, int p, 
     }
     __syncthreads();
     if (stop) return;
-    for (int h = threadIdx.x; h < TX * TY; h += blockDim.x) {
-        const int tx = h % TX, ty = h / TX;
-        const int i = i0 + tx, j = j0 + ty;
-        if (i >= n1f || j >= n1f) continue;
-        T acc = T(0);
-        for (int q = 0; q < w; ++q) {
-            const int ky = ty + q;
-            acc += ry[ky * w + (p + 1 - q)] * ts[ky * TX + tx];
+    // y pass and update, four points per thread at a time: their global
+    // operands are loaded before the first is updated
+    constexpr int U = 4;
+    const int nt = int(blockDim.x);
+    for (int base = threadIdx.x; base < TX * TY; base += U * nt) {
+        T ov[U];
+        double uv[U];
+        int64_t gv[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int h = base + u * nt;
+            const int tx = h % TX, ty = h / TX;
+            const int i = i0 + tx, j = j0 + ty;
+            ok[u] = h < TX * TY && i < n1f && j < n1f;
+            gv[u] = ok[u] ? int64_t(j) * n1f + i : 0;
+            ov[u] = ok[u] ? (mode == 0 ? uf[gv[u]] : e[gv[u]]) : T(0);
+            uv[u] = (ok[u] && mode != 0) ? u64[gv[u]] : 0.0;
         }
-        const int64_t gi = int64_t(j) * n1f + i;
-        if (mode == 0) {
-            uf[gi] += acc;
-        } else {
-            const T corr = e[gi] + acc;
-            u64[gi] += scaled ? scal[kScalSigma] * double(corr) : double(corr);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const int h = base + u * nt;
+            const int tx = h % TX, ty = h / TX;
+            T acc = T(0);
+            for (int q = 0; q < w; ++q) {
+                const int ky = ty + q;
+                acc += ry[ky * w + (p + 1 - q)] * ts[ky * TX + tx];
+            }
+            if (mode == 0) {
+                uf[gv[u]] = ov[u] + acc;
+            } else {
+                const T corr = ov[u] + acc;
+                u64[gv[u]] = uv[u] + (scaled ? scal[kScalSigma] * double(corr) : double(corr));
+            }
         }
     }
 }

@@ -18,6 +18,8 @@ namespace {
 constexpr int kWave = 64;
 // at most 512 threads per Schwarz tile: 256 VGPRs per lane, no spills for 7x7 blocks
 constexpr int kColourThreads = 512;
+// grids below this many unknowns take the register-prefetching Schwarz kernel
+constexpr int64_t kColourPreMaxN = int64_t(1) << 19;
 
 __host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
 
@@ -243,8 +245,26 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
             for (int l = 0; l < BD; ++l) irow[l] = row[l];
         }
     }
-    // the interior stencil (kappa = 1) staged in LDS behind the residuals
+    // one path per wavefront: the interior stencil when all its rows carry it
+    const bool uni = cs != nullptr && __all(!mine || point_uniform(gx, gy, gz, ulo, uhi, D));
+    // the operator row of a point next to the grid boundary (PRE, 2-D, short
+    // rows): loaded with the halo instead of after it
     constexpr int W = cpow(2 * P + 1, D);
+    constexpr bool kPreVal = PRE && D == 2 && W * sizeof(T) <= 392;
+    T arow[kPreVal ? W : 1];
+    if constexpr (kPreVal) {
+        if (!uni && mine && in_block && !x_zero) {
+            const int64_t padi = int64_t(gx + P) + int64_t(gy + P) * pitch1;
+#pragma unroll
+            for (int qy = -P; qy <= P; ++qy)
+#pragma unroll
+                for (int qx = -P; qx <= P; ++qx) {
+                    const int w = (qy + P) * (2 * P + 1) + (qx + P);
+                    arow[w] = dia_entry<D, P, T>(val, npad, padi, w, int64_t(qx) + int64_t(qy) * pitch1);
+                }
+        }
+    }
+    // the interior stencil (kappa = 1) staged in LDS behind the residuals
     T *css = rs + ntile;
     if (!x_zero) {
         if (cs)
@@ -257,8 +277,6 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
         }
         __syncthreads();
     }
-    // one path per wavefront: the interior stencil when all its rows carry it
-    const bool uni = cs != nullptr && __all(!mine || point_uniform(gx, gy, gz, ulo, uhi, D));
     const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
     T res = T(0);
     T cast_rhs = T(0);
@@ -293,8 +311,10 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
 #pragma unroll
                         for (int qx = -P; qx <= P; ++qx) {
                             const int w = (qy + P) * (2 * P + 1) + (qx + P);
-                            acc += dia_entry<D, P, T>(val, npad, padi, w, int64_t(qx) + int64_t(qy) * pitch1) *
-                                   xs[lc + qy * HX + qx];
+                            T a;
+                            if constexpr (kPreVal) a = arow[w];
+                            else a = dia_entry<D, P, T>(val, npad, padi, w, int64_t(qx) + int64_t(qy) * pitch1);
+                            acc += a * xs[lc + qy * HX + qx];
                         }
                 } else {
 #pragma unroll 1
@@ -334,7 +354,8 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
     x_dst[gi] = xi + delta;
 }
 
-template <int D, int P, int B, class T>
+// PRE: operands held in registers ahead of use (latency-bound grids)
+template <int D, int P, int B, class T, bool PRE>
 __global__ void __launch_bounds__(kColourThreads) k_colour(const T *__restrict__ val, int64_t npad, int pitch1, int pitch2,
                                                  int n1, const T *__restrict__ inv, int clsL, int ncls1, const T *__restrict__ x_src, T *__restrict__ x_dst,
                                                  const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz,
@@ -345,7 +366,7 @@ __global__ void __launch_bounds__(kColourThreads) k_colour(const T *__restrict__
     extern __shared__ unsigned char smem_raw[];
     int bx = blockIdx.x, by = blockIdx.y;
     if (D == 2) xcd_tile_2d(bx, by);
-    colour_body<D, P, B, T, true>(val, npad, pitch1, pitch2, n1, inv, clsL, ncls1, x_src, x_dst, rhs, x_zero, ox, oy,
+    colour_body<D, P, B, T, PRE>(val, npad, pitch1, pitch2, n1, inv, clsL, ncls1, x_src, x_dst, rhs, x_zero, ox, oy,
                                   oz, S, NBX, NBY, NBZ, cs, ulo, uhi, skip, r64, scal, rhs_out, bx, by,
                                   int(blockIdx.z), smem_raw);
 }
@@ -799,7 +820,10 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
                                                   : reinterpret_cast<const T *>(Pb.A.v32.ptr);
     const T *inv = std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.Inv64.ptr)
                                                   : reinterpret_cast<const T *>(Pb.Inv32.ptr);
-    hipLaunchKernelGGL((k_colour<D, P, B, T>), grid, dim3(threads), shm, s, val, Pb.A.npad, Pb.A.pitch[1],
+    // small grids are latency-bound: operands in registers ahead of use; large
+    // ones keep the registers for occupancy
+    auto kern = Pb.fine.n < kColourPreMaxN ? k_colour<D, P, B, T, true> : k_colour<D, P, B, T, false>;
+    hipLaunchKernelGGL(kern, grid, dim3(threads), shm, s, val, Pb.A.npad, Pb.A.pitch[1],
                        Pb.A.pitch[2], n1, inv, class_split(Pb), Pb.ncls1, x_src, x_dst, rhs, x_zero ? 1 : 0, ox,
                        oy, oz, S, nbx, nby, nbz, uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, r64,
                        Pb.scal.as<double>(), rhs_out);
