@@ -230,8 +230,10 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
     if (mine && in_block && !r64) rhs_v = rhs[gi];
     if (mine && r64) r64_v = r64[gi];
     // row loc of the block inverse (PRE: held in registers when it is short,
-    // for latency-bound launches; batched launches keep the registers free)
-    constexpr bool kPreRow = PRE && BD * sizeof(T) <= 128;
+    // for latency-bound launches; batched launches keep the registers free).
+    // Not for the 25-entry rows of 2-D 5x5 blocks: held in registers they made
+    // the FP32 sweep at p = 5 take 1.6x as long.
+    constexpr bool kPreRow = PRE && BD * sizeof(T) <= 128 && !(D == 2 && B == 5);
     constexpr int NR = kPreRow ? BD : 1;
     T irow[NR];
     const T *row = nullptr;
