@@ -3,6 +3,9 @@
 FP64 bar: 1e-12 relative (norm-wise) per operation and per cycle iterate,
 on the same seeded inputs and the same block ordering.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -225,3 +228,40 @@ def test_full_size_cycle_parity_256(m):
         e = rel(its[k], u)
         print(f"[256^2] cycle {k + 1}: relative difference {e:.2e}")
         assert e < 1e-12, e
+
+
+GOLDEN_LARGE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_grid_2d_p3_m1024.json")
+
+
+def test_large_grid_kernels_sampled():
+    """2-D p=3 on 1024x1024 elements (1.05 M DOFs), where the residual runs as
+    the column-blocked kernel and the transfers on 64x16 tiles:
+    sampled entries and the 2-norms of the whole vectors against the oracle
+    (values written by tests/golden/make_large_grid.py, which calls only the
+    oracle)."""
+    G = _gpu()
+    ref = json.load(open(GOLDEN_LARGE))
+    d, p, m = 2, 3, 1024
+    print(f"\n[case] large grid d={d} p={p} m={m}", flush=True)
+    gp = G.Problem(d, p, m)
+    gp.setup(0, G.Opts())
+    assert gp.n == ref["n"] and gp.nc == ref["nc"]
+    u = synth.initial_guess(d, p, m, seed=1)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    x = synth.rhs_normal(d, p, m, seed=3)
+    ec = synth.rhs_normal(d, 1, m, seed=4)
+
+    def check(name, full):
+        idx = np.array(ref[name]["index"], dtype=np.int64)
+        want = np.array([float(v) for v in ref[name]["value"]])
+        e = rel(full[idx], want)
+        en = abs(np.linalg.norm(full) / float(ref["norms"][name.replace("_add", "") + "_l2"]) - 1.0)
+        print(f"[large] {name}: sampled rel {e:.2e}, norm rel {en:.2e}", flush=True)
+        assert e < 1e-12 and en < 1e-12, (name, e, en)
+
+    for _ in range(2):  # the second call reuses the norm partials of the first
+        check("residual", host(gp.residual(dev(u), dev(b))))
+    check("restrict", host(gp.restrict(dev(x))))
+    ug = dev(u)
+    gp.prolong_add(dev(ec), ug)
+    check("prolong_add", host(ug))
