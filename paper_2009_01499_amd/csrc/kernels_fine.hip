@@ -431,13 +431,70 @@ __global__ void __launch_bounds__(128) k_lex_step(const double *__restrict__ val
 // The whole lexicographic sweep in one workgroup (small grids): the iterate,
 // the right-hand side and the step schedule live in LDS, the steps run one
 // after the other with a barrier between them, each step's blocks in
-// parallel, one thread per block point.  A thread issues the loads of its
-// inverse row and, next to the grid boundary, of its operator row before it
-// forms the block residual, so a step waits for one round trip to memory.
+// parallel, one thread per block point.  A thread loads its inverse row and,
+// next to the grid boundary, its operator row (2-D, p <= 3) one step ahead,
+// so the memory latency overlaps the previous step instead of adding to it.
 // Same arithmetic as k_lex_step (interior rows read the interior stencil,
 // which equals their diagonals bit for bit; out-of-grid neighbours are
 // skipped), so the result equals the step-by-step launches.
 constexpr int kLexThreads = 256;
+
+// one thread's point in one step and the operands it loads for it
+template <int D, int P, int B>
+struct LexPoint {
+    static constexpr int BD = cpow(B, D);
+    static constexpr bool kPreA = D == 2 && P <= 3;  // operator row held in registers
+    static constexpr int NA = kPreA ? cpow(2 * P + 1, D) : 1;
+    bool act = false, in = false, uni = false;
+    int gx = 0, gy = 0, gz = 0, gi = 0;
+    double row[BD];
+    double a[NA];
+};
+
+template <int D, int P, int B>
+__device__ __forceinline__ void lex_point_load(LexPoint<D, P, B> &q, int st, int nsteps, const int *off,
+                                               const int *blk, int n1, const double *__restrict__ val,
+                                               int64_t npad, int pitch1, const double *__restrict__ inv, int clsL,
+                                               int ncls1, bool has_cs, int ulo, int uhi) {
+    constexpr int BD = cpow(B, D);
+    constexpr int HB = (B - 1) / 2;
+    const int idx = threadIdx.x, l = idx % BD;
+    q.act = false;
+    q.in = false;
+    if (st >= nsteps) return;
+    const int first = off[st], cnt = off[st + 1] - first;
+    q.act = idx < cnt * BD;
+    if (!q.act) return;
+    const int j = blk[first + idx / BD];
+    const int jx = j % n1, jy = (j / n1) % n1, jz = (D == 3) ? j / (n1 * n1) : 0;
+    q.gx = jx + l % B - HB;
+    q.gy = jy + (l / B) % B - HB;
+    q.gz = (D == 3) ? jz + l / (B * B) - HB : 0;
+    q.in = q.gx >= 0 && q.gx < n1 && q.gy >= 0 && q.gy < n1 && (D == 2 || (q.gz >= 0 && q.gz < n1));
+    if (!q.in) return;
+    q.gi = (q.gz * n1 + q.gy) * n1 + q.gx;
+    q.uni = has_cs && point_uniform(q.gx, q.gy, q.gz, ulo, uhi, D);
+    int64_t slot = block_class(jx, n1, clsL) + int64_t(ncls1) * block_class(jy, n1, clsL);
+    if (D == 3) slot += int64_t(ncls1) * ncls1 * block_class(jz, n1, clsL);
+    const double *ir = inv + (slot * BD + l) * BD;
+#pragma unroll
+    for (int k = 0; k < BD; ++k) q.row[k] = ir[k];
+    if constexpr (LexPoint<D, P, B>::kPreA) {
+        if (!q.uni) {
+            const int64_t padi = int64_t(q.gx + P) + int64_t(q.gy + P) * pitch1;
+#pragma unroll
+            for (int qy = -P; qy <= P; ++qy)
+#pragma unroll
+                for (int qx = -P; qx <= P; ++qx) {
+                    const int hx = q.gx + qx, hy = q.gy + qy;
+                    const bool ok = hx >= 0 && hx < n1 && hy >= 0 && hy < n1;
+                    const int w = (qy + P) * (2 * P + 1) + (qx + P);
+                    q.a[w] = ok ? dia_entry<D, P, double>(val, npad, padi, w, int64_t(qx) + int64_t(qy) * pitch1)
+                                : 0.0;
+                }
+        }
+    }
+}
 
 template <int D, int P, int B>
 __global__ void __launch_bounds__(kLexThreads) k_lex_sweep(const double *__restrict__ val, int64_t npad, int pitch1,
@@ -449,9 +506,9 @@ __global__ void __launch_bounds__(kLexThreads) k_lex_sweep(const double *__restr
                                                            const int *__restrict__ skip) {
     if (skip && *skip) return;
     constexpr int BD = cpow(B, D);
-    constexpr int HB = (B - 1) / 2;
     constexpr int W = cpow(2 * P + 1, D);
     constexpr int WP = cpow(2 * P + 1, 2);  // one z plane of the stencil
+    using LP = LexPoint<D, P, B>;
     extern __shared__ unsigned char smem_raw[];
     const int n = (D == 3) ? n1 * n1 * n1 : n1 * n1;
     double *us = reinterpret_cast<double *>(smem_raw);
@@ -470,28 +527,19 @@ __global__ void __launch_bounds__(kLexThreads) k_lex_sweep(const double *__restr
         for (int w = threadIdx.x; w < W; w += blockDim.x) css[w] = cs[w];
     __syncthreads();
     const int idx = threadIdx.x;
-    const int l = idx % BD;
+    LP cur, nxt;
+    lex_point_load<D, P, B>(cur, 0, nsteps, off, blk, n1, val, npad, pitch1, inv, clsL, ncls1, cs != nullptr, ulo,
+                            uhi);
     for (int st = 0; st < nsteps; ++st) {
-        const int first = off[st], cnt = off[st + 1] - first;
-        const bool act = idx < cnt * BD;
-        bool in = false;
-        int gi = 0;
-        double row[BD];
-        if (act) {
-            const int j = blk[first + idx / BD];
-            const int jx = j % n1, jy = (j / n1) % n1, jz = (D == 3) ? j / (n1 * n1) : 0;
-            const int gx = jx + l % B - HB, gy = jy + (l / B) % B - HB, gz = (D == 3) ? jz + l / (B * B) - HB : 0;
-            in = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && (D == 2 || (gz >= 0 && gz < n1));
+        // the next step's operands: in flight during this step
+        lex_point_load<D, P, B>(nxt, st + 1, nsteps, off, blk, n1, val, npad, pitch1, inv, clsL, ncls1,
+                                cs != nullptr, ulo, uhi);
+        if (cur.act) {
             double r = 0.0;
-            if (in) {
-                gi = (gz * n1 + gy) * n1 + gx;
-                int64_t slot = block_class(jx, n1, clsL) + int64_t(ncls1) * block_class(jy, n1, clsL);
-                if (D == 3) slot += int64_t(ncls1) * ncls1 * block_class(jz, n1, clsL);
-                const double *ir = inv + (slot * BD + l) * BD;
-#pragma unroll
-                for (int k = 0; k < BD; ++k) row[k] = ir[k];
+            if (cur.in) {
+                const int gx = cur.gx, gy = cur.gy, gz = cur.gz, gi = cur.gi;
                 double acc = 0.0;
-                if (cs && point_uniform(gx, gy, gz, ulo, uhi, D)) {
+                if (cur.uni) {
                     // every neighbour lies inside the grid
 #pragma unroll 1
                     for (int qz = ((D == 3) ? -P : 0); qz <= ((D == 3) ? P : 0); ++qz)
@@ -501,6 +549,15 @@ __global__ void __launch_bounds__(kLexThreads) k_lex_sweep(const double *__restr
                             for (int qx = -P; qx <= P; ++qx)
                                 acc += css[(D == 3 ? (qz + P) * WP : 0) + (qy + P) * (2 * P + 1) + (qx + P)] *
                                        us[gi + (qz * n1 + qy) * n1 + qx];
+                } else if constexpr (LP::kPreA) {
+#pragma unroll
+                    for (int qy = -P; qy <= P; ++qy)
+#pragma unroll
+                        for (int qx = -P; qx <= P; ++qx) {
+                            const int hx = gx + qx, hy = gy + qy;
+                            const bool ok = hx >= 0 && hx < n1 && hy >= 0 && hy < n1;
+                            if (ok) acc += cur.a[(qy + P) * (2 * P + 1) + (qx + P)] * us[gi + qy * n1 + qx];
+                        }
                 } else {
                     const int64_t padi =
                         int64_t(gx + P) + int64_t(gy + P) * pitch1 + ((D == 3) ? int64_t(gz + P) * pitch2 : 0);
@@ -542,14 +599,15 @@ __global__ void __launch_bounds__(kLexThreads) k_lex_sweep(const double *__restr
             rs[idx] = r;
         }
         __syncthreads();
-        if (act && in) {
+        if (cur.act && cur.in) {
             const double *rb = rs + (idx / BD) * BD;
             double delta = 0.0;
 #pragma unroll
-            for (int k = 0; k < BD; ++k) delta += row[k] * rb[k];
-            us[gi] += delta;
+            for (int k = 0; k < BD; ++k) delta += cur.row[k] * rb[k];
+            us[cur.gi] += delta;
         }
         __syncthreads();
+        cur = nxt;
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = us[i];
 }
