@@ -55,6 +55,49 @@ __device__ __forceinline__ bool point_uniform(int x, int y, int z, int ulo, int 
     return x >= ulo && x <= uhi && y >= ulo && y <= uhi && (dim == 2 || (z >= ulo && z <= uhi));
 }
 
+// ------------------------------------------------------------------------
+// kappa = 1 in 3-D: the operator is K1 (x) M1 (x) M1 + M1 (x) K1 (x) M1 +
+// M1 (x) M1 (x) K1.  The entry for offsets (ox, oy, oz) from the 1-D factor
+// entries of the point's rows, with the products and sums in the order (and
+// the rounding, no contraction) of the assembly of the diagonals, so it
+// equals the stored diagonal bit for bit.  Out-of-grid neighbours give 0.
+__device__ __forceinline__ double kron3_entry(double kx, double mx, double ky, double my, double kz, double mz) {
+    const double p0 = __dmul_rn(__dmul_rn(kx, my), mz);
+    const double p1 = __dmul_rn(__dmul_rn(mx, ky), mz);
+    const double p2 = __dmul_rn(__dmul_rn(mx, my), kz);
+    return __dadd_rn(__dadd_rn(__dadd_rn(0.0, p0), p1), p2);
+}
+
+// 3-D row of a point next to the boundary from the 1-D factors (K then M,
+// [n1][2P+1] each), accumulated against the LDS halo in the diagonal order
+template <int P, class T>
+__device__ __forceinline__ T kron3_row_dot(const double *__restrict__ kron, int n1, int gx, int gy, int gz,
+                                           const T *xs, int lc, int HX, int HY) {
+    constexpr int W1 = 2 * P + 1;
+    const double *K = kron, *M = kron + int64_t(n1) * W1;
+    // the x rows stay in registers; the y and z loops stay rolled (register budget)
+    double kx[W1], mx[W1];
+#pragma unroll
+    for (int o = 0; o < W1; ++o) {
+        kx[o] = K[gx * W1 + o];
+        mx[o] = M[gx * W1 + o];
+    }
+    T acc = T(0);
+#pragma unroll 1
+    for (int oz = -P; oz <= P; ++oz) {
+        const double kz = K[gz * W1 + oz + P], mz = M[gz * W1 + oz + P];
+#pragma unroll 1
+        for (int oy = -P; oy <= P; ++oy) {
+            const double ky = K[gy * W1 + oy + P], my = M[gy * W1 + oy + P];
+            const T *xr = xs + lc + (oz * HY + oy) * HX;
+#pragma unroll
+            for (int ox = -P; ox <= P; ++ox)
+                acc += T(kron3_entry(kx[ox + P], mx[ox + P], ky, my, kz, mz)) * xr[ox];
+        }
+    }
+    return acc;
+}
+
 // Residual r = b - A x over tiles of TX x TY (x TZ) points; x staged in LDS
 // with a halo of width P (zeros outside the grid).  NORM: the per-workgroup
 // sums of r^2 are combined by the last workgroup to finish, in a fixed
@@ -66,7 +109,8 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
                                               int TX, int TY, int TZ, const T *__restrict__ x,
                                               const T *__restrict__ b, T *__restrict__ r, double *__restrict__ part,
                                               const T *__restrict__ cs, int ulo, int uhi,
-                                              const int *__restrict__ skip, int bx, int by, int bz, T *xs) {
+                                              const int *__restrict__ skip, int bx, int by, int bz, T *xs,
+                                              const double *__restrict__ kron = nullptr) {
     const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
     const int gx0 = bx * TX, gy0 = by * TY, gz0 = (D == 3) ? bz * TZ : 0;
@@ -126,6 +170,8 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
                         for (int ox = -P; ox <= P; ++ox)
                             acc += css[((oz + P) * (2 * P + 1) + (oy + P)) * (2 * P + 1) + (ox + P)] *
                                    xs[lc + (oz * HY + oy) * HX + ox];
+            } else if (kron) {
+                acc = kron3_row_dot<P, T>(kron, n1, gx, gy, gz, xs, lc, HX, HY);
             } else {
 #pragma unroll 1
                 for (int oz = -P; oz <= P; ++oz)
@@ -164,13 +210,14 @@ __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int
                                                   int n1, int TX, int TY, int TZ, const T *__restrict__ x,
                                                   const T *__restrict__ b, T *__restrict__ r,
                                                   double *__restrict__ partial, const T *__restrict__ cs, int ulo,
-                                                  int uhi, const int *__restrict__ skip) {
+                                                  int uhi, const int *__restrict__ skip,
+                                                  const double *__restrict__ kron) {
     extern __shared__ unsigned char smem_raw[];
     int bx = blockIdx.x, by = blockIdx.y;
     if (D == 2) xcd_tile_2d(bx, by);
     double *part = NORM ? partial + (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x : nullptr;
     residual_body<D, P, T, NORM>(val, npad, pitch1, pitch2, n1, TX, TY, TZ, x, b, r, part, cs, ulo, uhi, skip, bx, by,
-                                 int(blockIdx.z), reinterpret_cast<T *>(smem_raw));
+                                 int(blockIdx.z), reinterpret_cast<T *>(smem_raw), kron);
 }
 
 // ------------------------------------------------------------------------
@@ -194,7 +241,8 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
                                             int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo, int uhi,
                                             const int *__restrict__ skip, const double *__restrict__ r64,
                                             const double *__restrict__ scal, T *__restrict__ rhs_out, int tbx,
-                                            int tby, int tbz, unsigned char *smem_raw) {
+                                            int tby, int tbz, unsigned char *smem_raw,
+                                            const double *__restrict__ kron = nullptr) {
     // r64 != null (first colour of an FP32 correction sweep, x_zero): the
     // right-hand side is r64 / sigma, cast here and stored to rhs_out for the
     // later colours
@@ -318,6 +366,8 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
                             else a = dia_entry<D, P, T>(val, npad, padi, w, int64_t(qx) + int64_t(qy) * pitch1);
                             acc += a * xs[lc + qy * HX + qx];
                         }
+                } else if (kron) {
+                    acc = kron3_row_dot<P, T>(kron, n1, gx, gy, gz, xs, lc, HX, HY);
                 } else {
 #pragma unroll 1
                     for (int qz = -P; qz <= P; ++qz)
@@ -364,13 +414,13 @@ __global__ void __launch_bounds__(kColourThreads) k_colour(const T *__restrict__
                                                  int S, int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo,
                                                  int uhi, const int *__restrict__ skip,
                                                  const double *__restrict__ r64, const double *__restrict__ scal,
-                                                 T *__restrict__ rhs_out) {
+                                                 T *__restrict__ rhs_out, const double *__restrict__ kron) {
     extern __shared__ unsigned char smem_raw[];
     int bx = blockIdx.x, by = blockIdx.y;
     if (D == 2) xcd_tile_2d(bx, by);
     colour_body<D, P, B, T, PRE>(val, npad, pitch1, pitch2, n1, inv, clsL, ncls1, x_src, x_dst, rhs, x_zero, ox, oy,
                                   oz, S, NBX, NBY, NBZ, cs, ulo, uhi, skip, r64, scal, rhs_out, bx, by,
-                                  int(blockIdx.z), smem_raw);
+                                  int(blockIdx.z), smem_raw, kron);
 }
 
 // ------------------------------------------------------------------------
@@ -799,7 +849,7 @@ void residual_launch(const Problem &Pb, const T *val, const T *x, const T *b, T 
     nblocks = int(grid.x * grid.y * grid.z);
     hipLaunchKernelGGL((k_residual<D, P, T, NORM>), grid, dim3(TS::TX * TS::TY * TS::TZ), shm, s, val, Pb.A.npad,
                        Pb.A.pitch[1], Pb.A.pitch[2], n1, TS::TX, TS::TY, TS::TZ, x, b, r, partial,
-                       uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip);
+                       uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, Pb.kron64.as<double>());
     if (NORM)
         hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, Pb.partial.as<double>(), nblocks,
                            Pb.scal.as<double>(), scale_fp32 ? 1 : 0, book ? dev_flags(Pb) : nullptr, dev_hist(Pb),
@@ -886,7 +936,7 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
     hipLaunchKernelGGL(kern, grid, dim3(threads), shm, s, val, Pb.A.npad, Pb.A.pitch[1],
                        Pb.A.pitch[2], n1, inv, class_split(Pb), Pb.ncls1, x_src, x_dst, rhs, x_zero ? 1 : 0, ox,
                        oy, oz, S, nbx, nby, nbz, uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, r64,
-                       Pb.scal.as<double>(), rhs_out);
+                       Pb.scal.as<double>(), rhs_out, Pb.kron64.as<double>());
 }
 
 template <int D, int P, class T>

@@ -110,11 +110,17 @@ void element_matrices(int p, int m, std::vector<std::vector<double>> &Ke, std::v
             double x = (e + 0.5 * (gx[k] + 1.0)) * h, wq = 0.5 * h * gw[k];
             live_values(t, p, p + e, x, v, dv);
             for (int a = 0; a <= p; ++a)
-                for (int b = 0; b <= p; ++b) {
+                for (int b = a; b <= p; ++b) {
                     Ke[e][a * (p + 1) + b] += wq * dv[a] * dv[b];
                     Me[e][a * (p + 1) + b] += wq * v[a] * v[b];
                 }
         }
+        // symmetric bit for bit (the assembled 1-D factors then are too)
+        for (int a = 0; a <= p; ++a)
+            for (int b = 0; b < a; ++b) {
+                Ke[e][a * (p + 1) + b] = Ke[e][b * (p + 1) + a];
+                Me[e][a * (p + 1) + b] = Me[e][b * (p + 1) + a];
+            }
     }
     // Elements p .. m-1-p carry only cardinal (translated) B-splines, so their
     // matrices are equal in exact arithmetic; one copy for all of them makes
@@ -285,6 +291,29 @@ void host_assemble(Problem &P) {
     } else {
         P.ulo = 1;
         P.uhi = 0;
+    }
+
+    // kappa = 1 in 3-D: the 1-D factors, from which the kernels form the rows
+    // next to the boundary instead of reading (2p+1)^3 diagonals.  Their
+    // entry (i, i+o) and the stored entry (i+o, i) must agree bit for bit (so
+    // that an entry formed from row i equals the one the symmetric storage
+    // keeps for row i+o); otherwise the kernels read the diagonals.
+    P.kron64.free();
+    if (P.kappa_one && d == 3) {
+        bool sym = true;
+        for (int i = 0; i < n1 && sym; ++i)
+            for (int o = 0; o < w1; ++o) {
+                const int j = i + o - p;
+                if (j < 0 || j >= n1) continue;
+                const size_t a = size_t(i) * w1 + o, b = size_t(j) * w1 + (2 * p - o);
+                if (P.K1[a] != P.K1[b] || P.M1[a] != P.M1[b]) sym = false;
+            }
+        if (sym) {
+            std::vector<double> f(P.K1);
+            f.insert(f.end(), P.M1.begin(), P.M1.end());
+            P.kron64.alloc(f.size() * sizeof(double));
+            IGA2L_HIP(hipMemcpy(P.kron64.ptr, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
     }
 
     P.R1d64.alloc(P.R1.size() * sizeof(double));
