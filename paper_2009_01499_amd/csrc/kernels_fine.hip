@@ -69,14 +69,17 @@ __device__ __forceinline__ double kron3_entry(double kx, double mx, double ky, d
 }
 
 // 3-D row of a point next to the boundary from the 1-D factors (K then M,
-// [n1][2P+1] each), accumulated against the LDS halo in the diagonal order
+// [n1][2P+1] each), accumulated against the LDS halo in the diagonal order.
+// FP64: the entries equal the stored diagonals bit for bit.  FP32 (the
+// correction cycle): FP32 factors, the sum regrouped as
+// kx (my mz) + mx (ky mz + my kz), the yz part formed once per stencil row.
 template <int P, class T>
-__device__ __forceinline__ T kron3_row_dot(const double *__restrict__ kron, int n1, int gx, int gy, int gz,
-                                           const T *xs, int lc, int HX, int HY) {
+__device__ __forceinline__ T kron3_row_dot(const T *__restrict__ kron, int n1, int gx, int gy, int gz, const T *xs,
+                                           int lc, int HX, int HY) {
     constexpr int W1 = 2 * P + 1;
-    const double *K = kron, *M = kron + int64_t(n1) * W1;
+    const T *K = kron, *M = kron + int64_t(n1) * W1;
     // the x rows stay in registers; the y and z loops stay rolled (register budget)
-    double kx[W1], mx[W1];
+    T kx[W1], mx[W1];
 #pragma unroll
     for (int o = 0; o < W1; ++o) {
         kx[o] = K[gx * W1 + o];
@@ -85,14 +88,20 @@ __device__ __forceinline__ T kron3_row_dot(const double *__restrict__ kron, int 
     T acc = T(0);
 #pragma unroll 1
     for (int oz = -P; oz <= P; ++oz) {
-        const double kz = K[gz * W1 + oz + P], mz = M[gz * W1 + oz + P];
+        const T kz = K[gz * W1 + oz + P], mz = M[gz * W1 + oz + P];
 #pragma unroll 1
         for (int oy = -P; oy <= P; ++oy) {
-            const double ky = K[gy * W1 + oy + P], my = M[gy * W1 + oy + P];
+            const T ky = K[gy * W1 + oy + P], my = M[gy * W1 + oy + P];
             const T *xr = xs + lc + (oz * HY + oy) * HX;
+            if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-            for (int ox = -P; ox <= P; ++ox)
-                acc += T(kron3_entry(kx[ox + P], mx[ox + P], ky, my, kz, mz)) * xr[ox];
+                for (int ox = -P; ox <= P; ++ox)
+                    acc += kron3_entry(kx[ox + P], mx[ox + P], ky, my, kz, mz) * xr[ox];
+            } else {
+                const T a = my * mz, c = ky * mz + my * kz;
+#pragma unroll
+                for (int ox = -P; ox <= P; ++ox) acc += (kx[ox + P] * a + mx[ox + P] * c) * xr[ox];
+            }
         }
     }
     return acc;
@@ -110,7 +119,7 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
                                               const T *__restrict__ b, T *__restrict__ r, double *__restrict__ part,
                                               const T *__restrict__ cs, int ulo, int uhi,
                                               const int *__restrict__ skip, int bx, int by, int bz, T *xs,
-                                              const double *__restrict__ kron = nullptr) {
+                                              const T *__restrict__ kron = nullptr) {
     const int stop = skip ? *skip : 0;  // tested before the first store (hides the load latency)
     const int HX = TX + 2 * P, HY = TY + 2 * P, HZ = (D == 3) ? TZ + 2 * P : 1;
     const int gx0 = bx * TX, gy0 = by * TY, gz0 = (D == 3) ? bz * TZ : 0;
@@ -211,7 +220,7 @@ __global__ void __launch_bounds__(256) k_residual(const T *__restrict__ val, int
                                                   const T *__restrict__ b, T *__restrict__ r,
                                                   double *__restrict__ partial, const T *__restrict__ cs, int ulo,
                                                   int uhi, const int *__restrict__ skip,
-                                                  const double *__restrict__ kron) {
+                                                  const T *__restrict__ kron) {
     extern __shared__ unsigned char smem_raw[];
     int bx = blockIdx.x, by = blockIdx.y;
     if (D == 2) xcd_tile_2d(bx, by);
@@ -242,7 +251,7 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
                                             const int *__restrict__ skip, const double *__restrict__ r64,
                                             const double *__restrict__ scal, T *__restrict__ rhs_out, int tbx,
                                             int tby, int tbz, unsigned char *smem_raw,
-                                            const double *__restrict__ kron = nullptr) {
+                                            const T *__restrict__ kron = nullptr) {
     // r64 != null (first colour of an FP32 correction sweep, x_zero): the
     // right-hand side is r64 / sigma, cast here and stored to rhs_out for the
     // later colours
@@ -414,7 +423,7 @@ __global__ void __launch_bounds__(kColourThreads) k_colour(const T *__restrict__
                                                  int S, int NBX, int NBY, int NBZ, const T *__restrict__ cs, int ulo,
                                                  int uhi, const int *__restrict__ skip,
                                                  const double *__restrict__ r64, const double *__restrict__ scal,
-                                                 T *__restrict__ rhs_out, const double *__restrict__ kron) {
+                                                 T *__restrict__ rhs_out, const T *__restrict__ kron) {
     extern __shared__ unsigned char smem_raw[];
     int bx = blockIdx.x, by = blockIdx.y;
     if (D == 2) xcd_tile_2d(bx, by);
@@ -821,6 +830,13 @@ struct TileShape<3, P> {
     static constexpr int TX = 16, TY = 8, TZ = 2;
 };
 
+// 1-D factors for the 3-D boundary rows (null: read the diagonals)
+template <class T>
+const T *kron_factors(const Problem &Pb) {
+    return std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.kron64.ptr)
+                                          : reinterpret_cast<const T *>(Pb.kron32.ptr);
+}
+
 template <class T>
 const T *uniform_stencil(const Problem &Pb) {
     return std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.cs64.ptr)
@@ -849,7 +865,7 @@ void residual_launch(const Problem &Pb, const T *val, const T *x, const T *b, T 
     nblocks = int(grid.x * grid.y * grid.z);
     hipLaunchKernelGGL((k_residual<D, P, T, NORM>), grid, dim3(TS::TX * TS::TY * TS::TZ), shm, s, val, Pb.A.npad,
                        Pb.A.pitch[1], Pb.A.pitch[2], n1, TS::TX, TS::TY, TS::TZ, x, b, r, partial,
-                       uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, Pb.kron64.as<double>());
+                       uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, kron_factors<T>(Pb));
     if (NORM)
         hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, Pb.partial.as<double>(), nblocks,
                            Pb.scal.as<double>(), scale_fp32 ? 1 : 0, book ? dev_flags(Pb) : nullptr, dev_hist(Pb),
@@ -936,7 +952,7 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
     hipLaunchKernelGGL(kern, grid, dim3(threads), shm, s, val, Pb.A.npad, Pb.A.pitch[1],
                        Pb.A.pitch[2], n1, inv, class_split(Pb), Pb.ncls1, x_src, x_dst, rhs, x_zero ? 1 : 0, ox,
                        oy, oz, S, nbx, nby, nbz, uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, r64,
-                       Pb.scal.as<double>(), rhs_out, Pb.kron64.as<double>());
+                       Pb.scal.as<double>(), rhs_out, kron_factors<T>(Pb));
 }
 
 template <int D, int P, class T>

@@ -299,6 +299,7 @@ void host_assemble(Problem &P) {
     // that an entry formed from row i equals the one the symmetric storage
     // keeps for row i+o); otherwise the kernels read the diagonals.
     P.kron64.free();
+    P.kron32.free();
     if (P.kappa_one && d == 3) {
         bool sym = true;
         for (int i = 0; i < n1 && sym; ++i)
@@ -313,6 +314,9 @@ void host_assemble(Problem &P) {
             f.insert(f.end(), P.M1.begin(), P.M1.end());
             P.kron64.alloc(f.size() * sizeof(double));
             IGA2L_HIP(hipMemcpy(P.kron64.ptr, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice));
+            std::vector<float> f32(f.begin(), f.end());
+            P.kron32.alloc(f32.size() * sizeof(float));
+            IGA2L_HIP(hipMemcpy(P.kron32.ptr, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice));
         }
     }
 
