@@ -243,13 +243,14 @@ void host_assemble(Problem &P) {
                     if (j < 0 || j >= n1) in = false;
                 }
                 if (!in) continue;
+                // term c = F_x (F_y F_z) with F = K1 in direction c, M1 otherwise
+                // (the grouping the 3-D kernels reproduce when they form rows
+                // next to the boundary from the factors)
                 double term = 0.0;
                 for (int c = 0; c < d; ++c) {
-                    double prod = 1.0;
-                    for (int k = 0; k < d; ++k) {
-                        const std::vector<double> &F = (k == c) ? P.K1 : P.M1;
-                        prod *= F[size_t(ix[k]) * w1 + o[k]];
-                    }
+                    double f[kMaxDim];
+                    for (int k = 0; k < d; ++k) f[k] = ((k == c) ? P.K1 : P.M1)[size_t(ix[k]) * w1 + o[k]];
+                    const double prod = (d == 3) ? f[0] * (f[1] * f[2]) : (d == 2) ? f[0] * f[1] : f[0];
                     term += prod;
                 }
                 val[size_t(w - c0) * A.npad + padi] = term;
