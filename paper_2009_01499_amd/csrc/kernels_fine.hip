@@ -58,16 +58,21 @@ __device__ __forceinline__ bool point_uniform(int x, int y, int z, int ulo, int 
 // ------------------------------------------------------------------------
 // kappa = 1 in 3-D: the operator is K1 (x) M1 (x) M1 + M1 (x) K1 (x) M1 +
 // M1 (x) M1 (x) K1.  The entry for offsets (ox, oy, oz) from the 1-D factor
-// entries of the point's rows, with the products and sums grouped (and
-// rounded, no contraction) as in the assembly of the diagonals, so it equals
-// the stored diagonal bit for bit: kx (my mz) + mx (ky mz) + mx (my kz), the
-// yz products (myz, kymz, mykz) formed once per stencil row.  Out-of-grid
-// neighbours give 0.
+// entries of the point's rows, with the products and sums grouped and
+// rounded as in the assembly of the diagonals (contraction off, every
+// operation rounded on its own), so it equals the stored diagonal bit for
+// bit: kx (my mz) + mx (ky mz) + mx (my kz), the yz products (myz, kymz,
+// mykz) formed once per stencil row.  Out-of-grid neighbours give 0.
 __device__ __forceinline__ double kron3_entry(double kx, double mx, double myz, double kymz, double mykz) {
-    const double p0 = __dmul_rn(kx, myz);
-    const double p1 = __dmul_rn(mx, kymz);
-    const double p2 = __dmul_rn(mx, mykz);
-    return __dadd_rn(__dadd_rn(__dadd_rn(0.0, p0), p1), p2);
+#pragma clang fp contract(off)
+    const double p0 = kx * myz;
+    const double p1 = mx * kymz;
+    const double p2 = mx * mykz;
+    double t = 0.0;
+    t += p0;
+    t += p1;
+    t += p2;
+    return t;
 }
 
 // 3-D row of a point next to the boundary from the 1-D factors (K then M,
@@ -96,7 +101,7 @@ __device__ __forceinline__ T kron3_row_dot(const T *__restrict__ kron, int n1, i
             const T ky = K[gy * W1 + oy + P], my = M[gy * W1 + oy + P];
             const T *xr = xs + lc + (oz * HY + oy) * HX;
             if constexpr (std::is_same<T, double>::value) {
-                const double myz = __dmul_rn(my, mz), kymz = __dmul_rn(ky, mz), mykz = __dmul_rn(my, kz);
+                const double myz = my * mz, kymz = ky * mz, mykz = my * kz;
 #pragma unroll
                 for (int ox = -P; ox <= P; ++ox)
                     acc += kron3_entry(kx[ox + P], mx[ox + P], myz, kymz, mykz) * xr[ox];

@@ -6,6 +6,7 @@
 // per-cycle operation runs in the HIP kernels.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "internal.h"
@@ -301,7 +302,10 @@ void host_assemble(Problem &P) {
     // keeps for row i+o); otherwise the kernels read the diagonals.
     P.kron64.free();
     P.kron32.free();
-    if (P.kappa_one && d == 3) {
+    // IGA2L_DIAGONAL_ROWS=1 keeps the diagonals for every row (the two forms
+    // give the same FP64 results bit for bit; the switch lets that be checked)
+    const char *diag_rows = std::getenv("IGA2L_DIAGONAL_ROWS");
+    if (P.kappa_one && d == 3 && !(diag_rows && diag_rows[0] == '1')) {
         bool sym = true;
         for (int i = 0; i < n1 && sym; ++i)
             for (int o = 0; o < w1; ++o) {

@@ -265,3 +265,24 @@ def test_large_grid_kernels_sampled():
     ug = dev(u)
     gp.prolong_add(dev(ec), ug)
     check("prolong_add", host(ug))
+
+
+def test_3d_factor_rows_bitwise(monkeypatch):
+    """kappa = 1 in 3-D: rows next to the boundary formed from the 1-D factors
+    give the FP64 residual and Schwarz sweep of the stored diagonals bit for
+    bit (IGA2L_DIAGONAL_ROWS=1 makes set-up keep the diagonals for all rows)."""
+    G = _gpu()
+    d, p, m = 3, 3, 12
+    u = synth.initial_guess(d, p, m, seed=1)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("IGA2L_DIAGONAL_ROWS", flag)
+        gp = G.Problem(d, p, m)
+        gp.setup(0, G.Opts())
+        r = host(gp.residual(dev(u), dev(b)))
+        ug = dev(u)
+        gp.smooth(ug, dev(b), 1, G.Opts())
+        out.append((r, host(ug)))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
