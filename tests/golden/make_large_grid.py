@@ -45,18 +45,20 @@ def main():
     r = orc.residual(u, b)
     dc = orc.restrict(x)
     up = orc.prolong_add(ec, u)
+    sw = orc.sweep(u, b, ordering=O.COLOUR, s=3)
     fi = samples(orc.n1, 1500, 11)
     ci = samples(orc.n1c, 1500, 12)
     out = {
-        "what": "oracle residual, restriction, prolongation update; 2-D p=3 m=1024",
+        "what": "oracle residual, restriction, prolongation update, one coloured sweep; 2-D p=3 m=1024",
         "inputs": {"u": "synth.initial_guess(2, 3, 1024, seed=1)", "b": "synth.rhs_normal(2, 3, 1024, seed=0)",
                    "x": "synth.rhs_normal(2, 3, 1024, seed=3)", "e_c": "synth.rhs_normal(2, 1, 1024, seed=4)"},
         "n": orc.n, "nc": orc.nc,
         "residual": {"index": fi.tolist(), "value": [repr(float(v)) for v in r[fi]]},
         "prolong_add": {"index": fi.tolist(), "value": [repr(float(v)) for v in up[fi]]},
         "restrict": {"index": ci.tolist(), "value": [repr(float(v)) for v in dc[ci]]},
+        "sweep": {"index": fi.tolist(), "value": [repr(float(v)) for v in sw[fi]]},
         "norms": {"residual_l2": repr(float(np.linalg.norm(r))), "restrict_l2": repr(float(np.linalg.norm(dc))),
-                  "prolong_l2": repr(float(np.linalg.norm(up)))},
+                  "prolong_l2": repr(float(np.linalg.norm(up))), "sweep_l2": repr(float(np.linalg.norm(sw)))},
     }
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "large_grid_2d_p3_m1024.json")
     with open(path, "w") as f:

@@ -307,6 +307,100 @@ def test_restriction_closed_form_and_adjoint(p):
     assert np.allclose(R2, np.kron(R1, R1), atol=1e-15)
 
 
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6])
+def test_mixed_mass_polynomial_reproduction(p):
+    """Every row of M_p^1, the rows next to the boundary included, through an
+    identity that holds for any polynomial g of degree <= p vanishing at 0 and
+    1: g lies in the degree-p spline space, its B-spline coefficients at the
+    two ends are g(0) = g(1) = 0 (open knot vector), so with c the interior
+    coefficients, sum_j (M_p^1)_{Ij} c_j = integral of phi_I^1 g (Section
+    3.1.2, definition of M_p^{p_low}).  The coefficients come from scipy's
+    spline interpolation at the Greville abscissae, the integrals from Gauss
+    rules on the two elements of each hat; 1-D and the 2-D tensor case."""
+    from scipy.interpolate import make_interp_spline
+    m = 9
+    h = 1.0 / m
+    t = np.r_[np.zeros(p + 1), np.arange(1, m) / m, np.ones(p + 1)]
+    tau = np.array([t[i + 1:i + p + 1].mean() for i in range(m + p)])
+    xg, wg = np.polynomial.legendre.leggauss(p + 3)
+
+    def hat_integral(g, I):        # interior hat I, centred at node (I+1) h
+        xc = (I + 1) * h
+        tot = 0.0
+        for a, bnd in ((xc - h, xc), (xc, xc + h)):
+            x = 0.5 * (bnd - a) * xg + 0.5 * (a + bnd)
+            tot += 0.5 * (bnd - a) * np.sum(wg * g(x) * (1.0 - np.abs(x - xc) / h))
+        return tot
+
+    M1 = O.mix_to_dense(O.assemble_mix(1, p, 1, m), 1, p, 1, m)
+    M2 = O.mix_to_dense(O.assemble_mix(2, p, 1, m), 2, p, 1, m)
+    for k in range(p - 1):
+        def g(x, k=k):
+            return x * (1.0 - x) * (x - 0.3) ** k
+        c = make_interp_spline(tau, g(tau), k=p, t=t).c
+        assert abs(c[0]) < 1e-13 and abs(c[-1]) < 1e-13
+        ci = c[1:-1]
+        want = np.array([hat_integral(g, I) for I in range(m - 1)])
+        assert np.allclose(M1 @ ci, want, rtol=0, atol=1e-14 * np.abs(want).max()), (p, k)
+        assert np.allclose(M2 @ np.outer(ci, ci).ravel(), np.outer(want, want).ravel(), rtol=0,
+                           atol=1e-14 * np.abs(want).max() ** 2), (p, k)
+
+
+def test_seven_by_seven_sweep_sensitivity():
+    """The 7x7-block sweep (p = 7) of the oracle against the same sweep carried
+    out in extended precision (numpy longdouble, Gaussian elimination) on the
+    oracle's operator: agreement to 1e-13.  The same exact sweep on an equally
+    valid FP64 assembly of A (Kronecker products of the oracle's 1-D matrices,
+    within ~1e-15 of the quadrature-assembled entries) differs by more than
+    1e-12: blocks with condition numbers ~1e4 amplify last-bit differences of
+    the operator, which sets the GPU parity bar for 7x7 blocks (5e-11)."""
+    d, p, m = 2, 7, 14
+    P = O.Problem(d, p, m)
+    bw, n1, n = P.block_width, P.n1, P.n
+    A = O.offsets_to_dense(P.A(), d, n1, p)
+    K1 = O.offsets_to_dense(O.assemble(1, p, m, kind="stiff"), 1, n1, p)
+    M1 = O.offsets_to_dense(O.assemble(1, p, m, kind="mass"), 1, n1, p)
+    Ak = np.kron(M1, K1) + np.kron(K1, M1)
+    assert np.max(np.abs(A - Ak)) <= 5e-15 * np.max(np.abs(A))
+    u0 = synth.initial_guess(d, p, m, seed=1)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    members = [_block_members(d, n1, bw, j) for j in range(n)]
+
+    def ge_solve(Mx, r):
+        Mx, r = Mx.copy(), r.copy()
+        k = len(r)
+        for i in range(k):
+            f = Mx[i + 1:, i] / Mx[i, i]
+            Mx[i + 1:, i:] -= np.outer(f, Mx[i, i:])
+            r[i + 1:] -= f * r[i]
+        x = np.zeros_like(r)
+        for i in range(k - 1, -1, -1):
+            x[i] = (r[i] - Mx[i, i + 1:] @ x[i + 1:]) / Mx[i, i]
+        return x
+
+    def exact_sweep(Aop):
+        Al = Aop.astype(np.longdouble)
+        u, bl = u0.astype(np.longdouble), b.astype(np.longdouble)
+        for c in range(bw * bw):
+            r = bl - Al @ u
+            du = np.zeros_like(u)
+            for j in range(n):
+                if (j % n1) % bw + bw * ((j // n1) % bw) == c:
+                    I = members[j]
+                    du[I] += ge_solve(Al[np.ix_(I, I)], r[I])
+            u = u + du
+        return u
+
+    ext = exact_sweep(A)
+    ext_k = exact_sweep(Ak)
+    nrm = float(np.linalg.norm(ext))
+    e_orc = float(np.linalg.norm(P.sweep(u0, b, ordering=O.COLOUR, s=bw) - ext)) / nrm
+    e_asm = float(np.linalg.norm(ext_k - ext)) / nrm
+    print(f"oracle vs exact sweep {e_orc:.2e}; exact sweeps on two FP64 assemblies {e_asm:.2e}")
+    assert e_orc < 1e-13
+    assert 1e-12 < e_asm < 5e-11
+
+
 def test_exact_mass_inverse_variant():
     """lumped=0 applies (M_{plow}^{plow})^{-1} exactly."""
     d, p, m = 2, 3, 5
@@ -457,16 +551,17 @@ def _golden(name):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("p,m", [(2, 128), (3, 64), (4, 64), (5, 96)])
+@pytest.mark.parametrize("p,m", [(2, 128), (3, 64), (4, 64), (5, 96), (6, 64), (7, 64), (8, 64)])
 def test_table1_convergence_factors(p, m):
     """Table 1 (rho_h, exact coarse solve, p_low=1, same h, zero RHS, random
     initial guess): measured here as the geometric-mean residual reduction over
     cycles 10..K of the lexicographic two-level method; agreement within 8%
-    (the paper's grid size is not stated)."""
+    (the paper's grid size is not stated; at p = 6..8 the rate measured on
+    64x64 is 5-6 % below the paper's and rises with m)."""
     ref = {int(r[0]): (int(r[1]), r[2]) for r in _golden("table1_rho_h.txt")}
     bw, rho_paper = ref[p]
     P = O.Problem(2, p, m, block_width=bw)
-    K = 30 if p <= 4 else 25
+    K = 30 if p <= 4 else (25 if p <= 6 else 20)
     u0 = synth.initial_guess(2, p, m, seed=1)
     _, k, hist = P.solve(np.zeros(P.n), u0=u0, ordering=O.LEX, tol=0.0, max_cycles=K)
     est = (hist[K] / hist[10]) ** (1.0 / (K - 10))
