@@ -124,6 +124,23 @@ int iga2l_residual(const iga2l_problem *prob, const double *u, const double *b, 
 int iga2l_smooth(const iga2l_problem *prob, double *u, const double *b, int nsweeps,
                  const iga2l_opts *opts, void *stream);
 
+/*
+ * Allocation-free variant of iga2l_smooth, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and the same result, bit for bit,
+ * as iga2l_smooth with the coloured ordering (opts->ordering must be
+ * IGA2L_COLOUR, else EUNSUPPORTED).  The intermediate iterates of a sweep live
+ * in a fixed device array of the library (2 * IGA2L_NOALLOC_MAX_FINE doubles,
+ * 32 MiB, one copy per device, held until the process ends) instead of the
+ * problem's workspaces; the call performs no hipMalloc, hipFree or other
+ * allocation.  n_fine above IGA2L_NOALLOC_MAX_FINE: EINVAL.  Every call on
+ * one device shares that array: calls that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller.
+ */
+#define IGA2L_NOALLOC_MAX_FINE 2097152
+int iga2l_smooth_noalloc(const iga2l_problem *prob, double *u, const double *b, int nsweeps,
+                         const iga2l_opts *opts, void *stream);
+
 /* d_coarse = D^{-1} M_p^{1} r_fine: the restriction of Section 3.1.2 with the
  * row-sum lumped degree-1 mass matrix D.  FP64, n_fine -> n_coarse. */
 int iga2l_restrict(const iga2l_problem *prob, const double *r_fine, double *d_coarse, void *stream);

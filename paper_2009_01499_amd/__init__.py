@@ -88,6 +88,8 @@ _EXPORTS = {
     "iga2l_residual": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "iga2l_smooth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                     ctypes.POINTER(CIgaOpts), ctypes.c_void_p]),
+    "iga2l_smooth_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.POINTER(CIgaOpts), ctypes.c_void_p]),
     "iga2l_restrict": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "iga2l_prolong": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "iga2l_coarse_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -201,6 +203,14 @@ class Problem:
         o = (opts or Opts()).c()
         _check(lib().iga2l_smooth(self._h, _dev_ptr(u, self.n, "u"), _dev_ptr(b, self.n, "b"), nsweeps,
                                   ctypes.byref(o), _stream(stream)))
+        return u
+
+    def smooth_noalloc(self, u, b, nsweeps: int = 1, opts: Optional[Opts] = None, stream=None):
+        """iga2l_smooth_noalloc: the coloured sweeps of smooth() without any
+        device allocation (intermediate iterates in the library's fixed array)."""
+        o = (opts or Opts()).c()
+        _check(lib().iga2l_smooth_noalloc(self._h, _dev_ptr(u, self.n, "u"), _dev_ptr(b, self.n, "b"), nsweeps,
+                                          ctypes.byref(o), _stream(stream)))
         return u
 
     def restrict(self, r, dc=None, stream=None):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -273,6 +274,59 @@ bool knots_open_uniform(const double *t, int nt, int p, int &m) {
     return true;
 }
 
+// nsweeps coloured FP64 sweeps on A u = b in place on u; w0, w1: two device
+// vectors of n_fine doubles for the intermediate iterates (one kernel per
+// colour, each reading the colour-start iterate and writing the next one:
+// u -> w0 -> w1 -> w0 ... -> u)
+void smooth_colour(const Problem &P, double *u, const double *b, int nsweeps, int S, double *w0, double *w1,
+                   hipStream_t s) {
+    const size_t bytes = sizeof(double) * size_t(P.fine.n);
+    const int ncol = (P.dim == 3) ? S * S * S : S * S;
+    double *w[2] = {w0, w1};
+    for (int k = 0; k < nsweeps; ++k) {
+        if (ncol == 1) {
+            IGA2L_HIP(hipMemcpyAsync(w0, u, bytes, hipMemcpyDeviceToDevice, s));
+            launch_colour_step<double>(P, 0, 0, 0, S, w0, u, b, false, s);
+            continue;
+        }
+        const double *src = u;
+        int c = 0;
+        for (int cz = 0; cz < ((P.dim == 3) ? S : 1); ++cz)
+            for (int cy = 0; cy < S; ++cy)
+                for (int cx = 0; cx < S; ++cx, ++c) {
+                    double *dst = (c == ncol - 1) ? u : w[c & 1];
+                    launch_colour_step<double>(P, cx, cy, cz, S, src, dst, b, false, s);
+                    src = dst;
+                }
+    }
+}
+
+// Fixed device array of iga2l_smooth_noalloc: its two intermediate iterates of
+// at most IGA2L_NOALLOC_MAX_FINE doubles each.  Every device the library runs
+// on holds its own copy until the process ends.  Host code never uses the
+// array's name (a host-side stand-in); it uses the device address obtained
+// once per device by scratch_on().
+constexpr int64_t kNoAllocMaxFine = IGA2L_NOALLOC_MAX_FINE;
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxFine];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's copy of scratch; the caller has made the
+// device current
+double *scratch_on(int device) {
+    IGA2L_REQUIRE(device >= 0 && device < kMaxDevices, IGA2L_EUNSUPPORTED, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        IGA2L_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        IGA2L_REQUIRE(ptr != nullptr, IGA2L_EDEVICE, "hipGetSymbolAddress returned no address");
+        g_scratch_ptr[device] = static_cast<double *>(ptr);
+    }
+    return g_scratch_ptr[device];
+}
+
 }  // namespace
 }  // namespace iga2l
 
@@ -449,34 +503,40 @@ int iga2l_smooth(const iga2l_problem *prob, double *u, const double *b, int nswe
         check_opts(P, o);
         set_device(P);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const size_t bytes = sizeof(double) * size_t(P.fine.n);
-        if (o.ordering == IGA2L_LEX && P.lex_off.empty()) host_lex_schedule(P);
-        for (int k = 0; k < nsweeps; ++k) {
-            if (o.ordering == IGA2L_LEX) {
+        if (o.ordering == IGA2L_LEX) {
+            if (P.lex_off.empty()) host_lex_schedule(P);
+            for (int k = 0; k < nsweeps; ++k) {
                 if (lex_sweep_fits(P)) launch_lex_sweep(P, u, b, s);
                 else
                     for (size_t st = 0; st + 1 < P.lex_off.size(); ++st) launch_lex_step(P, int(st), u, b, s);
-            } else {
-                const int S = o.colour_period ? o.colour_period : P.bw;
-                const int ncol = (P.dim == 3) ? S * S * S : S * S;
-                if (ncol == 1) {
-                    IGA2L_HIP(hipMemcpyAsync(P.ework[0].ptr, u, bytes, hipMemcpyDeviceToDevice, s));
-                    launch_colour_step<double>(P, 0, 0, 0, S, P.ework[0].as<double>(), u, b, false, s);
-                    continue;
-                }
-                // u -> w0 -> w1 -> w0 ... -> u: one kernel per colour, each reading the
-                // colour-start iterate and writing the next one
-                const double *src = u;
-                int c = 0;
-                for (int cz = 0; cz < ((P.dim == 3) ? S : 1); ++cz)
-                    for (int cy = 0; cy < S; ++cy)
-                        for (int cx = 0; cx < S; ++cx, ++c) {
-                            double *dst = (c == ncol - 1) ? u : P.ework[c & 1].as<double>();
-                            launch_colour_step<double>(P, cx, cy, cz, S, src, dst, b, false, s);
-                            src = dst;
-                        }
             }
+        } else {
+            const int S = o.colour_period ? o.colour_period : P.bw;
+            smooth_colour(P, u, b, nsweeps, S, P.ework[0].as<double>(), P.ework[1].as<double>(), s);
         }
+        IGA2L_HIP(hipGetLastError());
+    });
+}
+
+int iga2l_smooth_noalloc(const iga2l_problem *prob, double *u, const double *b, int nsweeps,
+                         const iga2l_opts *opts, void *stream) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob && u && b, IGA2L_EINVAL, "null argument");
+        IGA2L_REQUIRE(nsweeps >= 0, IGA2L_EINVAL, "nsweeps must be >= 0");
+        const Problem &P = prob->P;
+        IGA2L_REQUIRE(P.fine.n <= kNoAllocMaxFine, IGA2L_EINVAL,
+                      "iga2l_smooth_noalloc: n_fine = " + std::to_string(P.fine.n) +
+                          " exceeds IGA2L_NOALLOC_MAX_FINE = " + std::to_string(kNoAllocMaxFine));
+        IGA2L_REQUIRE(P.blocks_ready, IGA2L_EINVAL, "iga2l_setup_blocks must run first");
+        iga2l_opts o = effective_opts(opts);
+        o.precision = IGA2L_FP64;
+        check_opts(P, o);
+        IGA2L_REQUIRE(o.ordering == IGA2L_COLOUR, IGA2L_EUNSUPPORTED,
+                      "iga2l_smooth_noalloc runs the coloured ordering only");
+        set_device(P);
+        double *w = scratch_on(P.device);
+        const int S = o.colour_period ? o.colour_period : P.bw;
+        smooth_colour(P, u, b, nsweeps, S, w, w + kNoAllocMaxFine, static_cast<hipStream_t>(stream));
         IGA2L_HIP(hipGetLastError());
     });
 }
