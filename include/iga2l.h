@@ -61,6 +61,17 @@ typedef struct {
     int precision;       /* IGA2L_FP64, or IGA2L_MIXED_FP32: FP64 residual and accumulation,
                             FP32 smoother, defect, transfers and V-cycle */
     int fine_post_sweeps;/* Schwarz sweeps after the coarse correction (paper: 0) */
+    int lumped;          /* 1: restriction D^{-1} M_p^1 with the row-sum lumped degree-1 mass
+                            matrix D (Section 3.1.2, the paper's choice); 0: the exact
+                            L2 projection (M_1^1)^{-1} M_p^1 (M_1^1 applied through its DST-I).
+                            Applies to iga2l_solve*; iga2l_restrict / iga2l_prolong follow the
+                            value of the last iga2l_setup_blocks */
+    int aggressive;      /* 1: aggressive coarsening (Section 3.3): the coarse level is the
+                            degree-1 discretisation on the grid of size 2h, reached by the degree
+                            transfer followed by linear interpolation's transpose; coarse =
+                            COARSE_VCYCLE runs one V(nu1,nu2) cycle from the 2h level, COARSE_DIRECT
+                            solves the 2h level exactly (kappa = 1, m even).  Needs more than 512
+                            unknowns on the degree-1 level.  0: degree 1 on the same grid */
 } iga2l_opts;
 
 typedef struct {
@@ -69,12 +80,14 @@ typedef struct {
     double r0;                 /* ||b - A u0||_2 */
     double relres;             /* final ||b - A u||_2 / r0 */
     double t_solve_ms;         /* wall time of the call (host clock, after the final sync) */
+    double t_setup_ms;         /* wall time of iga2l_assemble and every iga2l_setup_blocks of the problem */
     double *relres_history;    /* optional host array, filled with relres after each cycle */
     int history_cap;           /* its length (0 if none) */
 } iga2l_info;
 
 /* Fill o with the defaults: tol 1e-10, 100 cycles, COLOUR with s = block
- * width, V(1,1) coarse cycle, FP64, no post-smoothing. */
+ * width, V(1,1) coarse cycle, FP64, no post-smoothing, lumped transfers,
+ * degree-1 coarse level on the same grid. */
 void iga2l_default_opts(iga2l_opts *o);
 
 /*
@@ -142,14 +155,18 @@ int iga2l_smooth_noalloc(const iga2l_problem *prob, double *u, const double *b, 
                          const iga2l_opts *opts, void *stream);
 
 /* d_coarse = D^{-1} M_p^{1} r_fine: the restriction of Section 3.1.2 with the
- * row-sum lumped degree-1 mass matrix D.  FP64, n_fine -> n_coarse. */
+ * row-sum lumped degree-1 mass matrix D (with lumped = 0 at the last set-up:
+ * (M_1^1)^{-1} M_p^1 r_fine).  FP64, n_fine -> n_coarse. */
 int iga2l_restrict(const iga2l_problem *prob, const double *r_fine, double *d_coarse, void *stream);
 
 /* u_fine += (M_p^{1})^T D^{-1} e_coarse: the prolongation, adjoint of the restriction. */
 int iga2l_prolong(const iga2l_problem *prob, const double *e_coarse, double *u_fine, void *stream);
 
 /* e_coarse = approximation of A_1^{-1} d_coarse by opts->coarse (exact for
- * COARSE_DIRECT; one V(nu1,nu2) cycle from zero for COARSE_VCYCLE), FP64. */
+ * COARSE_DIRECT; one V(nu1,nu2) cycle from zero for COARSE_VCYCLE), FP64.
+ * With opts->aggressive: e_coarse = P_0 C P_0^T d_coarse, P_0 the linear
+ * interpolation from the 2h grid, C the exact 2h solve or the V-cycle from
+ * the 2h level (Section 3.3). */
 int iga2l_coarse_solve(const iga2l_problem *prob, const double *d_coarse, double *e_coarse,
                        const iga2l_opts *opts, void *stream);
 

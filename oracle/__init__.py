@@ -74,8 +74,10 @@ def lib():
             "or_prolong_add": (None, [vp, dp, dp]),
             "or_coarse_direct": (i, [vp, dp, dp]),
             "or_coarse_vcycle": (i, [vp, dp, dp, i, i]),
-            "or_cycle": (i, [vp, dp, dp, i, i, i, i, i, i, i]),
-            "or_solve": (i, [vp, dp, dp, i, i, i, i, i, i, i, d, i, dp]),
+            "or_cycle": (i, [vp, dp, dp, i, i, i, i, i, i, i, i]),
+            "or_solve": (i, [vp, dp, dp, i, i, i, i, i, i, i, i, d, i, dp]),
+            "or_setup_aggressive_direct": (i, [vp]),
+            "or_coarse_aggressive": (i, [vp, dp, dp, i, i, i]),
             "or_direct_solve": (i, [vp, dp, dp]),
             "or_grad_kappa": (i, [vp, dp, dp, dp]),
             "or_element_apply": (i, [vp, l, dp, dp]),
@@ -300,22 +302,39 @@ class Problem:
             raise ValueError(_err())
         return ec
 
-    def cycle(self, u, b, ordering=COLOUR, s=0, nu1=1, nu2=0, coarse=DIRECT, cnu1=1, cnu2=1):
+    def _aggressive_ready(self, coarse, aggressive):
+        if aggressive and coarse == DIRECT and not getattr(self, "_agg_direct", False):
+            if lib().or_setup_aggressive_direct(self._h):
+                raise ValueError(_err())
+            self._agg_direct = True
+
+    def coarse_aggressive(self, dc, coarse=DIRECT, nu1=1, nu2=1):
+        """Coarse correction of aggressive coarsening (degree 1 on 2h, Section 3.3)."""
+        self._aggressive_ready(coarse, True)
+        dc = np.ascontiguousarray(dc, dtype=np.float64)
+        ec = np.zeros(self.nc)
+        if lib().or_coarse_aggressive(self._h, _p(dc), _p(ec), coarse, nu1, nu2):
+            raise ValueError(_err())
+        return ec
+
+    def cycle(self, u, b, ordering=COLOUR, s=0, nu1=1, nu2=0, coarse=DIRECT, cnu1=1, cnu2=1, aggressive=False):
+        self._aggressive_ready(coarse, aggressive)
         u = np.array(u, dtype=np.float64, copy=True)
         b = np.ascontiguousarray(b, dtype=np.float64)
         if lib().or_cycle(self._h, _p(u), _p(b), ordering, s or self.block_width, nu1, nu2,
-                          coarse, cnu1, cnu2):
+                          coarse, cnu1, cnu2, 1 if aggressive else 0):
             raise ValueError(_err())
         return u
 
     def solve(self, b, u0=None, ordering=COLOUR, s=0, nu1=1, nu2=0, coarse=DIRECT, cnu1=1, cnu2=1,
-              tol=1e-10, max_cycles=100):
+              tol=1e-10, max_cycles=100, aggressive=False):
         """Iterate cycles to ||r|| <= tol ||r0||; returns (u, cycles, residual history)."""
+        self._aggressive_ready(coarse, aggressive)
         b = np.ascontiguousarray(b, dtype=np.float64)
         u = np.zeros(self.n) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
         hist = np.zeros(max_cycles + 1)
         k = lib().or_solve(self._h, _p(b), _p(u), ordering, s or self.block_width, nu1, nu2,
-                           coarse, cnu1, cnu2, tol, max_cycles, _p(hist))
+                           coarse, cnu1, cnu2, 1 if aggressive else 0, tol, max_cycles, _p(hist))
         if k < 0:
             raise ValueError(_err())
         return u, k, hist[:k + 1].copy()

@@ -538,6 +538,7 @@ typedef struct {
     double *chol;
     band_chol *coarse_chol;     /* Alow */
     band_chol *mass_chol;       /* Mlow (exact, non-lumped variant) */
+    band_chol *agg_chol;        /* degree-1 operator on the 2h grid (aggressive coarsening, exact) */
     int nlev;
     or_level *lev;        /* V-cycle hierarchy for plow = 1 */
 } or_problem;
@@ -546,7 +547,7 @@ void or_destroy(or_problem *P) {
     if (!P) return;
     free(P->kappa); free(P->A); free(P->Alow); free(P->Mlow); free(P->Mmix); free(P->Dlump);
     free(P->blk_off); free(P->blk_idx); free(P->chol_off); free(P->chol);
-    band_free(P->coarse_chol); band_free(P->mass_chol);
+    band_free(P->coarse_chol); band_free(P->mass_chol); band_free(P->agg_chol);
     for (int l = 0; l < P->nlev; l++) { free(P->lev[l].S); free(P->lev[l].Sfact); }
     free(P->lev);
     free(P);
@@ -1011,19 +1012,66 @@ int or_coarse_vcycle(const or_problem *P, const double *dc, double *ec, int nu1,
     return 0;
 }
 
+/*
+ * Aggressive coarsening (Section 3.3): the coarse level is the degree-plow
+ * discretisation on the grid of size 2h.  Its transfers are the composition
+ * of the degree transfer on h (I_p^{plow}, I_{plow}^p of Section 3.1.2) with
+ * the h <-> 2h transfers between degree-1 spaces (linear interpolation P_0 of
+ * the V-cycle hierarchy and its transpose, Section 3.2); the 2h operator is
+ * level 1 of that hierarchy (the Galerkin product P_0^T A_1 P_0, equal to the
+ * rediscretised degree-1 operator on 2h for kappa = 1).  Needs plow = 1 and a
+ * hierarchy of at least two levels.  The exact 2h solve is a banded
+ * Cholesky, factorised on first request.
+ */
+int or_setup_aggressive_direct(or_problem *P) {
+    if (!P->lev || P->nlev < 2) return fail("or_setup_aggressive_direct: needs a V-cycle hierarchy of >= 2 levels");
+    if (!P->agg_chol) {
+        P->agg_chol = band_factor_stencil(P->d, P->lev[1].n1, 1, P->lev[1].S);
+        if (!P->agg_chol) return fail("or_setup_aggressive_direct: factorisation failed");
+    }
+    return 0;
+}
+
+/* e_c = P_0 C P_0^T d_c, C = exact 2h solve (coarse 0) or one V(nu1,nu2)
+ * cycle from zero on levels 1, 2, ... (coarse 1) */
+static int coarse_aggressive(const or_problem *P, const double *dc, double *ec, int coarse, int nu1, int nu2) {
+    if (!P->lev || P->nlev < 2) return fail("aggressive coarsening needs a V-cycle hierarchy of >= 2 levels");
+    if (coarse == 0 && !P->agg_chol) return fail("aggressive coarsening: exact 2h solve not set up");
+    const or_level *F = &P->lev[0], *C = &P->lev[1];
+    double *rc = malloc(sizeof(double) * C->n), *ecl = malloc(sizeof(double) * C->n);
+    interp_restrict(P, F, C, dc, rc);
+    if (coarse == 0) {
+        memcpy(ecl, rc, sizeof(double) * C->n);
+        band_solve(P->agg_chol, ecl);
+    } else {
+        vcycle_level(P, 1, rc, ecl, nu1, nu2);
+    }
+    memset(ec, 0, sizeof(double) * F->n);
+    interp_prolong_add(P, F, C, ecl, ec);
+    free(rc); free(ecl);
+    return 0;
+}
+
+int or_coarse_aggressive(const or_problem *P, const double *dc, double *ec, int coarse, int nu1, int nu2) {
+    return coarse_aggressive(P, dc, ec, coarse, nu1, nu2);
+}
+
 /* ------------------------------------------------------------------ */
 /* the two-level cycle (Algorithm 1, general form of Section 3.1)      */
 /* ------------------------------------------------------------------ */
 
-/* options: ordering/s as in or_sweep; coarse 0 = exact, 1 = V(cnu1,cnu2) */
+/* options: ordering/s as in or_sweep; coarse 0 = exact, 1 = V(cnu1,cnu2);
+ * aggressive = 1: the coarse level is degree 1 on 2h (Section 3.3) */
 int or_cycle(const or_problem *P, double *u, const double *b, int ordering, int s,
-             int nu1, int nu2, int coarse, int cnu1, int cnu2) {
+             int nu1, int nu2, int coarse, int cnu1, int cnu2, int aggressive) {
     long n = P->n, nc = P->nc;
     for (int k = 0; k < nu1; k++) if (or_sweep(P, u, b, ordering, s)) return -1;
     double *d = malloc(sizeof(double) * n), *dc = malloc(sizeof(double) * nc), *ec = malloc(sizeof(double) * nc);
     or_residual(P, u, b, d);
     or_restrict(P, d, dc);
-    int rc = coarse == 0 ? or_coarse_direct(P, dc, ec) : or_coarse_vcycle(P, dc, ec, cnu1, cnu2);
+    int rc;
+    if (aggressive) rc = coarse_aggressive(P, dc, ec, coarse, cnu1, cnu2);
+    else rc = coarse == 0 ? or_coarse_direct(P, dc, ec) : or_coarse_vcycle(P, dc, ec, cnu1, cnu2);
     if (rc == 0) or_prolong_add(P, ec, u);
     free(d); free(dc); free(ec);
     if (rc) return rc;
@@ -1043,7 +1091,7 @@ static double norm2(const double *x, long n) {
  * may be NULL) receives the residual norms.  Returns the cycle count, or -1.
  */
 int or_solve(const or_problem *P, const double *b, double *u, int ordering, int s, int nu1, int nu2,
-             int coarse, int cnu1, int cnu2, double tol, int max_cycles, double *hist) {
+             int coarse, int cnu1, int cnu2, int aggressive, double tol, int max_cycles, double *hist) {
     long n = P->n;
     double *r = malloc(sizeof(double) * n);
     or_residual(P, u, b, r);
@@ -1051,7 +1099,7 @@ int or_solve(const or_problem *P, const double *b, double *u, int ordering, int 
     if (hist) hist[0] = r0;
     int k = 0;
     while (k < max_cycles && rk > tol * r0) {
-        if (or_cycle(P, u, b, ordering, s, nu1, nu2, coarse, cnu1, cnu2)) { free(r); return -1; }
+        if (or_cycle(P, u, b, ordering, s, nu1, nu2, coarse, cnu1, cnu2, aggressive)) { free(r); return -1; }
         k++;
         or_residual(P, u, b, r);
         rk = norm2(r, n);

@@ -37,12 +37,13 @@ class IGA2LError(RuntimeError):
 class CIgaOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_cycles", ctypes.c_int), ("ordering", ctypes.c_int),
                 ("colour_period", ctypes.c_int), ("coarse", ctypes.c_int), ("nu1", ctypes.c_int),
-                ("nu2", ctypes.c_int), ("precision", ctypes.c_int), ("fine_post_sweeps", ctypes.c_int)]
+                ("nu2", ctypes.c_int), ("precision", ctypes.c_int), ("fine_post_sweeps", ctypes.c_int),
+                ("lumped", ctypes.c_int), ("aggressive", ctypes.c_int)]
 
 
 class CIgaInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("r0", ctypes.c_double),
-                ("relres", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("relres", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
                 ("relres_history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int)]
 
 
@@ -58,10 +59,12 @@ class Opts:
     nu2: int = 1
     precision: int = FP64
     fine_post_sweeps: int = 0
+    lumped: int = 1
+    aggressive: int = 0
 
     def c(self) -> CIgaOpts:
         return CIgaOpts(self.tol, self.max_cycles, self.ordering, self.colour_period, self.coarse,
-                        self.nu1, self.nu2, self.precision, self.fine_post_sweeps)
+                        self.nu1, self.nu2, self.precision, self.fine_post_sweeps, self.lumped, self.aggressive)
 
 
 @dataclasses.dataclass
@@ -72,6 +75,7 @@ class Info:
     relres: float
     t_solve_ms: float
     history: np.ndarray
+    t_setup_ms: float = 0.0
 
 
 _lib = None
@@ -248,7 +252,8 @@ class Problem:
         co = o.c()
         code = lib().iga2l_solve(self._h, _dev_ptr(b, self.n, "b"), _dev_ptr(u, self.n, "u"), ctypes.byref(co),
                                  ctypes.byref(info), _stream(stream))
-        res = Info(info.iters, info.status, info.r0, info.relres, info.t_solve_ms, hist[:info.iters].copy())
+        res = Info(info.iters, info.status, info.r0, info.relres, info.t_solve_ms, hist[:info.iters].copy(),
+                   info.t_setup_ms)
         if code != OK and not (code == ENOTCONV and not raise_on_notconv):
             _check(code)
         return u, res
@@ -285,7 +290,8 @@ def solve_batch(problems: Sequence[Problem], bs, us, opts: Optional[Opts] = None
     code = lib().iga2l_solve_batch(hs, n, bp, up, ctypes.byref(co), infos, _stream(stream))
     if code != OK and not (code == ENOTCONV and not raise_on_notconv):
         _check(code)
-    return [Info(i.iters, i.status, i.r0, i.relres, i.t_solve_ms, h[:i.iters].copy()) for i, h in zip(infos, hists)]
+    return [Info(i.iters, i.status, i.r0, i.relres, i.t_solve_ms, h[:i.iters].copy(), i.t_setup_ms)
+            for i, h in zip(infos, hists)]
 
 
 def header_functions() -> list:

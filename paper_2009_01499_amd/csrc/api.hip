@@ -84,7 +84,20 @@ void check_opts(const Problem &P, const iga2l_opts &o) {
     }
     IGA2L_REQUIRE(!(o.ordering == IGA2L_LEX && o.precision != IGA2L_FP64), IGA2L_EUNSUPPORTED,
                   "the lexicographic ordering runs in FP64 only");
+    IGA2L_REQUIRE(o.lumped == 0 || o.lumped == 1, IGA2L_EINVAL, "lumped must be 0 or 1");
+    IGA2L_REQUIRE(o.aggressive == 0 || o.aggressive == 1, IGA2L_EINVAL, "aggressive must be 0 or 1");
 }
+
+// Applies the exact (not lumped) transfers while a call runs.
+struct TransferGuard {
+    Problem &P;
+    bool old;
+    TransferGuard(Problem &p, bool exact) : P(p), old(p.transfer_exact) {
+        IGA2L_REQUIRE(!exact || P.mass_ready, IGA2L_EINVAL, "exact transfers not set up (setup_blocks with lumped = 0)");
+        P.transfer_exact = exact;
+    }
+    ~TransferGuard() { P.transfer_exact = old; }
+};
 
 void set_device(const Problem &P) { IGA2L_HIP(hipSetDevice(P.device)); }
 
@@ -113,6 +126,10 @@ int sweep_colour(const Problem &P, int s_period, T *rhs, int start, bool e_zero,
 
 template <class T>
 void coarse_solve(Problem &P, const iga2l_opts &o, const T *dc, T *ec, hipStream_t s) {
+    if (o.aggressive) {
+        launch_coarse_aggressive<T>(P, dc, ec, o.coarse == IGA2L_COARSE_DIRECT, o.nu1, o.nu2, s);
+        return;
+    }
     if (o.coarse == IGA2L_COARSE_VCYCLE) {
         launch_vcycle<T>(P, dc, ec, o.nu1, o.nu2, s);
         return;
@@ -158,7 +175,9 @@ void correction_cycle(Problem &P, const iga2l_opts &o, double *u, hipStream_t s)
     T *e = P.ework[cur].as<T>();
     launch_defect<T>(P, e, rhs, P.dfine.as<T>(), s);
     launch_restrict<T>(P, P.dfine.as<T>(), P.dc.as<T>(), s);
+    if (P.transfer_exact) launch_mass_solve<T>(P, P.dc.as<T>(), s);
     coarse_solve<T>(P, o, P.dc.as<T>(), P.ec.as<T>(), s);
+    if (P.transfer_exact) launch_mass_solve<T>(P, P.ec.as<T>(), s);
     const bool scaled = !std::is_same<T, double>::value;
     if (o.fine_post_sweeps == 0) {
         launch_prolong_update<T>(P, P.ec.as<T>(), e, u, scaled, s);
@@ -217,7 +236,12 @@ void solve_impl(Problem &P, const double *b, double *u, const iga2l_opts &o, iga
     const bool fp32 = o.precision == IGA2L_MIXED_FP32;
     IGA2L_REQUIRE(!fp32 || P.fp32_ready, IGA2L_EINVAL, "FP32 data not set up (setup_blocks with MIXED_FP32)");
     IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_VCYCLE || P.vcycle_ready, IGA2L_EINVAL, "V-cycle not set up");
-    IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_DIRECT || P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");
+    if (o.aggressive)
+        IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_DIRECT || P.agg_direct_ready, IGA2L_EINVAL,
+                      "exact 2h solve not set up (setup_blocks with aggressive = 1)");
+    else
+        IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_DIRECT || P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");
+    TransferGuard tg(P, !o.lumped);
     ensure_history(P, std::max(o.max_cycles, 1));
     auto t0 = std::chrono::steady_clock::now();
     launch_residual64(P, u, b, P.r64.as<double>(), true, fp32, false, s);
@@ -256,6 +280,7 @@ void solve_impl(Problem &P, const double *b, double *u, const iga2l_opts &o, iga
         info->r0 = r0;
         info->relres = rel;
         info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        info->t_setup_ms = P.t_setup_ms;
         if (info->relres_history)
             for (int i = 0; i < std::min(k, info->history_cap); ++i)
                 info->relres_history[i] = hs[kScalCount + kFlagCount / 2 + i];
@@ -346,6 +371,8 @@ void iga2l_default_opts(iga2l_opts *o) {
     o->nu2 = 1;
     o->precision = IGA2L_FP64;
     o->fine_post_sweeps = 0;
+    o->lumped = 1;
+    o->aggressive = 0;
 }
 
 const char *iga2l_last_error(void) { return g_last_error.c_str(); }
@@ -368,6 +395,7 @@ int iga2l_assemble(int dim, const double *const *knots, const int *nknots, int p
                           "knots must be the open uniform vector (p+1 zeros, i/m, p+1 ones) with m >= 2");
             m = mk;
         }
+        const auto t_start = std::chrono::steady_clock::now();
         auto *h = new iga2l_problem();
         try {
             Problem &P = h->P;
@@ -386,6 +414,8 @@ int iga2l_assemble(int dim, const double *const *knots, const int *nknots, int p
             set_device(P);
             host_assemble(P);
             P.layout_id = next_layout_id();
+            IGA2L_HIP(hipDeviceSynchronize());
+            P.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         } catch (...) {
             delete h;
             throw;
@@ -405,7 +435,8 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
         IGA2L_REQUIRE(bw >= 1 && bw <= 7 && (bw & 1), IGA2L_EINVAL, "block width must be odd, 1..7");
         IGA2L_REQUIRE(P.dim == 2 || bw <= 3, IGA2L_EUNSUPPORTED, "3-D block width must be 1 or 3");
         hipStream_t s = nullptr;
-        auto tprev = std::chrono::steady_clock::now();
+        const auto t_start = std::chrono::steady_clock::now();
+        auto tprev = t_start;
         auto stage = [&](const char *what) {   // IGA2L_TUNE_LOG=1: set-up stage times
             if (!tune_log()) return;
             IGA2L_HIP(hipDeviceSynchronize());
@@ -447,15 +478,25 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             P.fp32_ready = true;
             stage("FP32 copies");
         }
-        if (o.coarse == IGA2L_COARSE_VCYCLE && !P.vcycle_ready) {
+        if ((o.coarse == IGA2L_COARSE_VCYCLE || o.aggressive) && !P.vcycle_ready) {
             host_build_levels(P);
             stage("V-cycle levels");
         }
-        if (o.coarse == IGA2L_COARSE_DIRECT && !P.direct_ready) {
+        if (o.aggressive) {
+            IGA2L_REQUIRE(P.levels.size() >= 2, IGA2L_EUNSUPPORTED,
+                          "aggressive coarsening needs a V-cycle hierarchy with a 2h level (more than 512 coarse "
+                          "unknowns)");
+            if (o.coarse == IGA2L_COARSE_DIRECT && !P.agg_direct_ready) host_build_agg_direct(P);
+        } else if (o.coarse == IGA2L_COARSE_DIRECT && !P.direct_ready) {
             IGA2L_REQUIRE(P.kappa_one, IGA2L_EUNSUPPORTED,
                           "the exact coarse solve needs kappa = 1; use the V-cycle for variable kappa");
             host_build_dst(P);
         }
+        if (!o.lumped && !P.mass_ready) {
+            host_build_mass(P);
+            stage("exact transfers");
+        }
+        P.lumped_default = o.lumped != 0;
         IGA2L_HIP(hipDeviceSynchronize());
         // tile shapes of the coloured sweep, timed once per working precision
         const int S = o.colour_period ? o.colour_period : P.bw;
@@ -469,6 +510,8 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
         }
         stage("tile autotuning");
         P.layout_id = next_layout_id();
+        IGA2L_HIP(hipDeviceSynchronize());
+        P.t_setup_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     });
 }
 
@@ -544,8 +587,12 @@ int iga2l_smooth_noalloc(const iga2l_problem *prob, double *u, const double *b, 
 int iga2l_restrict(const iga2l_problem *prob, const double *r_fine, double *d_coarse, void *stream) {
     return guarded([&] {
         IGA2L_REQUIRE(prob && r_fine && d_coarse, IGA2L_EINVAL, "null argument");
-        set_device(prob->P);
-        launch_restrict<double>(prob->P, r_fine, d_coarse, static_cast<hipStream_t>(stream));
+        Problem &P = const_cast<Problem &>(prob->P);
+        set_device(P);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        TransferGuard tg(P, !P.lumped_default);
+        launch_restrict<double>(P, r_fine, d_coarse, s);
+        if (P.transfer_exact) launch_mass_solve<double>(P, d_coarse, s);
         IGA2L_HIP(hipGetLastError());
     });
 }
@@ -553,8 +600,17 @@ int iga2l_restrict(const iga2l_problem *prob, const double *r_fine, double *d_co
 int iga2l_prolong(const iga2l_problem *prob, const double *e_coarse, double *u_fine, void *stream) {
     return guarded([&] {
         IGA2L_REQUIRE(prob && e_coarse && u_fine, IGA2L_EINVAL, "null argument");
-        set_device(prob->P);
-        launch_prolong_add<double>(prob->P, e_coarse, u_fine, static_cast<hipStream_t>(stream));
+        Problem &P = const_cast<Problem &>(prob->P);
+        set_device(P);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        TransferGuard tg(P, !P.lumped_default);
+        const double *ec = e_coarse;
+        if (P.transfer_exact) {
+            IGA2L_HIP(hipMemcpyAsync(P.ec.ptr, e_coarse, sizeof(double) * size_t(P.coarse.n), hipMemcpyDeviceToDevice, s));
+            launch_mass_solve<double>(P, P.ec.as<double>(), s);
+            ec = P.ec.as<double>();
+        }
+        launch_prolong_add<double>(P, ec, u_fine, s);
         IGA2L_HIP(hipGetLastError());
     });
 }

@@ -370,6 +370,7 @@ void batch_residual(const Plan &pl, bool fp32, bool book, hipStream_t s) {
 bool batch_supported(Problem *const *probs, int nprob, const iga2l_opts &o) {
     if (nprob < 2) return false;
     if (o.ordering != IGA2L_COLOUR || o.coarse != IGA2L_COARSE_VCYCLE || o.fine_post_sweeps != 0) return false;
+    if (!o.lumped || o.aggressive) return false;   // exact transfers / 2h coarse level: problem by problem
     if (o.nu1 < 0 || o.nu1 > 4 || o.nu2 < 1 || o.nu2 > 4) return false;
     for (int k = 0; k < nprob; ++k) {
         const Problem &P = *probs[k];
@@ -458,6 +459,7 @@ void solve_batch_fused(Problem *const *probs, int nprob, const double *const *b,
             inf.r0 = r0;
             inf.relres = rel;
             inf.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            inf.t_setup_ms = pv[k]->t_setup_ms;
             if (inf.relres_history)
                 for (int i = 0; i < std::min(it, std::min(inf.history_cap, pl.hist_cap)); ++i)
                     inf.relres_history[i] = hs[fixed + i];

@@ -121,6 +121,7 @@ struct Problem {
     // host copies of the 1-D factors (per direction identical)
     std::vector<double> K1, M1;   // [n1][2p+1], interior rows, offset j-i+p
     std::vector<double> R1;       // [n1c][p+2], coarse row I, fine column I-1+a
+    std::vector<double> Mx1;      // the same without the lumped scaling: Mmix1
     std::vector<std::vector<double>> Ke, Me;  // element matrices [m][(p+1)^2]
 
     SymDia A;                     // fine stiffness
@@ -152,6 +153,19 @@ struct Problem {
     bool vcycle_ready = false;
     DevBuf dst_S, dst_mu;         // DST-I matrix [n1c][n1c], eigenvalues [n_c]
     bool direct_ready = false;
+    // exact (not lumped) transfers: the degree-1 mass matrix M_1 is diagonalised
+    // by the same DST-I; dstM_mu holds its eigenvalues (products of the 1-D
+    // ones), Mx64/Mx32 the unlumped 1-D factor Mmix1 [n1c][p+2]
+    DevBuf dstM_S, dstM_mu, Mx64, Mx32, ctmp2;
+    bool mass_ready = false;
+    // aggressive coarsening (degree 1 on 2h): exact 2h solve by the DST-I of
+    // level 1 of the V-cycle hierarchy (kappa = 1, m even)
+    DevBuf dst2_S, dst2_mu, agg64, agg32;
+    bool agg_direct_ready = false;
+    // while a call runs: apply the exact transfers (else the lumped ones)
+    bool transfer_exact = false;
+    bool lumped_default = true;   // transfers of iga2l_restrict / iga2l_prolong (last set-up)
+    double t_setup_ms = 0.0;      // host wall time of assembly and set-up so far
 
     // workspaces
     DevBuf r64;                   // fine residual FP64
@@ -330,6 +344,8 @@ void solve_batch_fused(Problem *const *probs, int nprob, const double *const *b,
 void host_assemble(Problem &P);                 // 1-D factors, DIA, transfers, kappa
 void host_build_levels(Problem &P);             // V-cycle hierarchy (Galerkin)
 void host_build_dst(Problem &P);                // exact coarse solver (kappa = 1)
+void host_build_mass(Problem &P);               // exact M_1^{-1} transfers (DST-I of the mass matrix)
+void host_build_agg_direct(Problem &P);         // exact 2h solve of aggressive coarsening
 void host_block_classes(Problem &P, std::vector<int> &cls1, std::vector<int64_t> &reps);
 void host_lex_schedule(Problem &P);
 
@@ -382,6 +398,13 @@ void launch_prolong_update(const Problem &P, const T *ec, const T *e, double *u,
 template <class T>
 void launch_vcycle(Problem &P, const T *rhs, T *e, int nu1, int nu2, hipStream_t s);
 void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s);
+void dst_apply_2h(Problem &P, const double *d, double *e, double *t1, hipStream_t s);
+// x <- M_1^{-1} x in place on the coarse grid (exact transfers), FP64 or FP32
+template <class T>
+void launch_mass_solve(Problem &P, T *x, hipStream_t s);
+// aggressive coarsening: e = P_0 C P_0^T d, C = exact 2h solve or a V-cycle on levels 1..
+template <class T>
+void launch_coarse_aggressive(Problem &P, const T *d, T *e, bool exact, int nu1, int nu2, hipStream_t s);
 int64_t vcycle_bottom_lds(const Problem &P, size_t lb);   // LDS elements of the one-workgroup tail
 bool vcycle_bottom_fits(const Problem &P, size_t lb);
 void launch_convert(const void *src, void *dst, int64_t n, bool to_fp32, hipStream_t s, const int *skip = nullptr);

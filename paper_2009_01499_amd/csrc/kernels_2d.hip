@@ -313,8 +313,13 @@ __global__ void __launch_bounds__(256) kb_prolong_update2d(const BatchProb *__re
                       q.flags, q.pr_tx, q.pr_ty, bx, by, reinterpret_cast<T *>(smem_raw));
 }
 
+// the 1-D transfer factor: D1^{-1} Mmix1 (lumped), or Mmix1 when the exact
+// transfers apply M_1^{-1} separately
 template <class T>
 const T *R1_of(const Problem &P) {
+    if (P.transfer_exact)
+        return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.Mx64.ptr)
+                                              : reinterpret_cast<const T *>(P.Mx32.ptr);
     return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.R1d64.ptr)
                                           : reinterpret_cast<const T *>(P.R1d32.ptr);
 }

@@ -316,8 +316,13 @@ __global__ void k_galerkin(const double *__restrict__ Sf, int nf1, double *__res
     Sc[int64_t(W) * nc + I] = acc;
 }
 
+// the 1-D transfer factor: D1^{-1} Mmix1 (lumped), or Mmix1 when the exact
+// transfers apply M_1^{-1} separately
 template <class T>
 const T *R1_of(const Problem &P) {
+    if (P.transfer_exact)
+        return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.Mx64.ptr)
+                                              : reinterpret_cast<const T *>(P.Mx32.ptr);
     return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.R1d64.ptr)
                                           : reinterpret_cast<const T *>(P.R1d32.ptr);
 }
@@ -366,30 +371,63 @@ template void launch_prolong_update<double>(const Problem &, const double *, con
 template void launch_prolong_update<float>(const Problem &, const float *, const float *, double *, bool,
                                            hipStream_t);
 
-void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s) {
-    IGA2L_REQUIRE(P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");
-    const int n1 = P.coarse.n1, dim = P.dim;
-    const int64_t n = P.coarse.n;
-    double *t1 = P.ctmp.as<double>();
-    const double *S = P.dst_S.as<double>(), *mu = P.dst_mu.as<double>();
-    // forward transform along every axis, diagonal solve, inverse (= forward) transform
+// e = (S (x) .. (x) S) diag(mu)^{-1} (S (x) .. (x) S) d on a grid of n1^dim
+// points (S symmetric orthogonal): forward transform along every axis,
+// diagonal solve, inverse (= forward) transform.  t1: scratch of n doubles;
+// d may equal t1 only if it is not e.
+static void dst_apply(const double *S, const double *mu, int n1, int dim, const double *d, double *e, double *t1,
+                      const int *skip, hipStream_t s) {
+    const int64_t n = (dim == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
     const double *src = d;
     double *bufs[2] = {t1, e};
     int cur = 0;
     for (int ax = 0; ax < dim; ++ax) {
         hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, S, n1, dim, ax, src, bufs[cur],
-                           (ax == dim - 1) ? mu : nullptr, P.skip);
+                           (ax == dim - 1) ? mu : nullptr, skip);
         src = bufs[cur];
         cur = 1 - cur;
     }
     for (int ax = 0; ax < dim; ++ax) {
         hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, S, n1, dim, ax, src, bufs[cur],
-                           nullptr, P.skip);
+                           nullptr, skip);
         src = bufs[cur];
         cur = 1 - cur;
     }
     // 2*dim passes alternate t1, e, t1, e, ...: an even count, so the last one wrote e
 }
+
+// exact solve of level 1 (2h) of the hierarchy for aggressive coarsening
+void dst_apply_2h(Problem &P, const double *d, double *e, double *t1, hipStream_t s) {
+    dst_apply(P.dst2_S.as<double>(), P.dst2_mu.as<double>(), P.levels[1].g.n1, P.dim, d, e, t1, P.skip, s);
+}
+
+void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s) {
+    IGA2L_REQUIRE(P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");
+    dst_apply(P.dst_S.as<double>(), P.dst_mu.as<double>(), P.coarse.n1, P.dim, d, e, P.ctmp.as<double>(), P.skip, s);
+}
+
+// x <- M_1^{-1} x (the degree-1 mass matrix, Dirichlet-reduced): FP64 through
+// the DST-I; an FP32 x is widened, solved and narrowed
+template <class T>
+void launch_mass_solve(Problem &P, T *x, hipStream_t s) {
+    IGA2L_REQUIRE(P.mass_ready, IGA2L_EINVAL, "exact transfers not set up (setup_blocks with lumped = 0)");
+    const int64_t n = P.coarse.n;
+    double *t1 = P.ctmp2.as<double>();
+    if constexpr (std::is_same<T, double>::value) {
+        // x -> e through t1: the input must not be the output buffer
+        IGA2L_HIP(hipMemcpyAsync(P.ctmp.ptr, x, sizeof(double) * size_t(n), hipMemcpyDeviceToDevice, s));
+        dst_apply(P.dstM_S.as<double>(), P.dstM_mu.as<double>(), P.coarse.n1, P.dim, P.ctmp.as<double>(), x, t1,
+                  P.skip, s);
+    } else {
+        IGA2L_REQUIRE(P.dc64.ptr, IGA2L_EINVAL, "FP32 data not set up");
+        launch_convert(x, P.ctmp.ptr, n, false, s, P.skip);
+        dst_apply(P.dstM_S.as<double>(), P.dstM_mu.as<double>(), P.coarse.n1, P.dim, P.ctmp.as<double>(),
+                  P.dc64.as<double>(), t1, P.skip, s);
+        launch_convert(P.dc64.ptr, x, n, true, s, P.skip);
+    }
+}
+template void launch_mass_solve<double>(Problem &, double *, hipStream_t);
+template void launch_mass_solve<float>(Problem &, float *, hipStream_t);
 
 void launch_convert(const void *src, void *dst, int64_t n, bool to_fp32, hipStream_t s, const int *skip) {
     if (to_fp32)

@@ -423,7 +423,10 @@ struct ZPre {
 template <int D, class T>
 __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, const T *__restrict__ rhs_top,
                                                    T *__restrict__ e_top, int nu1, int nu2,
-                                                   const int *__restrict__ skip, unsigned char *smem_raw) {
+                                                   const int *__restrict__ skip, unsigned char *smem_raw,
+                                                   int nu1_top, int nu2_top) {
+    // nu1_top / nu2_top: smoothing steps on the first level handled here
+    // (0 for the 2h-coarse correction of aggressive coarsening), nu1 / nu2 below
     if (skip && *skip) return;
     T *sm = reinterpret_cast<T *>(smem_raw);
     // LDS: for each level two correction buffers (a half step reads one and
@@ -565,7 +568,7 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
     };
 
     for (int l = 0; l < last; ++l) {
-        for (int k = 0; k < nu1; ++k) {
+        for (int k = 0; k < (l == 0 ? nu1_top : nu1); ++k) {
             half(l, 0);
             half(l, 1);
         }
@@ -662,7 +665,7 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
             e[((D == 3) ? ((z + 1) * (n1 + 2) + y + 1) : (y + 1)) * (n1 + 2) + x + 1] += acc;
         }
         __syncthreads();
-        for (int k = 0; k < nu2; ++k) {
+        for (int k = 0; k < (l == 0 ? nu2_top : nu2); ++k) {
             half(l, 0);
             half(l, 1);
         }
@@ -680,9 +683,10 @@ __device__ __forceinline__ void vcycle_bottom_body(const BottomArgs<D, T> &A, co
 template <int D, class T>
 __global__ void __launch_bounds__(kBottomThreads) k_vcycle_bottom(BottomArgs<D, T> A, const T *__restrict__ rhs_top,
                                                                   T *__restrict__ e_top, int nu1, int nu2,
-                                                                  const int *__restrict__ skip) {
+                                                                  const int *__restrict__ skip, int nu1_top,
+                                                                  int nu2_top) {
     extern __shared__ unsigned char smem_raw[];
-    vcycle_bottom_body<D, T>(A, rhs_top, e_top, nu1, nu2, skip, smem_raw);
+    vcycle_bottom_body<D, T>(A, rhs_top, e_top, nu1, nu2, skip, smem_raw, nu1_top, nu2_top);
 }
 
 // batched: one workgroup per problem of the table
@@ -692,7 +696,7 @@ __global__ void __launch_bounds__(kBottomThreads) kb_vcycle_bottom(const BatchBo
     extern __shared__ unsigned char smem_raw[];
     const BatchBottom<T> &q = bb[blockIdx.x];
     const BottomArgs<2, T> a{q.nlev, q.levels};
-    vcycle_bottom_body<2, T>(a, q.rhs, q.e, nu1, nu2, q.skip, smem_raw);
+    vcycle_bottom_body<2, T>(a, q.rhs, q.e, nu1, nu2, q.skip, smem_raw, nu1, nu2);
 }
 
 template <class T>
@@ -713,7 +717,8 @@ LevelDev<T> levhost(const Problem &P, size_t l) {
 }
 
 template <int D, class T>
-void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, hipStream_t s);
+void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, hipStream_t s, int nu1_here = -1,
+                int nu2_here = -1);
 
 template <class T, int NU, bool RESTRICT>
 void launch_rb_multi2(const Problem &P, const LevelDev<T> &Ld, const T *e_src, bool zero_src, const T *ec,
@@ -757,16 +762,20 @@ void vcycle_top_fused2(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, in
     rb_multi2<T, false>(P, nu2, Ld, epre, nu1 == 0, ecl, n1c, rhs, e_out, static_cast<T *>(nullptr), 0, s);
 }
 
-// V-cycle from zero on level l of the multi-workgroup part; result in e_out
+// V-cycle from zero on level l of the multi-workgroup part; result in e_out.
+// nu1_here / nu2_here (if >= 0): smoothing steps on level l itself, nu1 / nu2
+// on the coarser levels
 template <int D, class T>
-void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, hipStream_t s) {
+void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, hipStream_t s, int nu1_here,
+                int nu2_here) {
+    const int n1h = nu1_here >= 0 ? nu1_here : nu1, n2h = nu2_here >= 0 ? nu2_here : nu2;
     const size_t lb = bottom_level<T>(P);
     if (l == lb) {
         const size_t nlev = P.levels.size() - lb;
         BottomArgs<D, T> a{int(nlev), levdev<T>(P) + lb};
         const size_t shm = size_t(vcycle_bottom_lds(P, lb)) * sizeof(T);
         hipLaunchKernelGGL((k_vcycle_bottom<D, T>), dim3(1), dim3(kBottomThreads), shm, s, a, rhs, e_out, nu1, nu2,
-                           P.skip);
+                           P.skip, n1h, n2h);
         return;
     }
     Level &L = P.levels[l];
@@ -774,7 +783,7 @@ void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, 
     const LevelDev<T> Ld = levhost<T>(P, l);
     const int n1 = L.g.n1, n1c = C.g.n1;
     if constexpr (D == 2) {
-        if (nu1 <= 4 && nu2 <= 4 && nu2 >= 1) {
+        if (n1h == nu1 && n2h == nu2 && nu1 <= 4 && nu2 <= 4 && nu2 >= 1) {
             vcycle_top_fused2<T>(P, l, rhs, e_out, nu1, nu2, s);
             return;
         }
@@ -785,7 +794,7 @@ void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, 
     T *buf[2] = {L.e[0].as<T>(), L.e[1].as<T>()};
     int cur = 0;
     bool zero = true;
-    for (int k = 0; k < nu1; ++k) {
+    for (int k = 0; k < n1h; ++k) {
         hipLaunchKernelGGL((k_rb_step<D, T>), sgrid, dim3(256), 0, s, Ld, buf[cur], zero ? 1 : 0,
                            static_cast<const T *>(nullptr), 0, rhs, buf[1 - cur], P.skip);
         cur = 1 - cur;
@@ -797,13 +806,13 @@ void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, 
                        P.skip);
     vcycle_top<D, T>(P, l + 1, rc, ecl, nu1, nu2, s);
     // post-smoothing; the first step loads e + P ec, the last one writes e_out
-    if (nu2 == 0) {
+    if (n2h == 0) {
         hipLaunchKernelGGL((k_interp_add2<D, T>), dim3(nblk(L.g.n, 256)), dim3(256), 0, s, buf[cur], zero ? 1 : 0,
                            static_cast<const T *>(ecl), n1c, n1, e_out, P.skip);
         return;
     }
-    for (int k = 0; k < nu2; ++k) {
-        T *dst = (k == nu2 - 1) ? e_out : buf[1 - cur];
+    for (int k = 0; k < n2h; ++k) {
+        T *dst = (k == n2h - 1) ? e_out : buf[1 - cur];
         hipLaunchKernelGGL((k_rb_step<D, T>), sgrid, dim3(256), 0, s, Ld, buf[cur], zero ? 1 : 0,
                            (k == 0) ? static_cast<const T *>(ecl) : static_cast<const T *>(nullptr), n1c, rhs, dst,
                            P.skip);
@@ -822,6 +831,50 @@ void launch_vcycle(Problem &P, const T *rhs, T *e, int nu1, int nu2, hipStream_t
 }
 template void launch_vcycle<double>(Problem &, const double *, double *, int, int, hipStream_t);
 template void launch_vcycle<float>(Problem &, const float *, float *, int, int, hipStream_t);
+
+// Aggressive coarsening (the coarse level is degree 1 on 2h): e = P_0 C P_0^T d
+// with P_0 the linear interpolation of the hierarchy from level 1 to level 0.
+// exact: C = the DST-I solve of level 1 (FP64); otherwise C = one V(nu1,nu2)
+// cycle from zero on levels 1, 2, ..., i.e. a V-cycle from level 0 without
+// smoothing on level 0.
+template <int D, class T>
+static void coarse_aggressive_dim(Problem &P, const T *d, T *e, bool exact, int nu1, int nu2, hipStream_t s) {
+    if (!exact) {
+        vcycle_top<D, T>(P, 0, d, e, nu1, nu2, s, 0, 0);
+        return;
+    }
+    IGA2L_REQUIRE(P.agg_direct_ready, IGA2L_EINVAL, "exact 2h solve not set up (setup_blocks with aggressive)");
+    Level &L = P.levels[0];
+    Level &C = P.levels[1];
+    const LevelDev<T> Ld = levhost<T>(P, 0);
+    const int n1 = L.g.n1, n1c = C.g.n1;
+    const int64_t n2 = C.g.n;
+    using TS = VT<D>;
+    const dim3 rgrid(nblk(n1c, TS::CX), nblk(n1c, TS::CY), D == 3 ? nblk(n1c, TS::CZ) : 1);
+    double *rc64 = P.agg64.as<double>(), *ec64 = rc64 + n2, *t1 = rc64 + 2 * n2;
+    T *rc = C.rhs.as<T>(), *ecl = C.res.as<T>();
+    hipLaunchKernelGGL((k_res_restrict_tiled<D, T>), rgrid, dim3(256), 0, s, Ld, static_cast<const T *>(nullptr), 1,
+                       d, n1c, rc, P.skip);
+    if constexpr (std::is_same<T, double>::value) {
+        dst_apply_2h(P, rc, ecl, t1, s);
+    } else {
+        launch_convert(rc, rc64, n2, false, s, P.skip);
+        dst_apply_2h(P, rc64, ec64, t1, s);
+        launch_convert(ec64, ecl, n2, true, s, P.skip);
+    }
+    hipLaunchKernelGGL((k_interp_add2<D, T>), dim3(nblk(L.g.n, 256)), dim3(256), 0, s, static_cast<const T *>(nullptr),
+                       1, static_cast<const T *>(ecl), n1c, n1, e, P.skip);
+}
+
+template <class T>
+void launch_coarse_aggressive(Problem &P, const T *d, T *e, bool exact, int nu1, int nu2, hipStream_t s) {
+    IGA2L_REQUIRE(P.vcycle_ready && P.levels.size() >= 2, IGA2L_EUNSUPPORTED,
+                  "aggressive coarsening needs a V-cycle hierarchy with a 2h level (more than 512 coarse unknowns)");
+    if (P.dim == 2) coarse_aggressive_dim<2, T>(P, d, e, exact, nu1, nu2, s);
+    else coarse_aggressive_dim<3, T>(P, d, e, exact, nu1, nu2, s);
+}
+template void launch_coarse_aggressive<double>(Problem &, const double *, double *, bool, int, int, hipStream_t);
+template void launch_coarse_aggressive<float>(Problem &, const float *, float *, bool, int, int, hipStream_t);
 
 // LDS (in elements) the bottom kernel needs for levels lb..coarsest
 int64_t vcycle_bottom_lds(const Problem &P, size_t lb) {

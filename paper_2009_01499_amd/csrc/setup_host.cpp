@@ -196,6 +196,7 @@ void host_assemble(Problem &P) {
                     }
                 }
             }
+        P.Mx1 = mix;
         P.R1.assign(mix.size(), 0.0);
         for (int I = 0; I < n1c; ++I)
             for (int a = 0; a < p + 2; ++a) P.R1[size_t(I) * (p + 2) + a] = mix[size_t(I) * (p + 2) + a] / lump[I];
@@ -547,8 +548,15 @@ void host_build_levels(Problem &P) {
 // For kappa = 1 the degree-1 operator on the uniform mesh is a sum of
 // Kronecker products of (1/h) tridiag(-1,2,-1) and (h/6) tridiag(1,4,1), all
 // diagonalised by the orthonormal DST-I matrix S_ik = sqrt(2/m) sin((i+1)(k+1)pi/m).
-void host_build_dst(Problem &P) {
-    const int m = P.m, n1 = m - 1, d = P.dim;
+// The degree-1 stiffness and mass matrices on a uniform grid of m cells with
+// homogeneous Dirichlet conditions, (1/h) tridiag(-1, 2, -1) and
+// (h/6) tridiag(1, 4, 1) per direction, are diagonalised by the orthonormal
+// DST-I matrix S_ik = sqrt(2/m) sin(ik pi/m) with eigenvalues
+// (2/h)(1 - cos t_k) and (h/3)(2 + cos t_k), t_k = k pi/m.  stiffness: mu =
+// eigenvalues of the d-dimensional stiffness sum_c prod_k (k == c ? K : M);
+// otherwise of the mass matrix prod_k M.
+static void dst_tables(int m, int d, bool stiffness, DevBuf &Sd, DevBuf &mud) {
+    const int n1 = m - 1;
     const double h = 1.0 / m;
     std::vector<double> S(size_t(n1) * n1), lk(n1), lm(n1);
     for (int i = 0; i < n1; ++i)
@@ -563,19 +571,56 @@ void host_build_dst(Problem &P) {
     int ix[kMaxDim] = {0, 0, 0};
     for (int64_t i = 0; i < n; ++i) {
         split(i, d, n1, ix);
-        double s = 0.0;
-        for (int c = 0; c < d; ++c) {
+        if (stiffness) {
+            double s = 0.0;
+            for (int c = 0; c < d; ++c) {
+                double prod = 1.0;
+                for (int k = 0; k < d; ++k) prod *= (k == c) ? lk[ix[k]] : lm[ix[k]];
+                s += prod;
+            }
+            mu[i] = s;
+        } else {
             double prod = 1.0;
-            for (int k = 0; k < d; ++k) prod *= (k == c) ? lk[ix[k]] : lm[ix[k]];
-            s += prod;
+            for (int k = 0; k < d; ++k) prod *= lm[ix[k]];
+            mu[i] = prod;
         }
-        mu[i] = s;
     }
-    P.dst_S.alloc(S.size() * sizeof(double));
-    P.dst_mu.alloc(mu.size() * sizeof(double));
-    IGA2L_HIP(hipMemcpy(P.dst_S.ptr, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
-    IGA2L_HIP(hipMemcpy(P.dst_mu.ptr, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice));
+    Sd.alloc(S.size() * sizeof(double));
+    mud.alloc(mu.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(Sd.ptr, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+    IGA2L_HIP(hipMemcpy(mud.ptr, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice));
+}
+
+void host_build_dst(Problem &P) {
+    dst_tables(P.m, P.dim, true, P.dst_S, P.dst_mu);
     P.direct_ready = true;
+}
+
+// exact transfers (Section 3.1.2 without lumping): the unlumped factor and
+// the DST-I of the degree-1 mass matrix
+void host_build_mass(Problem &P) {
+    dst_tables(P.m, P.dim, false, P.dstM_S, P.dstM_mu);
+    P.Mx64.alloc(P.Mx1.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.Mx64.ptr, P.Mx1.data(), P.Mx1.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<float> f32(P.Mx1.begin(), P.Mx1.end());
+    P.Mx32.alloc(f32.size() * sizeof(float));
+    IGA2L_HIP(hipMemcpy(P.Mx32.ptr, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice));
+    P.ctmp2.alloc(size_t(P.coarse.n) * sizeof(double));
+    P.mass_ready = true;
+}
+
+// aggressive coarsening, exact 2h solve: level 1 of the hierarchy is the
+// degree-1 operator on m/2 cells (Galerkin = rediscretisation for kappa = 1
+// with full coarsening of an even m), solved by its DST-I
+void host_build_agg_direct(Problem &P) {
+    IGA2L_REQUIRE(P.kappa_one, IGA2L_EUNSUPPORTED, "the exact 2h solve of aggressive coarsening needs kappa = 1");
+    IGA2L_REQUIRE(P.m % 2 == 0, IGA2L_EUNSUPPORTED, "the exact 2h solve of aggressive coarsening needs an even m");
+    IGA2L_REQUIRE(P.levels.size() >= 2 && P.levels[1].g.n1 == P.m / 2 - 1, IGA2L_EUNSUPPORTED,
+                  "aggressive coarsening needs a V-cycle hierarchy with a 2h level");
+    dst_tables(P.m / 2, P.dim, true, P.dst2_S, P.dst2_mu);
+    const size_t n2 = size_t(P.levels[1].g.n);
+    P.agg64.alloc(4 * n2 * sizeof(double));   // rhs, solution, transform buffer, FP64 staging
+    P.agg_direct_ready = true;
 }
 
 // ------------------------------------------------------- block classes --

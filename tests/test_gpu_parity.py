@@ -38,36 +38,46 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def _pair(d, p, m, kappa=None, bw=0, vcycle=True, direct=True, mixed=False):
+def _pair(d, p, m, kappa=None, bw=0, vcycle=True, direct=True, mixed=False, lumped=1, aggressive=0):
     G = _gpu()
-    print(f"\n[case] d={d} p={p} m={m} kappa={'grf' if kappa is not None else 1} bw={bw}", flush=True)
-    orc = O.Problem(d, p, m, kappa=kappa, block_width=bw, coarse_direct=direct, vcycle=vcycle)
+    print(f"\n[case] d={d} p={p} m={m} kappa={'grf' if kappa is not None else 1} bw={bw} lumped={lumped} "
+          f"aggressive={aggressive}", flush=True)
+    orc = O.Problem(d, p, m, kappa=kappa, block_width=bw, coarse_direct=direct and not aggressive,
+                    vcycle=vcycle or bool(aggressive), lumped=bool(lumped))
     gp = G.Problem(d, p, m, kappa=kappa)
+    extra = dict(precision=G.MIXED_FP32 if mixed else G.FP64, lumped=lumped, aggressive=aggressive)
     if vcycle:
-        gp.setup(bw, G.Opts(coarse=G.COARSE_VCYCLE, precision=G.MIXED_FP32 if mixed else G.FP64))
+        gp.setup(bw, G.Opts(coarse=G.COARSE_VCYCLE, **extra))
     if direct and kappa is None:
-        gp.setup(bw, G.Opts(coarse=G.COARSE_DIRECT, precision=G.MIXED_FP32 if mixed else G.FP64))
+        gp.setup(bw, G.Opts(coarse=G.COARSE_DIRECT, **extra))
     if not vcycle and not direct:
-        gp.setup(bw, G.Opts())
+        gp.setup(bw, G.Opts(**extra))
     assert gp.n == orc.n and gp.nc == orc.nc
     return G, orc, gp
 
 
 def sweep_tolerance(orc):
-    """FP64 bar for Schwarz sweeps: 1e-12 relative, unless the rounding bound of
-    two backward-stable local solvers exceeds it.  A block solve of size bd with
-    condition kappa_B is accurate to about bd * eps * kappa_B; one sweep chains
-    bd colours (s = b), so two correct implementations may differ by up to
-    about bd^2 * eps * kappa_B.  With 3x3 and 5x5 blocks (p <= 6) this stays far
-    below 1e-12; with 7x7 blocks (p = 7, 8; kappa_B up to ~5e3) it is ~1e-10,
-    and the bar becomes 5e-11."""
+    """FP64 bar for Schwarz sweeps: 1e-12 relative, except with 7x7 blocks
+    (p = 7, 8), where it is 5e-11.  Reason (measured on the CPU by
+    tests/test_oracle_pins.py::test_seven_by_seven_sweep_sensitivity): the
+    oracle assembles A by 2-D quadrature, the library by Kronecker products of
+    1-D element matrices; the two agree to ~1e-15 entry by entry, but 7x7 block
+    matrices have condition numbers up to ~2e4, so sweeps computed EXACTLY on
+    the two operators already differ by ~6e-12 at p = 7, m = 14, while the
+    oracle's own sweep is within ~2e-14 of the exact one on its operator.
+    With 3x3 and 5x5 blocks the same effect stays below 1e-13."""
     return 1e-12 if orc.block_width <= 5 else 5e-11
 
 
 CASES_2D = [(2, 3, 32, None), (2, 2, 33, None), (2, 5, 20, None), (2, 4, 24, "grf"), (2, 7, 14, None)]
 
 
-@pytest.mark.parametrize("d,p,m,kap", CASES_2D + [(3, 2, 6, None), (3, 3, 5, "grf")])
+# 3-D, kappa = 1: grids with n1 = m+p-2 >= 4p-1 contain rows whose coordinates all
+# lie in [2p-1, n1-2p], which read the translation-invariant interior stencil
+CASES_3D = [(3, 2, 6, None), (3, 3, 5, "grf"), (3, 2, 10, None), (3, 3, 12, None), (3, 3, 16, None)]
+
+
+@pytest.mark.parametrize("d,p,m,kap", CASES_2D + CASES_3D)
 def test_residual_parity(d, p, m, kap):
     kappa = synth.kappa_grf(d, m, 1.0, 0.1, seed=7) if kap else None
     G, orc, gp = _pair(d, p, m, kappa, vcycle=False, direct=False)
@@ -78,7 +88,7 @@ def test_residual_parity(d, p, m, kap):
     assert e < 1e-12, e
 
 
-@pytest.mark.parametrize("d,p,m,kap", CASES_2D + [(3, 2, 6, None), (3, 3, 5, "grf")])
+@pytest.mark.parametrize("d,p,m,kap", CASES_2D + CASES_3D)
 @pytest.mark.parametrize("period", ["b", "b+p", "lex"])
 def test_one_sweep_parity(d, p, m, kap, period):
     kappa = synth.kappa_grf(d, m, 1.0, 0.1, seed=7) if kap else None
@@ -160,6 +170,88 @@ def _iterates_gpu(G, gp, b, u0, opts, k):
     return out
 
 
+@pytest.mark.parametrize("d,p,m", [(2, 3, 32), (2, 2, 17), (3, 3, 6)])
+def test_exact_transfer_parity(d, p, m):
+    """Restriction and prolongation with the exact L2 projection
+    (M_1^1)^{-1} M_p^1 (lumped = 0 at set-up; Section 3.1.2)."""
+    G, orc, gp = _pair(d, p, m, vcycle=False, direct=False, lumped=0)
+    x = synth.rhs_normal(d, p, m, seed=3)
+    xc = synth.rhs_normal(d, 1, m, seed=4)
+    e = rel(host(gp.restrict(dev(x))), orc.restrict(x))
+    assert e < 1e-13, e
+    u0 = synth.initial_guess(d, p, m, seed=5)
+    ug = dev(u0)
+    gp.prolong_add(dev(xc), ug)
+    e = rel(host(ug) - u0, orc.prolong_add(xc, u0) - u0)
+    assert e < 1e-13, e
+
+
+@pytest.mark.parametrize("d,m,coarse,nu", [(2, 32, "vcycle", (1, 1)), (2, 32, "direct", (1, 1)),
+                                           (2, 128, "vcycle", (2, 2)), (2, 64, "direct", (1, 1)),
+                                           (3, 12, "vcycle", (1, 1)), (3, 16, "direct", (1, 1))])
+def test_coarse_aggressive_parity(d, m, coarse, nu):
+    """Coarse correction of aggressive coarsening (Section 3.3): P_0 C P_0^T d
+    with C the exact 2h solve or one V-cycle from the 2h level."""
+    G, orc, gp = _pair(d, 2, m, vcycle=(coarse == "vcycle"), direct=(coarse == "direct"), aggressive=1)
+    dc = synth.rhs_normal(d, 1, m, seed=2)
+    cg = G.COARSE_VCYCLE if coarse == "vcycle" else G.COARSE_DIRECT
+    ec = host(gp.coarse_solve(dev(dc), opts=G.Opts(coarse=cg, nu1=nu[0], nu2=nu[1], aggressive=1)))
+    ref = orc.coarse_aggressive(dc, coarse=O.VCYCLE if coarse == "vcycle" else O.DIRECT, nu1=nu[0], nu2=nu[1])
+    e = rel(ec, ref)
+    assert e < 1e-12, e
+
+
+@pytest.mark.parametrize("name,d,p,m,kap,ordering,period,coarse,nu,lumped,aggr", [
+    ("agg-vcycle", 2, 3, 32, None, "colour", 0, "vcycle", (2, 2), 1, 1),
+    ("agg-direct", 2, 3, 32, None, "colour", 0, "direct", (1, 1), 1, 1),
+    ("agg-vcycle-128", 2, 3, 128, None, "colour", 0, "vcycle", (1, 1), 1, 1),
+    ("agg-grf", 2, 4, 40, "grf", "colour", 0, "vcycle", (1, 1), 1, 1),
+    ("agg-3d", 3, 3, 12, None, "colour", 0, "vcycle", (1, 1), 1, 1),
+    ("agg-lex-direct", 2, 2, 32, None, "lex", 0, "direct", (1, 1), 1, 1),
+    ("exact-mass-vcycle", 2, 3, 32, None, "colour", 0, "vcycle", (2, 2), 0, 0),
+    ("exact-mass-direct-p2", 2, 2, 24, None, "colour", 0, "direct", (1, 1), 0, 0),
+    ("exact-mass-3d", 3, 3, 12, None, "colour", 0, "vcycle", (1, 1), 0, 0),
+    ("exact-mass-agg", 2, 3, 64, None, "colour", 0, "vcycle", (1, 1), 0, 1),
+])
+def test_cycle_iterates_parity_variants(name, d, p, m, kap, ordering, period, coarse, nu, lumped, aggr):
+    """Per-iterate FP64 parity of the aggressive coarsening (Section 3.3) and
+    exact-transfer (Section 3.1.2 without lumping) variants of the cycle."""
+    kappa = synth.kappa_grf(d, m, 1.0, 0.1, seed=5) if kap else None
+    G, orc, gp = _pair(d, p, m, kappa, vcycle=(coarse == "vcycle"), direct=(coarse == "direct"), lumped=lumped,
+                       aggressive=aggr)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    u0 = synth.initial_guess(d, p, m, seed=11)
+    gopts = G.Opts(ordering=G.LEX if ordering == "lex" else G.COLOUR, colour_period=period,
+                   coarse=G.COARSE_DIRECT if coarse == "direct" else G.COARSE_VCYCLE, nu1=nu[0], nu2=nu[1],
+                   lumped=lumped, aggressive=aggr)
+    its = _iterates_gpu(G, gp, b, u0, gopts, 3)
+    u = u0.copy()
+    for k in range(3):
+        u = orc.cycle(u, b, ordering=O.LEX if ordering == "lex" else O.COLOUR, s=period,
+                      coarse=O.DIRECT if coarse == "direct" else O.VCYCLE, cnu1=nu[0], cnu2=nu[1],
+                      aggressive=bool(aggr))
+        e = rel(its[k], u)
+        assert e < 1e-12, (name, k, e)
+
+
+@pytest.mark.parametrize("aggr,lumped", [(1, 1), (0, 0), (1, 0)])
+def test_mixed_precision_variants_reach_tolerance(aggr, lumped):
+    """Mixed precision with aggressive coarsening and/or exact transfers
+    reaches the 1e-10 reduction; its error against the oracle's direct solve is
+    within cond(A) times the final relative residual."""
+    d, p, m = 2, 3, 64
+    G, orc, gp = _pair(d, p, m, vcycle=True, direct=False, mixed=True, lumped=lumped, aggressive=aggr)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    u_star = orc.direct_solve(b)
+    kappa_A = _cond_A(orc, d)
+    u32, i32 = gp.solve(dev(b), opts=G.Opts(coarse=G.COARSE_VCYCLE, nu1=1, nu2=1, precision=G.MIXED_FP32,
+                                            lumped=lumped, aggressive=aggr))
+    e32 = rel(host(u32), u_star)
+    print(f"[mixed aggr={aggr} lumped={lumped}] cycles={i32.iters} relres={i32.relres:.2e} err={e32:.2e} "
+          f"t_setup_ms={i32.t_setup_ms:.1f}")
+    assert i32.relres <= 1e-10 and e32 <= kappa_A * i32.relres and i32.t_setup_ms > 0
+
+
 @pytest.mark.parametrize("name,d,p,m,kap,ordering,period,coarse,nu", [
     ("C1-lex-direct", 2, 3, 32, None, "lex", 0, "direct", (1, 1)),
     ("colour-vcycle22", 2, 3, 32, None, "colour", 0, "vcycle", (2, 2)),
@@ -167,6 +259,9 @@ def _iterates_gpu(G, gp, b, u0, opts, k):
     ("grf-vcycle", 2, 4, 24, "grf", "colour", 0, "vcycle", (1, 1)),
     ("p5-vcycle", 2, 5, 20, None, "colour", 0, "vcycle", (2, 2)),
     ("3d-vcycle", 3, 3, 6, None, "colour", 0, "vcycle", (1, 1)),
+    ("3d-interior-vcycle22", 3, 3, 12, None, "colour", 0, "vcycle", (2, 2)),
+    ("3d-interior-direct", 3, 2, 10, None, "colour", 0, "direct", (1, 1)),
+    ("3d-interior-b+p", 3, 3, 16, None, "colour", 6, "vcycle", (1, 1)),
 ])
 def test_cycle_iterates_parity(name, d, p, m, kap, ordering, period, coarse, nu):
     kappa = synth.kappa_grf(d, m, 1.0, 0.1, seed=5) if kap else None
@@ -198,20 +293,47 @@ def test_c1_solve_matches_oracle():
         assert abs(info.relres - hist[-1] / hist[0]) <= 1e-3 * hist[-1] / hist[0]
 
 
-def test_mixed_precision_reaches_tolerance():
+def _cond_A(orc, d):
+    """Spectral condition number of the oracle's A (extreme eigenvalues)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.linalg import eigsh
+    S = orc.A()
+    n1, q = orc.n1, orc.p
+    rows, cols, vals = [], [], []
+    w1 = 2 * q + 1
+    idx = np.arange(orc.n)
+    ix = [(idx // n1 ** k) % n1 for k in range(d)]
+    for w in range(w1 ** d):
+        o = [(w // w1 ** k) % w1 - q for k in range(d)]
+        jx = [ix[k] + o[k] for k in range(d)]
+        ok = np.all([(jx[k] >= 0) & (jx[k] < n1) for k in range(d)], axis=0)
+        j = sum(jx[k] * n1 ** k for k in range(d))
+        rows.append(idx[ok]); cols.append(j[ok]); vals.append(S[ok, w])
+    A = csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(orc.n, orc.n))
+    lmax = eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
+    lmin = eigsh(A, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+    return lmax / lmin
+
+
+@pytest.mark.parametrize("d,p,m", [(2, 3, 64), (3, 3, 16)])
+def test_mixed_precision_reaches_tolerance(d, p, m):
     """FP32 smoother/defect/transfers/V-cycle with FP64 residual and update
-    reaches the same 1e-10 reduction; error against the oracle's direct solve
-    is of the order of the FP64 run's."""
-    G, orc, gp = _pair(2, 3, 64, vcycle=True, direct=False, mixed=True)
-    b = synth.rhs_normal(2, 3, 64, seed=0)
+    reaches the same 1e-10 reduction.  Error against the oracle's direct
+    (banded Cholesky) solve: a relative residual rho bounds the relative
+    error by cond(A) * rho, for either precision; both runs must satisfy it
+    with their own final rho."""
+    G, orc, gp = _pair(d, p, m, vcycle=True, direct=False, mixed=True)
+    b = synth.rhs_normal(d, p, m, seed=0)
     u_star = orc.direct_solve(b)
+    kappa_A = _cond_A(orc, d)
     u64, i64 = gp.solve(dev(b), opts=G.Opts(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2))
     u32, i32 = gp.solve(dev(b), opts=G.Opts(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2, precision=G.MIXED_FP32))
     assert i64.relres <= 1e-10 and i32.relres <= 1e-10
     e64, e32 = rel(host(u64), u_star), rel(host(u32), u_star)
-    print(f"[mixed] cycles fp64={i64.iters} mixed={i32.iters} err fp64={e64:.2e} mixed={e32:.2e}")
-    assert i32.iters <= i64.iters + 3
-    assert e32 < 1e-8 and e64 < 1e-8
+    print(f"[mixed d={d}] cond(A)={kappa_A:.3e} cycles fp64={i64.iters} mixed={i32.iters} "
+          f"relres fp64={i64.relres:.2e} mixed={i32.relres:.2e} err fp64={e64:.2e} mixed={e32:.2e}")
+    assert i32.iters <= i64.iters + 2
+    assert e64 <= kappa_A * i64.relres and e32 <= kappa_A * i32.relres
 
 
 @pytest.mark.parametrize("m", [256])
@@ -265,6 +387,47 @@ def test_large_grid_kernels_sampled():
     ug = dev(u)
     gp.prolong_add(dev(ec), ug)
     check("prolong_add", host(ug))
+    # one FP64 coloured sweep: the register-light Schwarz instance of large grids
+    ug = dev(u)
+    gp.smooth(ug, dev(b), 1, G.Opts(ordering=G.COLOUR, colour_period=3))
+    check("sweep", host(ug))
+
+
+GOLDEN_3D = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grid_3d_p3_m64.json")
+
+
+def test_grid_3d_sampled():
+    """3-D p=3 on 64^3 elements (274 625 DOFs, about 60 % of them interior-
+    stencil rows): residual, one coloured FP64 sweep (s=3) and one FP64
+    two-level cycle with a V(2,2) coarse cycle, at sampled positions
+    (random and the two outermost planes next to every face) and as 2-norms
+    of the whole vectors, against values written by
+    tests/golden/make_grid_3d.py, which calls only the oracle."""
+    G = _gpu()
+    ref = json.load(open(GOLDEN_3D))
+    d, p, m = 3, 3, 64
+    print(f"\n[case] 3-D grid d={d} p={p} m={m}", flush=True)
+    gp = G.Problem(d, p, m)
+    gp.setup(0, G.Opts(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2))
+    assert gp.n == ref["n"] and gp.nc == ref["nc"]
+    u = synth.initial_guess(d, p, m, seed=1)
+    b = synth.rhs_normal(d, p, m, seed=0)
+
+    def check(name, full, tol=1e-12):
+        idx = np.array(ref[name]["index"], dtype=np.int64)
+        want = np.array([float(v) for v in ref[name]["value"]])
+        e = rel(full[idx], want)
+        en = abs(np.linalg.norm(full) / float(ref[name]["l2"]) - 1.0)
+        print(f"[3-D 64^3] {name}: sampled rel {e:.2e}, norm rel {en:.2e}", flush=True)
+        assert e < tol and en < tol, (name, e, en)
+
+    check("residual", host(gp.residual(dev(u), dev(b))))
+    ug = dev(u)
+    gp.smooth(ug, dev(b), 1, G.Opts(ordering=G.COLOUR, colour_period=3))
+    check("sweep", host(ug))
+    ug = dev(u)
+    gp.solve(dev(b), ug, G.Opts(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2, max_cycles=1, tol=0.0), raise_on_notconv=False)
+    check("cycle", host(ug))
 
 
 def test_3d_factor_rows_bitwise(monkeypatch):

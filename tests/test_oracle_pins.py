@@ -585,17 +585,95 @@ def test_vcycle_coarse_matches_exact_coarse_rate():
 
 
 def test_coloured_iteration_counts_in_paper_band():
-    """Coloured variants reach a 1e-8 reduction from a random guess in a number
-    of cycles comparable to Table 4 (context band, not an exact target)."""
+    """The configuration of Table 4 (coloured Schwarz sweep, aggressive
+    coarsening to degree 1 on 2h with one V(1,1) red-black cycle, random
+    initial guess, 1e-8 reduction) reaches the tolerance in a number of cycles
+    comparable to the paper's (context band, not an exact target: the paper's
+    colouring is not reproducible, Section 3.1.1); the same method without
+    aggressive coarsening needs about as many (Section 3.3)."""
     table = _golden("table4_iterations.txt")
-    it_paper = {2: table[0][1], 3: table[0][2], 4: table[0][3]}
-    for p in (2, 3, 4):
+    it_paper = {2: table[0][1], 3: table[0][2], 4: table[0][3], 5: table[0][4]}
+    for p in (2, 3, 4, 5):
         m = 64
         P = O.Problem(2, p, m, vcycle=True, coarse_direct=False)
         u0 = synth.initial_guess(2, p, m, seed=7)
         _, k, _ = P.solve(np.zeros(P.n), u0=u0, ordering=O.COLOUR, coarse=O.VCYCLE, cnu1=1, cnu2=1,
-                          tol=1e-8, max_cycles=60)
+                          tol=1e-8, max_cycles=60, aggressive=True)
+        _, k_same, _ = P.solve(np.zeros(P.n), u0=u0, ordering=O.COLOUR, coarse=O.VCYCLE, cnu1=1, cnu2=1,
+                               tol=1e-8, max_cycles=60)
         assert it_paper[p] - 3 <= k <= 3 * it_paper[p], (p, k)
+        assert abs(k - k_same) <= 1, (p, k, k_same)
+
+
+def _interp_1d(n1f):
+    """Linear interpolation from the odd-indexed interior nodes (coarse node I
+    at fine index 2I+1) of a 1-D grid of n1f interior nodes, zero boundary."""
+    n1c = n1f // 2
+    P0 = np.zeros((n1f, n1c))
+    for I in range(n1c):
+        P0[2 * I + 1, I] = 1.0
+        P0[2 * I, I] = 0.5
+        if 2 * I + 2 < n1f:
+            P0[2 * I + 2, I] = 0.5
+    return P0
+
+
+@pytest.mark.parametrize("d,p,m", [(2, 3, 24), (3, 2, 10)])
+def test_aggressive_coarse_correction_dense(d, p, m):
+    """Aggressive coarsening (Section 3.3), dense statement: after the sweep,
+    u1 = u_s + P_p P_0 A_2h^{-1} P_0^T R (b - A u_s), where R, P_p = R^T are the
+    degree transfers on h (Section 3.1.2), P_0 the linear interpolation from
+    the 2h grid and A_2h = P_0^T A_1 P_0, which for kappa = 1 equals the degree-1
+    operator assembled directly on m/2 elements.  With a hierarchy of two
+    levels the V-cycle variant solves the 2h level exactly, so it gives the
+    same iterate."""
+    P = O.Problem(d, p, m, vcycle=True, coarse_direct=False)
+    assert P.nlevels() == 2
+    A = O.offsets_to_dense(P.A(), d, P.n1, p)
+    A1 = O.offsets_to_dense(P.Alow(), d, P.n1c, 1)
+    Mmix = O.mix_to_dense(P.Mmix(), d, p, 1, m)
+    R = Mmix / P.Dlump()[:, None]
+    P1 = _interp_1d(P.n1c)
+    P0 = P1
+    for _ in range(d - 1):
+        P0 = np.kron(P0, P1)
+    A2h = P0.T @ A1 @ P0
+    A2h_direct = O.offsets_to_dense(O.assemble(d, 1, m // 2), d, m // 2 - 1, 1)
+    assert np.allclose(A2h, A2h_direct, atol=1e-13 * np.abs(A2h).max())
+    b = synth.rhs_normal(d, p, m, seed=31)
+    u0 = synth.initial_guess(d, p, m, seed=32)
+    us = P.sweep(u0, b, ordering=O.COLOUR)
+    ref = us + R.T @ (P0 @ np.linalg.solve(A2h, P0.T @ (R @ (b - A @ us))))
+    got = P.cycle(u0, b, ordering=O.COLOUR, coarse=O.DIRECT, aggressive=True)
+    assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    got_v = P.cycle(u0, b, ordering=O.COLOUR, coarse=O.VCYCLE, cnu1=2, cnu2=1, aggressive=True)
+    assert np.allclose(got_v, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.slow
+def test_table3_aggressive_rates():
+    """Table 3 (rho_2g^ag: degree 1 on 2h, exact coarse solve): the measured
+    rate of the lexicographic method with aggressive coarsening on 64x64
+    elements is within 8 % of the LFA prediction for p = 3, 4, 5.  At p = 2 the
+    measured rate stays below the prediction and rises with m (0.09, 0.14,
+    0.14 on 64, 128, 256 elements): the infinite-grid analysis is pessimistic
+    there; checked as a band at m = 128.  One V(1,1) cycle on the 2h level
+    gives the same rate as the exact 2h solve (p = 3)."""
+    ref = {int(r[0]): (int(r[1]), r[2]) for r in _golden("table3_rho_ag.txt")}
+    for p, m, lo, hi in [(3, 64, 0.92, 1.08), (4, 64, 0.92, 1.08), (5, 64, 0.92, 1.08), (2, 128, 0.7, 1.0)]:
+        bw, rho_lfa = ref[p]
+        P = O.Problem(2, p, m, block_width=bw, vcycle=True, coarse_direct=False)
+        K = 30 if p <= 4 else 25
+        u0 = synth.initial_guess(2, p, m, seed=1)
+        _, _, hist = P.solve(np.zeros(P.n), u0=u0, ordering=O.LEX, coarse=O.DIRECT, aggressive=True, tol=0.0,
+                             max_cycles=K)
+        est = (hist[K] / hist[10]) ** (1.0 / (K - 10))
+        assert lo < est / rho_lfa < hi, (p, est, rho_lfa)
+        if p == 3:
+            _, _, hv = P.solve(np.zeros(P.n), u0=u0, ordering=O.LEX, coarse=O.VCYCLE, aggressive=True, tol=0.0,
+                               max_cycles=K)
+            est_v = (hv[K] / hv[10]) ** (1.0 / (K - 10))
+            assert abs(est_v / est - 1) < 0.02, (est_v, est)
 
 
 def test_solution_matches_direct_solve():
