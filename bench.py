@@ -32,7 +32,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP64_PEAK_TFS = 78.6        # MI355X FP64 vector, published
-FP32_PEAK_TFS = 157.3       # MI355X FP32 vector, published
+FP32_PEAK_TFS = 157.3       # MI355X FP32 vector, published (packed FP32 instructions)
+# FP32 without packed instructions (the library is compiled without them): one
+# FMA per lane per cycle, 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+FP32_NONPACKED_TFS = 78.6
 
 
 def parse():
@@ -76,6 +79,16 @@ def cpu_baseline(d, p, m, b, nu, cycles_gpu):
                      f"(relres {rel:.1e}); set-up {t_setup:.1f}s excluded",
            "seconds_per_cycle": t_cyc / ncyc, "host_cpu": _cpu_model(), "nproc": os.cpu_count()}
     return rec, (u if rel <= 1e-10 else None)
+
+
+def oracle_solution(d, p, m, b, kappa=None, nu=(2, 2), tol=1e-10, max_cycles=200):
+    """CPU-oracle leg of the suite lines: the oracle's converged solution of the
+    same coloured two-level solve (FP64, V(nu) coarse, from u=0), against which
+    the GPU result's error is stated."""
+    import oracle as O
+    orc = O.Problem(d, p, m, kappa=kappa, vcycle=True, coarse_direct=False)
+    u, k, _ = orc.solve(b, coarse=O.VCYCLE, cnu1=nu[0], cnu2=nu[1], tol=tol, max_cycles=max_cycles)
+    return u, k
 
 
 def _cpu_model():
@@ -127,7 +140,7 @@ def roofline_large(torch, G, m, p=3):
     return out
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_colour_2d_p3_m256_fp64_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_colour_2d_p3_m256_fp32_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_01499_amd", "csrc", "kernels_fine.hip")
 
 
@@ -246,22 +259,31 @@ def main():
     }
     # ---- roofline of the dominant kernel, HIP-event timed
     if not args.no_roofline:
-        sweep_opts = G.Opts()
+        # The timed mixed solve spends most of its time in the FP32 Schwarz colour
+        # kernel (9 launches per cycle).  Its work per launch: one block per DOF,
+        # n/b^d blocks per colour, each 2 b^d (2p+1)^d flops for the block
+        # residual and 2 b^{2d} for the shared inverse: n (2(2p+1)^d + 2 b^d)
+        # flops, bound by FP32 arithmetic (no dense contraction in 2-D).
+        # Timed by the library with HIP events on the stream it launches on.
+        bw = 3
+        flops = float(n) * (2 * (2 * p + 1) ** d + 2 * bw ** d)
+        ms32 = prob.time_colour(G.MIXED_FP32, 50)
+        ms64 = prob.time_colour(G.FP64, 50)
+        ach32 = flops / (ms32 * 1e-3) / 1e12
+        ach64 = flops / (ms64 * 1e-3) / 1e12
+        out["roofline"] = {"kernel": f"k_colour<2,{p},3,float,true> (one colour of the FP32 Schwarz sweep)",
+                           "bound": "alu", "achieved": ach32, "peak": FP32_PEAK_TFS, "unit": "TFLOP/s",
+                           "frac": ach32 / FP32_PEAK_TFS, "traffic": measured_traffic(),
+                           "frac_nonpacked_fp32_peak": ach32 / FP32_NONPACKED_TFS,
+                           "avg_launch_us": ms32 * 1e3, "algorithmic_flops_per_launch": flops,
+                           "bytes_view": {"algorithmic_bytes_per_sweep": 12.0 * n,
+                                          "GB_per_s_per_sweep": 12.0 * n / (9 * ms32 * 1e-3) / 1e9},
+                           "note": "latency-bound at 66049 DOFs (0.26 MB per FP32 vector); see roofline_large"}
+        out["roofline_fp64_colour"] = {"kernel": f"k_colour<2,{p},3,double,true>", "bound": "alu",
+                                       "achieved": ach64, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                                       "frac": ach64 / FP64_PEAK_TFS, "avg_launch_us": ms64 * 1e3,
+                                       "algorithmic_flops_per_launch": flops}
         uu = torch.zeros_like(b)
-        ncol = 9
-        ms_sweep = event_time(torch, lambda: prob.smooth(uu, b, 1, sweep_opts), 50)
-        ms_col = ms_sweep / ncol
-        # algorithmic bytes per colour launch (FP64): iterate and right-hand
-        # side read, new iterate written, 24 B per DOF.  kappa = 1: interior
-        # tiles take the operator from the interior stencil (no diagonals are
-        # read); the shared block inverses (49 x 81 words) stay in cache.
-        bytes_per_launch = 24.0 * n
-        achieved = bytes_per_launch / (ms_col * 1e-3) / 1e9
-        out["roofline"] = {"kernel": "k_colour<2,3,3,double,true> (one colour of the Schwarz sweep)",
-                           "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                           "avg_launch_us": ms_col * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch,
-                           "note": "latency-bound at 66049 DOFs (0.5 MB per vector); see roofline_large"}
         r = torch.empty_like(b)
         ms_res = event_time(torch, lambda: prob.residual(uu, b, r), 100)
         ach_res = 24.0 * n / (ms_res * 1e-3) / 1e9

@@ -6,15 +6,25 @@ as one JSON line each (the headline line of bench.py stays the first line).
   C3  3-D p=3, 64x64x64, coloured 3x3x3 Schwarz, V(2,2) coarse, FP64 and mixed
   C4  256 independent 2-D problems, m in 32..128, p in 2..4, kappa = exp(GRF)
   C5  2-D p=4 256x256 GRF kappa: forward mixed solve + adjoint gradient
+  AGG 2-D 256x256, p = 2..5, the paper's timed configuration: aggressive
+      coarsening (degree 1 on 2h) with one V(1,1) cycle there
+Each line states the error of the GPU solution against the oracle's (C3:
+against sampled values of a stored oracle solution; C4: four sampled problems).
 Every step is a complete solve to a 1e-10 residual reduction from u = 0 with
 inputs resident on the GPU; times are host wall clock around synchronised
 calls.
 """
 from __future__ import annotations
 
+import json
+import os
 import time
 
+import numpy as np
+
 import synth
+
+GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "c3_solution_3d_p3_m64.json")
 
 
 def _timed(torch, fn, steps):
@@ -28,17 +38,23 @@ def _timed(torch, fn, steps):
     return (time.perf_counter() - t0) / steps, out
 
 
-def _solve_line(torch, G, name, d, p, m, opts_list, steps, kappa=None, block_width=0):
+def _error_vs(u_ref, u):
+    return float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
+
+
+def _solve_line(torch, G, name, d, p, m, opts_list, steps, kappa=None, block_width=0, oracle_ref=None):
+    """oracle_ref(b_np, solutions) -> dict of errors against the oracle (or None)."""
     prob = G.Problem(d, p, m, kappa=kappa, device=0)
     t0 = time.perf_counter()
     for o in opts_list.values():
         prob.setup(block_width, o)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    b = torch.tensor(synth.rhs_normal(d, p, m, seed=0), device="cuda")
+    b_np = synth.rhs_normal(d, p, m, seed=0)
+    b = torch.tensor(b_np, device="cuda")
     u = torch.zeros_like(b)
     line = {"config": name, "dim": d, "p": p, "m": m, "n_fine": prob.n, "setup_s": t_setup}
-
+    sols = {}
     for label, o in opts_list.items():
         def one():
             u.zero_()
@@ -46,8 +62,38 @@ def _solve_line(torch, G, name, d, p, m, opts_list, steps, kappa=None, block_wid
         t, info = _timed(torch, one, steps)
         line[label] = {"time_to_tol_ms": 1e3 * t, "cycles": info.iters, "relres": info.relres,
                        "fine_dof_per_s_per_cycle": prob.n * info.iters / t}
+        sols[label] = u.cpu().numpy().copy()
     prob.close()
+    if oracle_ref is not None:
+        line["error_vs_oracle"] = oracle_ref(b_np, sols)
     return line
+
+
+def _oracle_c2(d, p, m, nu):
+    """Errors of every solution against the oracle's converged solution of the
+    same FP64 solve (CPU-oracle leg)."""
+    def ref(b_np, sols):
+        from bench import oracle_solution
+        u_orc, k = oracle_solution(d, p, m, b_np, nu=nu)
+        out = {label: _error_vs(u_orc, v) for label, v in sols.items()}
+        out["oracle_cycles"] = k
+        return out
+    return ref
+
+
+def _oracle_c3(b_np, sols):
+    """C3: the oracle's solution at 3000 sampled DOFs and its 2-norm, written by
+    tests/golden/make_c3_solution.py (the oracle's set-up at 64^3 takes ~20 min)."""
+    if not os.path.exists(GOLDEN_C3):
+        return None
+    ref = json.load(open(GOLDEN_C3))
+    idx = np.array(ref["sample"]["index"], dtype=np.int64)
+    want = np.array([float(v) for v in ref["sample"]["value"]])
+    out = {"oracle_cycles": ref["cycles"], "sample": "3000 seeded DOFs + 2-norm of u"}
+    for label, v in sols.items():
+        out[label] = {"sampled_rel": _error_vs(want, v[idx]),
+                      "norm_rel": abs(float(np.linalg.norm(v)) / float(ref["u_l2"]) - 1.0)}
+    return out
 
 
 def run(torch, G, steps=5, only=None):
@@ -66,12 +112,22 @@ def run(torch, G, steps=5, only=None):
     # C2 sweep over p
     for p in ((2, 3, 4, 5) if want("C2") else ()):
         lines.append(_solve_line(torch, G, "C2", 2, p, 256,
-                                 {"fp64": G.Opts(**v22), "mixed": G.Opts(precision=G.MIXED_FP32, **v22)}, steps))
+                                 {"fp64": G.Opts(**v22), "mixed": G.Opts(precision=G.MIXED_FP32, **v22)}, steps,
+                                 oracle_ref=_oracle_c2(2, p, 256, (2, 2))))
     # C3
     if want("C3"):
         lines.append(_solve_line(torch, G, "C3", 3, 3, 64,
                                  {"fp64": G.Opts(**v22), "mixed": G.Opts(precision=G.MIXED_FP32, **v22)},
-                                 max(2, steps // 2)))
+                                 max(2, steps // 2), oracle_ref=_oracle_c3))
+    # the paper's own configuration (Section 5.1): aggressive coarsening to degree 1
+    # on 2h with one V(1,1) cycle there, coloured sweep
+    if want("AGG"):
+        v11a = dict(coarse=G.COARSE_VCYCLE, nu1=1, nu2=1, tol=1e-10, aggressive=1)
+        for p in (2, 3, 4, 5):
+            line = _solve_line(torch, G, "C2-aggressive", 2, p, 256,
+                               {"fp64": G.Opts(**v11a), "mixed": G.Opts(precision=G.MIXED_FP32, **v11a)}, steps)
+            line["paper_table4_iterations_1e-8_context"] = {2: 6, 3: 6, 4: 7, 5: 5}[p]
+            lines.append(line)
     if want("C4"):
         lines.append(_c4(torch, G, v22))
     if want("C5"):
@@ -109,6 +165,17 @@ def _c4(torch, G, v22):
             pr.solve(b, u, mixed)
 
     t_seq, _ = _timed(torch, one_by_one, 1)
+    # error against the oracle on four sampled problems (mixed batch solution)
+    batch(mixed)
+    torch.cuda.synchronize()
+    err = {}
+    from bench import oracle_solution
+    for k in (0, 85, 170, 255):
+        sp = specs[k]
+        kap = synth.kappa_grf(2, sp["m"], 1.0, 0.1, seed=sp["kappa_seed"])
+        u_orc, _ = oracle_solution(2, sp["p"], sp["m"], synth.rhs_normal(2, sp["p"], sp["m"], seed=sp["rhs_seed"]),
+                                   kappa=kap, nu=(2, 2))
+        err[f"problem {k} (m={sp['m']}, p={sp['p']})"] = _error_vs(u_orc, us[k].cpu().numpy())
     ndof = sum(p.n for p in probs)
     cyc = sum(p.n * i.iters for p, i in zip(probs, infos))
     rec = {"config": "C4", "problems": len(probs), "total_fine_dofs": ndof, "setup_s": t_setup,
@@ -116,7 +183,7 @@ def _c4(torch, G, v22):
                      "worst_relres": max(i.relres for i in infos), "fine_dof_cycles_per_s": cyc / t_mixed},
            "fp64": {"time_to_tol_ms": 1e3 * t_fp64, "max_cycles": max(i.iters for i in infos64),
                     "worst_relres": max(i.relres for i in infos64)},
-           "mixed_one_problem_at_a_time_ms": 1e3 * t_seq}
+           "mixed_one_problem_at_a_time_ms": 1e3 * t_seq, "error_vs_oracle_mixed_sampled": err}
     for pr in probs:
         pr.close()
     return rec
@@ -141,7 +208,13 @@ def _c5(torch, G):
         return loss
 
     t, _ = _timed(torch, fb, 2)
+    # forward solution against the oracle's converged solution (CPU-oracle leg)
+    from bench import oracle_solution
+    u_fwd = G.iga_solve(kt.detach(), b, d, p, m, fwd, tight).cpu().numpy()
+    u_orc, _ = oracle_solution(d, p, m, b.cpu().numpy(), kappa=kap, nu=(2, 2))
+    err_fwd = _error_vs(u_orc, u_fwd)
     rec = {"config": "C5", "dim": d, "p": p, "m": m, "forward_backward_ms_incl_assembly": 1e3 * t,
+           "error_vs_oracle_forward_mixed": err_fwd,
            "note": "assembly + set-up of A(kappa), mixed forward solve, FP64 adjoint solve to 1e-12, "
                    "dL/dkappa kernel"}
     obs.close()

@@ -154,6 +154,19 @@ int iga2l_smooth(const iga2l_problem *prob, double *u, const double *b, int nswe
 int iga2l_smooth_noalloc(const iga2l_problem *prob, double *u, const double *b, int nsweeps,
                          const iga2l_opts *opts, void *stream);
 
+/*
+ * Measurement helper for benchmarks: the average duration in milliseconds of
+ * one launch of the coloured Schwarz kernel (one colour of the sweep of
+ * Section 3.1.1, colour period from opts, default the block width) in the
+ * given arithmetic (IGA2L_FP64, or IGA2L_MIXED_FP32 for the FP32 kernel of
+ * the mixed-precision correction cycle), timed with HIP events on stream over
+ * nsweeps (>= 1) back-to-back sweeps after one warm-up sweep.  The sweeps run
+ * on the problem's own correction workspaces with a zero iterate and
+ * right-hand side (their previous contents are lost).  Synchronises.
+ */
+int iga2l_time_colour(const iga2l_problem *prob, int precision, int nsweeps, const iga2l_opts *opts,
+                      void *stream, double *ms_per_launch);
+
 /* d_coarse = D^{-1} M_p^{1} r_fine: the restriction of Section 3.1.2 with the
  * row-sum lumped degree-1 mass matrix D (with lumped = 0 at the last set-up:
  * (M_1^1)^{-1} M_p^1 r_fine).  FP64, n_fine -> n_coarse. */

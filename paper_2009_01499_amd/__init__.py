@@ -94,6 +94,8 @@ _EXPORTS = {
                                     ctypes.POINTER(CIgaOpts), ctypes.c_void_p]),
     "iga2l_smooth_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.POINTER(CIgaOpts), ctypes.c_void_p]),
+    "iga2l_time_colour": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(CIgaOpts),
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "iga2l_restrict": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "iga2l_prolong": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "iga2l_coarse_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -216,6 +218,14 @@ class Problem:
         _check(lib().iga2l_smooth_noalloc(self._h, _dev_ptr(u, self.n, "u"), _dev_ptr(b, self.n, "b"), nsweeps,
                                           ctypes.byref(o), _stream(stream)))
         return u
+
+    def time_colour(self, precision: int = FP64, nsweeps: int = 20, opts: Optional[Opts] = None, stream=None) -> float:
+        """Average ms per launch of the coloured Schwarz kernel (HIP events in the library)."""
+        o = (opts or Opts()).c()
+        ms = ctypes.c_double()
+        _check(lib().iga2l_time_colour(self._h, precision, nsweeps, ctypes.byref(o), _stream(stream),
+                                       ctypes.byref(ms)))
+        return ms.value
 
     def restrict(self, r, dc=None, stream=None):
         torch = _torch()

@@ -584,6 +584,58 @@ int iga2l_smooth_noalloc(const iga2l_problem *prob, double *u, const double *b, 
     });
 }
 
+int iga2l_time_colour(const iga2l_problem *prob, int precision, int nsweeps, const iga2l_opts *opts, void *stream,
+                      double *ms_per_launch) {
+    return guarded([&] {
+        IGA2L_REQUIRE(prob && ms_per_launch, IGA2L_EINVAL, "null argument");
+        IGA2L_REQUIRE(nsweeps >= 1, IGA2L_EINVAL, "nsweeps must be >= 1");
+        Problem &P = const_cast<Problem &>(prob->P);
+        IGA2L_REQUIRE(P.blocks_ready, IGA2L_EINVAL, "iga2l_setup_blocks must run first");
+        IGA2L_REQUIRE(precision == IGA2L_FP64 || (precision == IGA2L_MIXED_FP32 && P.fp32_ready), IGA2L_EINVAL,
+                      "precision not set up");
+        iga2l_opts o = effective_opts(opts);
+        o.ordering = IGA2L_COLOUR;
+        check_opts(P, o);
+        set_device(P);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int S = o.colour_period ? o.colour_period : P.bw;
+        const int ncol = (P.dim == 3) ? S * S * S : S * S;
+        const bool fp32 = precision == IGA2L_MIXED_FP32;
+        // zero iterate and right-hand side (the arithmetic does not depend on the values)
+        launch_fill_zero(P.ework[0].ptr, P.fine.n, fp32, s, nullptr);
+        launch_fill_zero(P.ework[1].ptr, P.fine.n, fp32, s, nullptr);
+        launch_fill_zero(P.rhs_w.ptr, P.fine.n, fp32, s, nullptr);
+        auto sweep = [&]() {
+            int cur = 0;
+            for (int cz = 0; cz < ((P.dim == 3) ? S : 1); ++cz)
+                for (int cy = 0; cy < S; ++cy)
+                    for (int cx = 0; cx < S; ++cx) {
+                        if (fp32)
+                            launch_colour_step<float>(P, cx, cy, cz, S, P.ework[cur].as<float>(),
+                                                      P.ework[1 - cur].as<float>(), P.rhs_w.as<float>(), false, s);
+                        else
+                            launch_colour_step<double>(P, cx, cy, cz, S, P.ework[cur].as<double>(),
+                                                       P.ework[1 - cur].as<double>(), P.rhs_w.as<double>(), false, s);
+                        cur = 1 - cur;
+                    }
+        };
+        sweep();   // warm-up
+        hipEvent_t e0, e1;
+        IGA2L_HIP(hipEventCreate(&e0));
+        IGA2L_HIP(hipEventCreate(&e1));
+        float ms = 0.0f;
+        hipError_t err = hipEventRecord(e0, s);
+        for (int k = 0; k < nsweeps && err == hipSuccess; ++k) sweep();
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        IGA2L_HIP(err);
+        *ms_per_launch = double(ms) / (double(nsweeps) * ncol);
+    });
+}
+
 int iga2l_restrict(const iga2l_problem *prob, const double *r_fine, double *d_coarse, void *stream) {
     return guarded([&] {
         IGA2L_REQUIRE(prob && r_fine && d_coarse, IGA2L_EINVAL, "null argument");

@@ -9,8 +9,8 @@ Inputs are the seeded synthetic vectors of `synth` (u: initial_guess seed 1,
 b: rhs_normal seed 0).  Samples: 1500 uniform random positions plus every 4th
 point (in both in-plane directions) of the two outermost grid planes next to
 each of the six faces, where rows differ from the interior stencil.  The
-oracle's brute-force 3-D assembly at this size takes minutes on one core, so
-the GPU tests read the file.
+oracle's brute-force 3-D assembly at this size takes about 20 minutes on one
+core, so the GPU tests read the file.
 
 Run from the repository root:  python tests/golden/make_grid_3d.py
 """
