@@ -621,7 +621,9 @@ static int build_blocks(or_problem *P) {
  * rediscretisation for kappa = 1); for other m the last coarse cell next to
  * the boundary is narrower.
  */
+#ifndef OR_COARSEST_MAX
 #define OR_COARSEST_MAX 512
+#endif
 static double interp_weight(int i_fine, int I_coarse) {
     /* fine interior node i sits at grid node i+1, coarse node I at fine grid
      * node 2(I+1), i.e. fine interior index 2I+1 */

@@ -379,6 +379,16 @@ bool tune_log();
 std::vector<std::pair<int, int>> colour_tile_candidates(int S, int n1);
 template <class T>
 void launch_cast_scale(const Problem &P, const double *r64, T *rhs, hipStream_t s);
+// 3-D kappa = 1 by sum factorisation (kernels_3d.hip): the Schwarz colour with
+// colour period 3 and 3x3x3 blocks (shared inverse applied by MFMA) and the residual
+bool colour3d_sf_ok(const Problem &P, int S);
+bool residual3d_sf_ok(const Problem &P);
+int64_t residual3d_sf_workgroups(const Problem &P);
+template <class T>
+void launch_colour3d_sf(const Problem &P, int cx, int cy, int cz, const T *x_src, T *x_dst, const T *rhs, bool x_zero,
+                        const double *r64, T *rhs_out, hipStream_t s);
+template <class T, bool NORM>
+void launch_residual3d_sf(const Problem &P, const T *x, const T *b, T *r, double *partial, hipStream_t s);
 // 2-D bandwidth-oriented variants (kernels_2d.hip)
 template <class T>
 void launch_residual2d(const Problem &P, const T *val, const T *x, const T *b, T *r, double *partial, hipStream_t s);

@@ -865,6 +865,16 @@ void residual_launch(const Problem &Pb, const T *val, const T *x, const T *b, T 
                                dev_hist(Pb), Pb.hist_cap);
         return;
     }
+    if constexpr (D == 3) if (residual3d_sf_ok(Pb)) {
+        // kappa = 1: sum factorisation over the 1-D factors
+        launch_residual3d_sf<T, NORM>(Pb, x, b, r, NORM ? partial : nullptr, s);
+        nblocks = int(residual3d_sf_workgroups(Pb));
+        if (NORM)
+            hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, Pb.partial.as<double>(), nblocks,
+                               Pb.scal.as<double>(), scale_fp32 ? 1 : 0, book ? dev_flags(Pb) : nullptr,
+                               dev_hist(Pb), Pb.hist_cap);
+        return;
+    }
     using TS = TileShape<D, P>;
     const int n1 = Pb.fine.n1;
     dim3 grid((n1 + TS::TX - 1) / TS::TX, (n1 + TS::TY - 1) / TS::TY, D == 3 ? (n1 + TS::TZ - 1) / TS::TZ : 1);
@@ -926,6 +936,11 @@ void defect_dp(const Problem &Pb, const T *e, const T *rhs, T *d, hipStream_t s)
 template <int D, int P, int B, class T>
 void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs,
                    bool x_zero, const double *r64, T *rhs_out, hipStream_t s, int tile_nbx = 0, int tile_nby = 0) {
+    if constexpr (D == 3 && B == 3) if (colour3d_sf_ok(Pb, S)) {
+        // kappa = 1, colour period 3: sum-factorised residual, shared inverse on MFMA
+        launch_colour3d_sf<T>(Pb, cx, cy, cz, x_src, x_dst, rhs, x_zero, r64, rhs_out, s);
+        return;
+    }
     const int n1 = Pb.fine.n1;
     constexpr int HB = (B - 1) / 2;
     constexpr int pr = std::is_same<T, double>::value ? 0 : 1;
@@ -1127,6 +1142,7 @@ template void launch_defect<float>(const Problem &, const float *, const float *
 
 // number of workgroups of the FP64 residual launch (one partial sum each)
 int64_t residual_workgroups(const Problem &Pb) {
+    if (residual3d_sf_ok(Pb)) return residual3d_sf_workgroups(Pb);
     const int64_t n1 = Pb.fine.n1;
     if (Pb.dim == 2) return ((n1 + TileShape<2, 1>::TX - 1) / TileShape<2, 1>::TX) * ((n1 + TileShape<2, 1>::TY - 1) / TileShape<2, 1>::TY);
     return ((n1 + TileShape<3, 1>::TX - 1) / TileShape<3, 1>::TX) * ((n1 + TileShape<3, 1>::TY - 1) / TileShape<3, 1>::TY) *
