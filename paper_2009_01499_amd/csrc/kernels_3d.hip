@@ -32,7 +32,7 @@ namespace iga2l {
 
 namespace {
 
-constexpr int kSfThreads = 256;
+constexpr int kSfThreads = 512;
 constexpr int kSfWaves = kSfThreads / 64;
 
 typedef float sf_f4 __attribute__((ext_vector_type(4)));
@@ -58,6 +58,7 @@ struct Sf {
     static constexpr int NBX = TX / 3, NBY = TY / 3, NBZ = TZ / 3, NB = NBX * NBY * NBZ;
     static constexpr int NG = (NB + 15) / 16;       // groups of 16 blocks (MFMA columns)
     static constexpr int PTS = (NR + kSfThreads - 1) / kSfThreads;   // tile points per thread
+    static constexpr int UH = (NU + kSfThreads - 1) / kSfThreads;    // halo loads per thread
     static_assert(NR <= NT, "r and delta live in the tM / tK area");
 };
 
@@ -156,7 +157,8 @@ __device__ __forceinline__ void sf_stage(T *sm, const T *__restrict__ x, const T
         // kron = K1 [n1][W1] then M1 [n1][W1]
         f[i] = in ? kron[(c < W1 ? int64_t(0) : int64_t(n1) * W1) + int64_t(g) * W1 + (c % W1)] : T(0);
     }
-    stage_lds<4, T>(sm, G::NU, [&](int h) -> T {
+    // every halo load of a thread is issued before its first LDS store: one memory round trip
+    stage_lds<G::UH, T>(sm, G::NU, [&](int h) -> T {
         const int hx = h % G::HX, hy = (h / G::HX) % G::HY, hz = h / (G::HX * G::HY);
         const int gx = gx0 + hx - P, gy = gy0 + hy - P, gz = gz0 + hz - P;
         const bool in = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && gz >= 0 && gz < n1;
@@ -234,7 +236,7 @@ __global__ void __launch_bounds__(kSfThreads) k_colour3d_sf(
     const bool mfma = clsL >= 0;
     const int mt = wave % 2;    // M tile (block points 0..15 or 16..31) of this wave's jobs
     T ainv[7];
-    if (mfma) {
+    if (mfma && wave / 2 < G::NG) {
         const int64_t slot = int64_t(clsL) * (1 + ncls1 + int64_t(ncls1) * ncls1);
         const int i = mt * 16 + lane % 16;
 #pragma unroll

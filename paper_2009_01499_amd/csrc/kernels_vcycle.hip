@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
     constexpr int NH = HX * HY * HZ;
     __shared__ T e0[NH];
     __shared__ T e1[NH];
+    __shared__ T rs[NH];
     const int n1 = L.n1;
     int bx = blockIdx.x, by = blockIdx.y;
     if (D == 2) xcd_tile_2d(bx, by);
@@ -107,18 +108,49 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
     auto inside = [n1](int x, int y, int z) {
         return x >= 0 && x < n1 && y >= 0 && y < n1 && (D == 2 || (z >= 0 && z < n1));
     };
-    // load the step-start iterate over the tile plus a halo of 2
-    for (int h = threadIdx.x; h < NH; h += blockDim.x) {
+    // load the step-start iterate over the tile plus a halo of 2, and the
+    // right-hand side over the same window; every load of a thread is issued
+    // before its first LDS store (one memory round trip)
+    constexpr int U = (NH + 255) / 256;
+    auto halo_index = [&](int h, int64_t &gi) {
         const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
         const int gx = gx0 + hx - 2, gy = gy0 + hy - 2, gz = gz0 + hz - zoff;
-        T v = T(0);
-        if (inside(gx, gy, gz)) {
-            const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
-            if (!zero_src) v = e_src[gi];
-            if (ec) v += interp_value<D, T>(ec, n1c, gx, gy, gz);
+        gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+        return inside(gx, gy, gz);
+    };
+    if (!ec) {
+        T v[U], rv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int h = int(threadIdx.x) + u * int(blockDim.x);
+            int64_t gi = 0;
+            const bool in = h < NH && halo_index(h, gi);
+            v[u] = (in && !zero_src) ? e_src[gi] : T(0);
+            rv[u] = in ? rhs[gi] : T(0);
         }
-        e0[h] = v;
-        e1[h] = v;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int h = int(threadIdx.x) + u * int(blockDim.x);
+            if (h < NH) {
+                e0[h] = v[u];
+                e1[h] = v[u];
+                rs[h] = rv[u];
+            }
+        }
+    } else {
+        for (int h = threadIdx.x; h < NH; h += blockDim.x) {
+            int64_t gi = 0;
+            T v = T(0), rv = T(0);
+            if (halo_index(h, gi)) {
+                const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+                if (!zero_src) v = e_src[gi];
+                v += interp_value<D, T>(ec, n1c, gx0 + hx - 2, gy0 + hy - 2, gz0 + hz - zoff);
+                rv = rhs[gi];
+            }
+            e0[h] = v;
+            e1[h] = v;
+            rs[h] = rv;
+        }
     }
     __syncthreads();
     // red half step on the tile and its halo ring of width 1
@@ -134,7 +166,7 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
             for (int oy = -1; oy <= 1; ++oy)
                 for (int ox = -1; ox <= 1; ++ox)
                     acc += coef<D, T>(L, gi, w_of<D>(ox, oy, oz)) * e0[h + (oz * HY + oy) * HX + ox];
-        e1[h] = e0[h] + (rhs[gi] - acc) * inv_diag<D, T>(L, gi);
+        e1[h] = e0[h] + (rs[h] - acc) * inv_diag<D, T>(L, gi);
     }
     __syncthreads();
     if (stop) return;
@@ -153,7 +185,7 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
                 for (int oy = -1; oy <= 1; ++oy)
                     for (int ox = -1; ox <= 1; ++ox)
                         acc += coef<D, T>(L, gi, w_of<D>(ox, oy, oz)) * e1[h + (oz * HY + oy) * HX + ox];
-            v = e1[h] + (rhs[gi] - acc) * inv_diag<D, T>(L, gi);
+            v = e1[h] + (rs[h] - acc) * inv_diag<D, T>(L, gi);
         }
         e_dst[gi] = v;
     }
@@ -332,21 +364,35 @@ __global__ void __launch_bounds__(256) k_res_restrict_tiled(LevelDev<T> L, const
     auto inside = [n1](int x, int y, int z) {
         return x >= 0 && x < n1 && y >= 0 && y < n1 && (D == 2 || (z >= 0 && z < n1));
     };
+    // the right-hand side of this thread's fine points and the iterate halo:
+    // every load issued before the first LDS store
+    constexpr int NF = FX * FY * FZ, UF = (NF + 255) / 256;
+    T rv[UF];
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+        const int f = int(threadIdx.x) + u * int(blockDim.x);
+        const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
+        const int gx = fx0 + fx, gy = fy0 + fy, gz = fz0 + fz;
+        rv[u] = (f < NF && inside(gx, gy, gz)) ? rhs[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
+    }
     if (!zero_e) {
-        for (int h = threadIdx.x; h < EX * EY * EZ; h += blockDim.x) {
+        stage_lds<(EX * EY * EZ + 255) / 256, T>(es, EX * EY * EZ, [&](int h) -> T {
             const int hx = h % EX, hy = (h / EX) % EY, hz = h / (EX * EY);
             const int gx = fx0 + hx - 1, gy = fy0 + hy - 1, gz = fz0 + hz - ez;
-            es[h] = inside(gx, gy, gz) ? e[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
-        }
+            return inside(gx, gy, gz) ? e[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
+        });
         __syncthreads();
     }
-    for (int f = threadIdx.x; f < FX * FY * FZ; f += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+        const int f = int(threadIdx.x) + u * int(blockDim.x);
+        if (f >= NF) continue;
         const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
         const int gx = fx0 + fx, gy = fy0 + fy, gz = fz0 + fz;
         T r = T(0);
         if (inside(gx, gy, gz)) {
             const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
-            r = rhs[gi];
+            r = rv[u];
             if (!zero_e) {
                 const int h = ((fz + ez) * EY + (fy + 1)) * EX + (fx + 1);
                 T acc = T(0);
