@@ -57,8 +57,15 @@ struct Sf {
     static constexpr int OFF_R = OFF_T, OFF_D = OFF_T + NT;
     static constexpr int NBX = TX / 3, NBY = TY / 3, NBZ = TZ / 3, NB = NBX * NBY * NBZ;
     static constexpr int NG = (NB + 15) / 16;       // groups of 16 blocks (MFMA columns)
-    static constexpr int PTS = (NR + kSfThreads - 1) / kSfThreads;   // tile points per thread
     static constexpr int UH = (NU + kSfThreads - 1) / kSfThreads;    // halo loads per thread
+    // thread mappings that keep a thread's factor rows fixed: the x pass gives
+    // thread t the column x = t % TX (XA threads, rows strided by XR); the y
+    // pass and the tile points give thread t < YA the column (x, y) =
+    // (t % TX, t / TX % TY) and the planes t / YT + YR k
+    static constexpr int XR = kSfThreads / TX, XA = XR * TX;
+    static constexpr int YT = TX * TY, YR = kSfThreads / YT, YA = YR * YT;
+    static constexpr int PTS = TZ / YR;      // tile points per thread (q = t + YA k)
+    static_assert(TZ % YR == 0, "tile planes must divide among the thread planes");
     static_assert(NR <= NT, "r and delta live in the tM / tK area");
 };
 
@@ -87,40 +94,55 @@ template <int P, class T>
 __device__ __forceinline__ void sf_apply(T *sm) {
     using G = Sf<P>;
     constexpr int W1 = G::W1;
+    const int t = threadIdx.x;
     const T *xs = sm;
     T *tM = sm + G::OFF_T, *tK = tM + G::NT;
     const T *fx = sm + G::OFF_F, *fy = fx + G::TX * 2 * W1;
     // x pass: tM, tK at (x, hy, hz) for the tile's x and the halo's y, z
-    for (int q = threadIdx.x; q < G::NT; q += kSfThreads) {
-        const int x = q % G::TX, hyz = q / G::TX;
-        const T *xr = xs + hyz * G::HX + x;
-        const T *kr = fx + x * 2 * W1, *mr = kr + W1;
-        T am = T(0), ak = T(0);
+    if (t < G::XA) {
+        const int x = t % G::TX;
+        T kr[W1], mr[W1];
 #pragma unroll
         for (int o = 0; o < W1; ++o) {
-            const T v = xr[o];
-            am += mr[o] * v;
-            ak += kr[o] * v;
+            kr[o] = fx[x * 2 * W1 + o];
+            mr[o] = fx[x * 2 * W1 + W1 + o];
         }
-        tM[q] = am;
-        tK[q] = ak;
+        for (int row = t / G::TX; row < G::HY * G::HZ; row += G::XR) {
+            const T *xr = xs + row * G::HX + x;
+            T am = T(0), ak = T(0);
+#pragma unroll
+            for (int o = 0; o < W1; ++o) {
+                const T v = xr[o];
+                am += mr[o] * v;
+                ak += kr[o] * v;
+            }
+            tM[row * G::TX + x] = am;
+            tK[row * G::TX + x] = ak;
+        }
     }
     __syncthreads();
     // y pass: a = My tM, b = Ky tM + My tK at (x, y, hz)
     T *a = sm + G::OFF_A, *b = a + G::NA;
-    for (int q = threadIdx.x; q < G::NA; q += kSfThreads) {
-        const int x = q % G::TX, y = (q / G::TX) % G::TY, hz = q / (G::TX * G::TY);
-        const int base = (hz * G::HY + y) * G::TX + x;
-        const T *kr = fy + y * 2 * W1, *mr = kr + W1;
-        T va = T(0), vb = T(0);
+    if (t < G::YA) {
+        const int x = t % G::TX, y = (t / G::TX) % G::TY;
+        T kr[W1], mr[W1];
 #pragma unroll
         for (int o = 0; o < W1; ++o) {
-            const T m = tM[base + o * G::TX], k = tK[base + o * G::TX];
-            va += mr[o] * m;
-            vb += kr[o] * m + mr[o] * k;
+            kr[o] = fy[y * 2 * W1 + o];
+            mr[o] = fy[y * 2 * W1 + W1 + o];
         }
-        a[q] = va;
-        b[q] = vb;
+        for (int hz = t / G::YT; hz < G::HZ; hz += G::YR) {
+            const int base = (hz * G::HY + y) * G::TX + x;
+            T va = T(0), vb = T(0);
+#pragma unroll
+            for (int o = 0; o < W1; ++o) {
+                const T m = tM[base + o * G::TX], k = tK[base + o * G::TX];
+                va += mr[o] * m;
+                vb += kr[o] * m + mr[o] * k;
+            }
+            a[(hz * G::TY + y) * G::TX + x] = va;
+            b[(hz * G::TY + y) * G::TX + x] = vb;
+        }
     }
     __syncthreads();
 }
@@ -166,6 +188,14 @@ __device__ __forceinline__ void sf_stage(T *sm, const T *__restrict__ x, const T
     });
 }
 
+// tile point q (x fastest) of the tile with origin (gx0, gy0, gz0) inside the grid
+template <int P>
+__device__ __forceinline__ bool in_grid3(int gx0, int gy0, int gz0, int q, int n1) {
+    using G = Sf<P>;
+    const int gx = gx0 + q % G::TX, gy = gy0 + (q / G::TX) % G::TY, gz = gz0 + q / G::YT;
+    return gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && gz >= 0 && gz < n1;
+}
+
 // tile -> workgroup: tiles dealt to the XCDs in contiguous bands
 __device__ __forceinline__ void sf_tile(int ntx, int nty, int ntz, int &tx, int &ty, int &tz) {
     int L, dummy;
@@ -202,7 +232,7 @@ struct MfmaAcc<double> {
 // kappa = 1.  x_zero: the colour-start iterate is zero (no halo, r = rhs);
 // r64 (with x_zero): the right-hand side is r64 / sigma, also stored to rhs_out.
 template <int P, class T>
-__global__ void __launch_bounds__(kSfThreads) k_colour3d_sf(
+__global__ void __launch_bounds__(kSfThreads, 4) k_colour3d_sf(
     const T *__restrict__ kron, int n1, const T *__restrict__ inv, int clsL, int ncls1, const T *__restrict__ x_src,
     T *__restrict__ x_dst, const T *__restrict__ rhs, int x_zero, int ox, int oy, int oz, int ntx, int nty, int ntz,
     const int *__restrict__ skip, const double *__restrict__ r64, const double *__restrict__ scal,
@@ -214,22 +244,40 @@ __global__ void __launch_bounds__(kSfThreads) k_colour3d_sf(
     int tbx, tby, tbz;
     sf_tile(ntx, nty, ntz, tbx, tby, tbz);
     const int gx0 = ox + tbx * G::TX, gy0 = oy + tby * G::TY, gz0 = oz + tbz * G::TZ;
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    // this thread's tile points: right-hand side and iterate, issued with the halo
+    const int t = threadIdx.x, lane = t % 64, wave = t / 64;
+    // this thread's tile points q = t + YA k: right-hand side, iterate and the
+    // block each belongs to, issued with the halo
     T rv[G::PTS], xv[G::PTS];
+    // per point: -2 outside the grid or in no block of the colour, -1 interior
+    // block (MFMA), else the offset of its inverse row (boundary block)
+    int64_t rowoff[G::PTS];
 #pragma unroll
     for (int k = 0; k < G::PTS; ++k) {
-        const int q = threadIdx.x + k * kSfThreads;
-        const int x = q % G::TX, y = (q / G::TX) % G::TY, z = q / (G::TX * G::TY);
+        const int q = t + k * G::YA;
+        const int x = q % G::TX, y = (q / G::TX) % G::TY, z = q / G::YT;
         const int gx = gx0 + x, gy = gy0 + y, gz = gz0 + z;
-        const bool in = q < G::NR && gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && gz >= 0 && gz < n1;
+        const bool in = t < G::YA && gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && gz >= 0 && gz < n1;
         const int64_t gi = in ? (int64_t(gz) * n1 + gy) * n1 + gx : 0;
         rv[k] = T(0);
         xv[k] = T(0);
+        rowoff[k] = -2;
         if (in) {
             if (r64) rv[k] = T(r64[gi] * scal[kScalInvSigma]);
             else rv[k] = rhs[gi];
             if (!x_zero) xv[k] = x_src[gi];
+            const int ccx = gx0 + 3 * (x / 3) + 1, ccy = gy0 + 3 * (y / 3) + 1, ccz = gz0 + 3 * (z / 3) + 1;
+            if (ccx >= 0 && ccx < n1 && ccy >= 0 && ccy < n1 && ccz >= 0 && ccz < n1) {
+                const int cx = clsL >= 0 ? sf_block_class(ccx, n1, clsL) : ccx;
+                const int cy = clsL >= 0 ? sf_block_class(ccy, n1, clsL) : ccy;
+                const int cz = clsL >= 0 ? sf_block_class(ccz, n1, clsL) : ccz;
+                if (clsL >= 0 && cx == clsL && cy == clsL && cz == clsL) {
+                    rowoff[k] = -1;
+                } else {
+                    const int64_t slot = cx + int64_t(ncls1) * cy + int64_t(ncls1) * ncls1 * cz;
+                    const int loc = (x % 3) + 3 * (y % 3) + 9 * (z % 3);
+                    rowoff[k] = (slot * 27 + loc) * 27;
+                }
+            }
         }
     }
     // the interior inverse rows this wave multiplies (A operand of its MFMA jobs)
@@ -252,21 +300,13 @@ __global__ void __launch_bounds__(kSfThreads) k_colour3d_sf(
         sf_apply<P, T>(sm);
         // z pass: r = rhs - A x (0 outside the grid); tM / tK are dead, r takes their place
 #pragma unroll
-        for (int k = 0; k < G::PTS; ++k) {
-            const int q = threadIdx.x + k * kSfThreads;
-            if (q < G::NR) {
-                const int x = q % G::TX, y = (q / G::TX) % G::TY, z = q / (G::TX * G::TY);
-                const int gx = gx0 + x, gy = gy0 + y, gz = gz0 + z;
-                const bool in = gx >= 0 && gx < n1 && gy >= 0 && gy < n1 && gz >= 0 && gz < n1;
-                rv[k] = in ? rv[k] - sf_z<P, T>(sm, q) : T(0);
-            }
-        }
+        for (int k = 0; k < G::PTS; ++k)
+            if (t < G::YA)
+                rv[k] = in_grid3<P>(gx0, gy0, gz0, t + k * G::YA, n1) ? rv[k] - sf_z<P, T>(sm, t + k * G::YA) : T(0);
     }
 #pragma unroll
-    for (int k = 0; k < G::PTS; ++k) {
-        const int q = threadIdx.x + k * kSfThreads;
-        if (q < G::NR) r[q] = rv[k];
-    }
+    for (int k = 0; k < G::PTS; ++k)
+        if (t < G::YA) r[t + k * G::YA] = rv[k];
     __syncthreads();
     // interior blocks: delta = Inv R on the matrix cores, jobs (group of 16
     // blocks, M tile) dealt to the waves
@@ -293,30 +333,19 @@ __global__ void __launch_bounds__(kSfThreads) k_colour3d_sf(
     // update: x_dst = x + delta; blocks outside the interior class on the vector units
 #pragma unroll
     for (int k = 0; k < G::PTS; ++k) {
-        const int q = threadIdx.x + k * kSfThreads;
-        if (q >= G::NR) continue;
-        const int x = q % G::TX, y = (q / G::TX) % G::TY, z = q / (G::TX * G::TY);
-        const int gx = gx0 + x, gy = gy0 + y, gz = gz0 + z;
-        if (gx < 0 || gx >= n1 || gy < 0 || gy >= n1 || gz < 0 || gz >= n1) continue;
-        const int64_t gi = (int64_t(gz) * n1 + gy) * n1 + gx;
+        const int q = t + k * G::YA;
+        if (t >= G::YA || !in_grid3<P>(gx0, gy0, gz0, q, n1)) continue;
+        const int x = q % G::TX, y = (q / G::TX) % G::TY, z = q / G::YT;
+        const int64_t gi = (int64_t(gz0 + z) * n1 + gy0 + y) * n1 + gx0 + x;
         if (r64) rhs_out[gi] = rv[k];
-        const int bx = x / 3, by = y / 3, bz = z / 3;
-        const int ccx = gx0 + 3 * bx + 1, ccy = gy0 + 3 * by + 1, ccz = gz0 + 3 * bz + 1;
         T d = T(0);
-        if (ccx >= 0 && ccx < n1 && ccy >= 0 && ccy < n1 && ccz >= 0 && ccz < n1) {
-            const int cx = clsL >= 0 ? sf_block_class(ccx, n1, clsL) : ccx;
-            const int cy = clsL >= 0 ? sf_block_class(ccy, n1, clsL) : ccy;
-            const int cz = clsL >= 0 ? sf_block_class(ccz, n1, clsL) : ccz;
-            if (mfma && cx == clsL && cy == clsL && cz == clsL) {
-                d = delta[q];
-            } else {
-                const int64_t slot = cx + int64_t(ncls1) * cy + int64_t(ncls1) * ncls1 * cz;
-                const int loc = (x % 3) + 3 * (y % 3) + 9 * (z % 3);
-                const T *row = inv + (slot * 27 + loc) * 27;
-                const int nblk = (bz * G::NBY + by) * G::NBX + bx;
+        if (rowoff[k] == -1) {
+            d = delta[q];
+        } else if (rowoff[k] >= 0) {
+            const int nblk = ((z / 3) * G::NBY + y / 3) * G::NBX + x / 3;
+            // (loading these rows ahead into registers measured slower: occupancy)
 #pragma unroll
-                for (int l = 0; l < 27; ++l) d += row[l] * r[sf_block_point<P>(nblk, l)];
-            }
+            for (int l = 0; l < 27; ++l) d += inv[rowoff[k] + l] * r[sf_block_point<P>(nblk, l)];
         }
         x_dst[gi] = xv[k] + d;
     }
@@ -337,12 +366,13 @@ __global__ void __launch_bounds__(kSfThreads) k_residual3d_sf(const T *__restric
     int tbx, tby, tbz;
     sf_tile(ntx, nty, ntz, tbx, tby, tbz);
     const int gx0 = tbx * G::TX, gy0 = tby * G::TY, gz0 = tbz * G::TZ;
+    const int t = threadIdx.x;
     T bv[G::PTS];
 #pragma unroll
     for (int k = 0; k < G::PTS; ++k) {
-        const int q = threadIdx.x + k * kSfThreads;
-        const int gx = gx0 + q % G::TX, gy = gy0 + (q / G::TX) % G::TY, gz = gz0 + q / (G::TX * G::TY);
-        const bool in = q < G::NR && gx < n1 && gy < n1 && gz < n1;
+        const int q = t + k * G::YA;
+        const int gx = gx0 + q % G::TX, gy = gy0 + (q / G::TX) % G::TY, gz = gz0 + q / G::YT;
+        const bool in = t < G::YA && gx < n1 && gy < n1 && gz < n1;
         bv[k] = in ? b[(int64_t(gz) * n1 + gy) * n1 + gx] : T(0);
     }
     sf_stage<P, T>(sm, x, kron, n1, gx0, gy0, gz0);
@@ -351,9 +381,9 @@ __global__ void __launch_bounds__(kSfThreads) k_residual3d_sf(const T *__restric
     double rr = 0.0;
 #pragma unroll
     for (int k = 0; k < G::PTS; ++k) {
-        const int q = threadIdx.x + k * kSfThreads;
-        const int gx = gx0 + q % G::TX, gy = gy0 + (q / G::TX) % G::TY, gz = gz0 + q / (G::TX * G::TY);
-        if (q < G::NR && gx < n1 && gy < n1 && gz < n1) {
+        const int q = t + k * G::YA;
+        const int gx = gx0 + q % G::TX, gy = gy0 + (q / G::TX) % G::TY, gz = gz0 + q / G::YT;
+        if (t < G::YA && gx < n1 && gy < n1 && gz < n1) {
             const T res = bv[k] - sf_z<P, T>(sm, q);
             if (!stop) r[(int64_t(gz) * n1 + gy) * n1 + gx] = res;
             rr += double(res) * double(res);
