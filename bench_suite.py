@@ -158,6 +158,11 @@ def _c4(torch, G, v22):
 
     t_mixed, infos = _timed(torch, lambda: batch(mixed), 3)
     t_fp64, infos64 = _timed(torch, lambda: batch(fp64), 3)
+    # the same with the kernels of every cycle launched directly instead of the
+    # captured graph being replayed (numerics identical)
+    os.environ["IGA2L_BATCH_GRAPH"] = "0"
+    t_mixed_eager, _ = _timed(torch, lambda: batch(mixed), 3)
+    del os.environ["IGA2L_BATCH_GRAPH"]
 
     def one_by_one():
         for pr, b, u in zip(probs, bs, us):
@@ -183,6 +188,7 @@ def _c4(torch, G, v22):
                      "worst_relres": max(i.relres for i in infos), "fine_dof_cycles_per_s": cyc / t_mixed},
            "fp64": {"time_to_tol_ms": 1e3 * t_fp64, "max_cycles": max(i.iters for i in infos64),
                     "worst_relres": max(i.relres for i in infos64)},
+           "mixed_without_graph_ms": 1e3 * t_mixed_eager,
            "mixed_one_problem_at_a_time_ms": 1e3 * t_seq, "error_vs_oracle_mixed_sampled": err}
     for pr in probs:
         pr.close()

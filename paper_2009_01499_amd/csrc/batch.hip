@@ -14,6 +14,7 @@
 #include <atomic>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -65,8 +66,16 @@ struct Plan {
     DevBuf status_dev;
     double *status_host = nullptr;     // pinned
     int expected_cycles = 1;
+    // one cycle (correction cycle + FP64 residual, norm and convergence test)
+    // captured into a HIP graph, replayed once per cycle
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 
     ~Plan() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (host_table) (void)hipHostFree(host_table);
         if (status_host) (void)hipHostFree(status_host);
     }
@@ -365,6 +374,35 @@ void batch_residual(const Plan &pl, bool fp32, bool book, hipStream_t s) {
     launch_norm_finalize_batch(tb, pl.nprob, fp32, book, s);
 }
 
+// IGA2L_BATCH_GRAPH=0 in the environment: launch the kernels of every cycle
+// directly instead of replaying the captured graph (same kernels, same results)
+bool batch_graph_enabled() {
+    const char *e = std::getenv("IGA2L_BATCH_GRAPH");
+    return !(e && e[0] == '0');
+}
+
+// Captures one cycle of the plan (kernel launches only: no memset or copy
+// nodes) on a private stream of default priority and instantiates it.  The
+// kernels read every problem's vectors through the device table, so the graph
+// stays valid for every call with the same plan.
+void ensure_graph(Plan &pl, bool fp32) {
+    if (pl.gexec) return;
+    if (!pl.cap_stream) IGA2L_HIP(hipStreamCreateWithFlags(&pl.cap_stream, hipStreamNonBlocking));
+    IGA2L_HIP(hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        if (fp32) batch_cycle<float>(pl, pl.cap_stream);
+        else batch_cycle<double>(pl, pl.cap_stream);
+        batch_residual(pl, fp32, true, pl.cap_stream);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(pl.cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    IGA2L_HIP(hipStreamEndCapture(pl.cap_stream, &pl.graph));
+    IGA2L_HIP(hipGraphInstantiate(&pl.gexec, pl.graph, nullptr, nullptr, 0));
+}
+
 }  // namespace
 
 bool batch_supported(Problem *const *probs, int nprob, const iga2l_opts &o) {
@@ -418,11 +456,17 @@ void solve_batch_fused(Problem *const *probs, int nprob, const double *const *b,
     int issued = 0;
     int batch = std::max(1, std::min(pl.expected_cycles, o.max_cycles));
     const int fixed = kScalCount + kFlagCount / 2;
+    const bool graph = batch_graph_enabled();
+    if (graph) ensure_graph(pl, fp32);
     while (true) {
         for (int j = 0; j < batch && issued < o.max_cycles; ++j, ++issued) {
-            if (fp32) batch_cycle<float>(pl, s);
-            else batch_cycle<double>(pl, s);
-            batch_residual(pl, fp32, true, s);
+            if (graph) {
+                IGA2L_HIP(hipGraphLaunch(pl.gexec, s));
+            } else {
+                if (fp32) batch_cycle<float>(pl, s);
+                else batch_cycle<double>(pl, s);
+                batch_residual(pl, fp32, true, s);
+            }
         }
         IGA2L_HIP(hipGetLastError());
         const int words = fixed + std::min(issued, pl.hist_cap);

@@ -131,3 +131,31 @@ def test_batch_fallback_paths():
     probs3 = [G.Problem(3, 2, m).setup(3, col3) for m in (8, 12)]
     bs3 = [torch.tensor(synth.rhs_normal(3, 2, m, seed=6), device="cuda") for m in (8, 12)]
     _single_vs_batch(G, probs3, bs3, col3, "3d")
+
+
+def test_batch_graph_replays_equal_eager(monkeypatch):
+    """The batched cycle runs as a captured HIP graph, replayed once per cycle.
+    Three batched solves in a row (graph replays, with eager single-problem
+    solves and synchronisations between them) each equal the batched solve
+    with direct kernel launches (IGA2L_BATCH_GRAPH=0) bit for bit, and so do
+    the single solves."""
+    G = _G()
+    specs = synth.batch_specs(8, seed=5)
+    print("\n[case] graph replays, batch of", [(s["m"], s["p"]) for s in specs], flush=True)
+    opts = G.Opts(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2, tol=1e-10, precision=G.MIXED_FP32)
+    probs, bs = _problems(G, specs, opts)
+    monkeypatch.setenv("IGA2L_BATCH_GRAPH", "0")
+    ref = [torch.zeros_like(b) for b in bs]
+    ref_infos = G.solve_batch(probs, bs, ref, opts)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("IGA2L_BATCH_GRAPH", "1")
+    for rep in range(3):
+        us = [torch.zeros_like(b) for b in bs]
+        infos = G.solve_batch(probs, bs, us, opts)
+        torch.cuda.synchronize()
+        for k in range(len(bs)):
+            assert infos[k].iters == ref_infos[k].iters, (rep, k)
+            assert torch.equal(us[k], ref[k]), (rep, k)
+        u1, _ = probs[rep].solve(bs[rep], None, opts)
+        torch.cuda.synchronize()
+        assert torch.equal(u1, ref[rep]), rep
