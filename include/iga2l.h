@@ -72,6 +72,12 @@ typedef struct {
                             COARSE_VCYCLE runs one V(nu1,nu2) cycle from the 2h level, COARSE_DIRECT
                             solves the 2h level exactly (kappa = 1, m even).  Needs more than 512
                             unknowns on the degree-1 level.  0: degree 1 on the same grid */
+    int plow;            /* degree of the coarse space on the same knots (Section 3.1): 1 (default) or
+                            2 (Section 5, for geometries that need it); 2 is solved exactly
+                            (COARSE_DIRECT, kappa = 1, by fast diagonalisation of the 1-D degree-2
+                            stiffness and mass matrices), with lumped or exact transfers.  Fixed by
+                            iga2l_setup_blocks (which re-sizes the coarse space); n_coarse =
+                            (m + plow - 2)^d */
 } iga2l_opts;
 
 typedef struct {
@@ -87,7 +93,7 @@ typedef struct {
 
 /* Fill o with the defaults: tol 1e-10, 100 cycles, COLOUR with s = block
  * width, V(1,1) coarse cycle, FP64, no post-smoothing, lumped transfers,
- * degree-1 coarse level on the same grid. */
+ * degree-1 coarse level on the same grid (plow = 1). */
 void iga2l_default_opts(iga2l_opts *o);
 
 /*

@@ -38,7 +38,7 @@ class CIgaOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_cycles", ctypes.c_int), ("ordering", ctypes.c_int),
                 ("colour_period", ctypes.c_int), ("coarse", ctypes.c_int), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("precision", ctypes.c_int), ("fine_post_sweeps", ctypes.c_int),
-                ("lumped", ctypes.c_int), ("aggressive", ctypes.c_int)]
+                ("lumped", ctypes.c_int), ("aggressive", ctypes.c_int), ("plow", ctypes.c_int)]
 
 
 class CIgaInfo(ctypes.Structure):
@@ -61,10 +61,12 @@ class Opts:
     fine_post_sweeps: int = 0
     lumped: int = 1
     aggressive: int = 0
+    plow: int = 1
 
     def c(self) -> CIgaOpts:
         return CIgaOpts(self.tol, self.max_cycles, self.ordering, self.colour_period, self.coarse,
-                        self.nu1, self.nu2, self.precision, self.fine_post_sweeps, self.lumped, self.aggressive)
+                        self.nu1, self.nu2, self.precision, self.fine_post_sweeps, self.lumped, self.aggressive,
+                        self.plow)
 
 
 @dataclasses.dataclass
@@ -194,6 +196,9 @@ class Problem:
     def setup(self, block_width: int = 0, opts: Optional[Opts] = None):
         o = (opts or Opts()).c()
         _check(lib().iga2l_setup_blocks(self._h, block_width, ctypes.byref(o)))
+        nc = ctypes.c_int64()
+        _check(lib().iga2l_sizes(self._h, None, ctypes.byref(nc), None))
+        self.nc = nc.value      # the coarse space follows the set-up's plow
         return self
 
     # --------------------------------------------------------- operations --

@@ -86,6 +86,10 @@ void check_opts(const Problem &P, const iga2l_opts &o) {
                   "the lexicographic ordering runs in FP64 only");
     IGA2L_REQUIRE(o.lumped == 0 || o.lumped == 1, IGA2L_EINVAL, "lumped must be 0 or 1");
     IGA2L_REQUIRE(o.aggressive == 0 || o.aggressive == 1, IGA2L_EINVAL, "aggressive must be 0 or 1");
+    IGA2L_REQUIRE(o.plow == 1 || o.plow == 2, IGA2L_EINVAL, "plow must be 1 or 2");
+    IGA2L_REQUIRE(o.plow == 1 || o.plow <= P.p, IGA2L_EINVAL, "plow may not exceed p");
+    IGA2L_REQUIRE(o.plow == 1 || (o.coarse == IGA2L_COARSE_DIRECT && !o.aggressive), IGA2L_EUNSUPPORTED,
+                  "the degree-2 coarse space is solved exactly (coarse = COARSE_DIRECT, no aggressive coarsening)");
 }
 
 // Applies the exact (not lumped) transfers while a call runs.
@@ -235,6 +239,7 @@ void solve_impl(Problem &P, const double *b, double *u, const iga2l_opts &o, iga
     IGA2L_REQUIRE(b && u, IGA2L_EINVAL, "null vector");
     const bool fp32 = o.precision == IGA2L_MIXED_FP32;
     IGA2L_REQUIRE(!fp32 || P.fp32_ready, IGA2L_EINVAL, "FP32 data not set up (setup_blocks with MIXED_FP32)");
+    IGA2L_REQUIRE(o.plow == P.plow, IGA2L_EINVAL, "coarse degree differs from the last set-up (iga2l_setup_blocks)");
     IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_VCYCLE || P.vcycle_ready, IGA2L_EINVAL, "V-cycle not set up");
     if (o.aggressive)
         IGA2L_REQUIRE(o.coarse != IGA2L_COARSE_DIRECT || P.agg_direct_ready, IGA2L_EINVAL,
@@ -373,6 +378,7 @@ void iga2l_default_opts(iga2l_opts *o) {
     o->fine_post_sweeps = 0;
     o->lumped = 1;
     o->aggressive = 0;
+    o->plow = 1;
 }
 
 const char *iga2l_last_error(void) { return g_last_error.c_str(); }
@@ -465,6 +471,10 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             stage("block inverses");
         }
         check_opts(P, o);
+        if (o.plow != P.plow) {
+            host_set_coarse_degree(P, o.plow);
+            stage("coarse space");
+        }
         if (o.precision == IGA2L_MIXED_FP32 && !P.fp32_ready) {
             P.A.v32.alloc(size_t(P.A.Wh) * P.A.npad * sizeof(float));
             launch_convert(P.A.v64.ptr, P.A.v32.ptr, int64_t(P.A.Wh) * P.A.npad, true, s);

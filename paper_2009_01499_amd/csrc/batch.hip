@@ -408,7 +408,7 @@ void ensure_graph(Plan &pl, bool fp32) {
 bool batch_supported(Problem *const *probs, int nprob, const iga2l_opts &o) {
     if (nprob < 2) return false;
     if (o.ordering != IGA2L_COLOUR || o.coarse != IGA2L_COARSE_VCYCLE || o.fine_post_sweeps != 0) return false;
-    if (!o.lumped || o.aggressive) return false;   // exact transfers / 2h coarse level: problem by problem
+    if (!o.lumped || o.aggressive || o.plow != 1) return false;   // other coarse spaces: problem by problem
     if (o.nu1 < 0 || o.nu1 > 4 || o.nu2 < 1 || o.nu2 > 4) return false;
     for (int k = 0; k < nprob; ++k) {
         const Problem &P = *probs[k];

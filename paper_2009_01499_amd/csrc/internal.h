@@ -120,7 +120,8 @@ struct Problem {
 
     // host copies of the 1-D factors (per direction identical)
     std::vector<double> K1, M1;   // [n1][2p+1], interior rows, offset j-i+p
-    std::vector<double> R1;       // [n1c][p+2], coarse row I, fine column I-1+a
+    int plow = 1;                 // degree of the coarse space (1 or 2)
+    std::vector<double> R1;       // [n1c][p+plow+1], coarse row I, fine column I-plow+a
     std::vector<double> Mx1;      // the same without the lumped scaling: Mmix1
     std::vector<std::vector<double>> Ke, Me;  // element matrices [m][(p+1)^2]
 
@@ -157,6 +158,9 @@ struct Problem {
     // by the same DST-I; dstM_mu holds its eigenvalues (products of the 1-D
     // ones), Mx64/Mx32 the unlumped 1-D factor Mmix1 [n1c][p+2]
     DevBuf dstM_S, dstM_mu, Mx64, Mx32, ctmp2;
+    // degree-2 coarse space (kappa = 1): fast diagonalisation, forward V^T and
+    // backward V per axis; dst_mu then holds the eigenvalue sums, dstM_mu ones
+    DevBuf fdm_Vt, fdm_V;
     bool mass_ready = false;
     // aggressive coarsening (degree 1 on 2h): exact 2h solve by the DST-I of
     // level 1 of the V-cycle hierarchy (kappa = 1, m even)
@@ -344,7 +348,11 @@ void solve_batch_fused(Problem *const *probs, int nprob, const double *const *b,
 void host_assemble(Problem &P);                 // 1-D factors, DIA, transfers, kappa
 void host_build_levels(Problem &P);             // V-cycle hierarchy (Galerkin)
 void host_build_dst(Problem &P);                // exact coarse solver (kappa = 1)
-void host_build_mass(Problem &P);               // exact M_1^{-1} transfers (DST-I of the mass matrix)
+void host_build_mass(Problem &P);               // exact M_low^{-1} transfers (DST-I / fast diagonalisation)
+void host_transfer_factors(Problem &P, int plow);  // 1-D transfer factors, coarse grid of degree plow
+void host_coarse_workspaces(Problem &P);        // coarse vectors sized by the coarse grid
+void host_set_coarse_degree(Problem &P, int plow);
+void host_build_fdm(Problem &P);                // exact degree-2 coarse solve (kappa = 1)
 void host_build_agg_direct(Problem &P);         // exact 2h solve of aggressive coarsening
 void host_block_classes(Problem &P, std::vector<int> &cls1, std::vector<int64_t> &reps);
 void host_lex_schedule(Problem &P);

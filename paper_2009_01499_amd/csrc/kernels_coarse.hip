@@ -17,28 +17,29 @@ namespace {
 inline unsigned nblocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
 // ------------------------------------------------------------ transfers --
-// d_c[I] = sum_a R1[Ix][ax] R1[Iy][ay] (R1[Iz][az]) d[I - 1 + a], a in [0,p+1]^D
+// d_c[I] = sum_a R1[Ix][ax] R1[Iy][ay] (R1[Iz][az]) d[I - plow + a],
+// a in [0, p+plow]^D (coarse space of degree plow)
 template <int D, class T>
-__global__ void k_restrict(const T *__restrict__ R1, int p, int n1f, int n1c, const T *__restrict__ df,
+__global__ void k_restrict(const T *__restrict__ R1, int p, int plow, int n1f, int n1c, const T *__restrict__ df,
                            T *__restrict__ dc, const int *__restrict__ skip) {
     const int stop = skip ? *skip : 0;  // tested before the store (hides the load latency)
     const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nc = (D == 3) ? int64_t(n1c) * n1c * n1c : int64_t(n1c) * n1c;
     if (I >= nc) return;
     const int Ix = int(I % n1c), Iy = int((I / n1c) % n1c), Iz = (D == 3) ? int(I / (int64_t(n1c) * n1c)) : 0;
-    const int w = p + 2;
+    const int w = p + plow + 1;
     T acc = T(0);
     for (int az = 0; az < ((D == 3) ? w : 1); ++az) {
-        const int jz = (D == 3) ? Iz - 1 + az : 0;
+        const int jz = (D == 3) ? Iz - plow + az : 0;
         if (D == 3 && (jz < 0 || jz >= n1f)) continue;
         const T rz = (D == 3) ? R1[Iz * w + az] : T(1);
         for (int ay = 0; ay < w; ++ay) {
-            const int jy = Iy - 1 + ay;
+            const int jy = Iy - plow + ay;
             if (jy < 0 || jy >= n1f) continue;
             const T ry = R1[Iy * w + ay] * rz;
             T line = T(0);
             for (int ax = 0; ax < w; ++ax) {
-                const int jx = Ix - 1 + ax;
+                const int jx = Ix - plow + ax;
                 if (jx < 0 || jx >= n1f) continue;
                 line += R1[Ix * w + ax] * df[(int64_t(jz) * n1f + jy) * n1f + jx];
             }
@@ -49,23 +50,24 @@ __global__ void k_restrict(const T *__restrict__ R1, int p, int n1f, int n1c, co
     dc[I] = acc;
 }
 
-// (P e_c)[i] = sum over coarse I with i - I + 1 in [0,p+1] per direction of
-// R1[Ix][ix-Ix+1] R1[Iy][iy-Iy+1] (..) e_c[I]: the exact transpose of k_restrict.
+// (P e_c)[i] = sum over coarse I with i - I + plow in [0,p+plow] per direction
+// of R1[Ix][ix-Ix+plow] R1[Iy][iy-Iy+plow] (..) e_c[I]: the exact transpose of
+// k_restrict.
 template <int D, class T>
-__device__ __forceinline__ T prolong_value(const T *__restrict__ R1, int p, int n1f, int n1c,
+__device__ __forceinline__ T prolong_value(const T *__restrict__ R1, int p, int plow, int n1f, int n1c,
                                            const T *__restrict__ ec, int ix, int iy, int iz) {
-    const int w = p + 2;
+    const int w = p + plow + 1;
     T acc = T(0);
-    for (int Iz = ((D == 3) ? iz - p : 0); Iz <= ((D == 3) ? iz + 1 : 0); ++Iz) {
+    for (int Iz = ((D == 3) ? iz - p : 0); Iz <= ((D == 3) ? iz + plow : 0); ++Iz) {
         if (D == 3 && (Iz < 0 || Iz >= n1c)) continue;
-        const T rz = (D == 3) ? R1[Iz * w + (iz - Iz + 1)] : T(1);
-        for (int Iy = iy - p; Iy <= iy + 1; ++Iy) {
+        const T rz = (D == 3) ? R1[Iz * w + (iz - Iz + plow)] : T(1);
+        for (int Iy = iy - p; Iy <= iy + plow; ++Iy) {
             if (Iy < 0 || Iy >= n1c) continue;
-            const T ry = R1[Iy * w + (iy - Iy + 1)] * rz;
+            const T ry = R1[Iy * w + (iy - Iy + plow)] * rz;
             T line = T(0);
-            for (int Ix = ix - p; Ix <= ix + 1; ++Ix) {
+            for (int Ix = ix - p; Ix <= ix + plow; ++Ix) {
                 if (Ix < 0 || Ix >= n1c) continue;
-                line += R1[Ix * w + (ix - Ix + 1)] * ec[(int64_t(Iz) * n1c + Iy) * n1c + Ix];
+                line += R1[Ix * w + (ix - Ix + plow)] * ec[(int64_t(Iz) * n1c + Iy) * n1c + Ix];
             }
             acc += ry * line;
         }
@@ -74,33 +76,33 @@ __device__ __forceinline__ T prolong_value(const T *__restrict__ R1, int p, int 
 }
 
 template <int D, class T>
-__global__ void k_prolong_add(const T *__restrict__ R1, int p, int n1f, int n1c, const T *__restrict__ ec,
+__global__ void k_prolong_add(const T *__restrict__ R1, int p, int plow, int n1f, int n1c, const T *__restrict__ ec,
                               T *__restrict__ uf, const int *__restrict__ skip) {
     if (skip && *skip) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nf = (D == 3) ? int64_t(n1f) * n1f * n1f : int64_t(n1f) * n1f;
     if (i >= nf) return;
     const int ix = int(i % n1f), iy = int((i / n1f) % n1f), iz = (D == 3) ? int(i / (int64_t(n1f) * n1f)) : 0;
-    uf[i] += prolong_value<D, T>(R1, p, n1f, n1c, ec, ix, iy, iz);
+    uf[i] += prolong_value<D, T>(R1, p, plow, n1f, n1c, ec, ix, iy, iz);
 }
 
 // u64 += sigma * (e + P e_c): end of a correction cycle
 template <int D, class T>
-__global__ void k_prolong_update(const T *__restrict__ R1, int p, int n1f, int n1c, const T *__restrict__ ec,
-                                 const T *__restrict__ e, double *__restrict__ u, const double *__restrict__ scal,
-                                 int scaled, const int *__restrict__ skip) {
+__global__ void k_prolong_update(const T *__restrict__ R1, int p, int plow, int n1f, int n1c,
+                                 const T *__restrict__ ec, const T *__restrict__ e, double *__restrict__ u,
+                                 const double *__restrict__ scal, int scaled, const int *__restrict__ skip) {
     const int stop = skip ? *skip : 0;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nf = (D == 3) ? int64_t(n1f) * n1f * n1f : int64_t(n1f) * n1f;
     if (i >= nf) return;
     const int ix = int(i % n1f), iy = int((i / n1f) % n1f), iz = (D == 3) ? int(i / (int64_t(n1f) * n1f)) : 0;
-    const T corr = e[i] + prolong_value<D, T>(R1, p, n1f, n1c, ec, ix, iy, iz);
+    const T corr = e[i] + prolong_value<D, T>(R1, p, plow, n1f, n1c, ec, ix, iy, iz);
     if (stop) return;
     u[i] += scaled ? scal[kScalSigma] * double(corr) : double(corr);
 }
 
 // ----------------------------------------------------------------- DST --
-// out[.., k, ..] = sum_i S[k][i] in[.., i, ..] along one axis (S symmetric);
+// out[.., k, ..] = sum_i S[k][i] in[.., i, ..] along one axis (S row-major);
 // with mu != nullptr the result is divided by mu (diagonal solve).
 __global__ void k_dst_axis(const double *__restrict__ S, int n1, int dim, int axis, const double *__restrict__ in,
                            double *__restrict__ out, const double *__restrict__ mu, const int *__restrict__ skip) {
@@ -330,14 +332,17 @@ const T *R1_of(const Problem &P) {
 }  // namespace
 
 // ------------------------------------------------------------ launchers --
+// 2-D with the degree-1 coarse space: the tiled sum-factorised kernels of
+// kernels_2d.hip; otherwise one thread per output point
 template <class T>
 void launch_restrict(const Problem &P, const T *df, T *dc, hipStream_t s) {
-    if (P.dim == 2) {
+    if (P.dim == 2 && P.plow == 1) {
         launch_restrict2d<T>(P, df, dc, s);
         return;
     }
     const int64_t nc = P.coarse.n;
-    hipLaunchKernelGGL((k_restrict<3, T>), dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
+    auto kern = P.dim == 2 ? k_restrict<2, T> : k_restrict<3, T>;
+    hipLaunchKernelGGL(kern, dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.plow, P.fine.n1,
                        P.coarse.n1, df, dc, P.skip);
 }
 template void launch_restrict<double>(const Problem &, const double *, double *, hipStream_t);
@@ -345,12 +350,13 @@ template void launch_restrict<float>(const Problem &, const float *, float *, hi
 
 template <class T>
 void launch_prolong_add(const Problem &P, const T *ec, T *uf, hipStream_t s) {
-    if (P.dim == 2) {
+    if (P.dim == 2 && P.plow == 1) {
         launch_prolong2d<T>(P, ec, uf, nullptr, nullptr, false, s);
         return;
     }
     const int64_t nf = P.fine.n;
-    hipLaunchKernelGGL((k_prolong_add<3, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.fine.n1,
+    auto kern = P.dim == 2 ? k_prolong_add<2, T> : k_prolong_add<3, T>;
+    hipLaunchKernelGGL(kern, dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.plow, P.fine.n1,
                        P.coarse.n1, ec, uf, P.skip);
 }
 template void launch_prolong_add<double>(const Problem &, const double *, double *, hipStream_t);
@@ -358,13 +364,14 @@ template void launch_prolong_add<float>(const Problem &, const float *, float *,
 
 template <class T>
 void launch_prolong_update(const Problem &P, const T *ec, const T *e, double *u, bool scaled, hipStream_t s) {
-    if (P.dim == 2) {
+    if (P.dim == 2 && P.plow == 1) {
         launch_prolong2d<T>(P, ec, nullptr, e, u, scaled, s);
         return;
     }
     const int64_t nf = P.fine.n;
-    hipLaunchKernelGGL((k_prolong_update<3, T>), dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p,
-                       P.fine.n1, P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0, P.skip);
+    auto kern = P.dim == 2 ? k_prolong_update<2, T> : k_prolong_update<3, T>;
+    hipLaunchKernelGGL(kern, dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.plow, P.fine.n1,
+                       P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0, P.skip);
 }
 template void launch_prolong_update<double>(const Problem &, const double *, const double *, double *, bool,
                                             hipStream_t);
@@ -375,8 +382,10 @@ template void launch_prolong_update<float>(const Problem &, const float *, const
 // points (S symmetric orthogonal): forward transform along every axis,
 // diagonal solve, inverse (= forward) transform.  t1: scratch of n doubles;
 // d may equal t1 only if it is not e.
+// Sb = nullptr: Sb = S (the DST-I is its own inverse); the fast
+// diagonalisation of the degree-2 space passes V^T forward and V backward.
 static void dst_apply(const double *S, const double *mu, int n1, int dim, const double *d, double *e, double *t1,
-                      const int *skip, hipStream_t s) {
+                      const int *skip, hipStream_t s, const double *Sb = nullptr) {
     const int64_t n = (dim == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
     const double *src = d;
     double *bufs[2] = {t1, e};
@@ -388,8 +397,8 @@ static void dst_apply(const double *S, const double *mu, int n1, int dim, const 
         cur = 1 - cur;
     }
     for (int ax = 0; ax < dim; ++ax) {
-        hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, S, n1, dim, ax, src, bufs[cur],
-                           nullptr, skip);
+        hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, Sb ? Sb : S, n1, dim, ax, src,
+                           bufs[cur], nullptr, skip);
         src = bufs[cur];
         cur = 1 - cur;
     }
@@ -403,10 +412,26 @@ void dst_apply_2h(Problem &P, const double *d, double *e, double *t1, hipStream_
 
 void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s) {
     IGA2L_REQUIRE(P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");
-    dst_apply(P.dst_S.as<double>(), P.dst_mu.as<double>(), P.coarse.n1, P.dim, d, e, P.ctmp.as<double>(), P.skip, s);
+    if (P.plow == 2)
+        dst_apply(P.fdm_Vt.as<double>(), P.dst_mu.as<double>(), P.coarse.n1, P.dim, d, e, P.ctmp.as<double>(), P.skip,
+                  s, P.fdm_V.as<double>());
+    else
+        dst_apply(P.dst_S.as<double>(), P.dst_mu.as<double>(), P.coarse.n1, P.dim, d, e, P.ctmp.as<double>(), P.skip,
+                  s);
 }
 
-// x <- M_1^{-1} x (the degree-1 mass matrix, Dirichlet-reduced): FP64 through
+// e = M_low^{-1} d: the DST-I of the degree-1 mass matrix, or the fast
+// diagonalisation of the degree-2 space with unit eigenvalues (M2^{-1} = V V^T
+// per direction)
+static void mass_apply(Problem &P, const double *d, double *e, double *t1, hipStream_t s) {
+    if (P.plow == 2)
+        dst_apply(P.fdm_Vt.as<double>(), P.dstM_mu.as<double>(), P.coarse.n1, P.dim, d, e, t1, P.skip, s,
+                  P.fdm_V.as<double>());
+    else
+        dst_apply(P.dstM_S.as<double>(), P.dstM_mu.as<double>(), P.coarse.n1, P.dim, d, e, t1, P.skip, s);
+}
+
+// x <- M_low^{-1} x (the coarse-space mass matrix, Dirichlet-reduced): FP64 through
 // the DST-I; an FP32 x is widened, solved and narrowed
 template <class T>
 void launch_mass_solve(Problem &P, T *x, hipStream_t s) {
@@ -416,13 +441,11 @@ void launch_mass_solve(Problem &P, T *x, hipStream_t s) {
     if constexpr (std::is_same<T, double>::value) {
         // x -> e through t1: the input must not be the output buffer
         IGA2L_HIP(hipMemcpyAsync(P.ctmp.ptr, x, sizeof(double) * size_t(n), hipMemcpyDeviceToDevice, s));
-        dst_apply(P.dstM_S.as<double>(), P.dstM_mu.as<double>(), P.coarse.n1, P.dim, P.ctmp.as<double>(), x, t1,
-                  P.skip, s);
+        mass_apply(P, P.ctmp.as<double>(), x, t1, s);
     } else {
         IGA2L_REQUIRE(P.dc64.ptr, IGA2L_EINVAL, "FP32 data not set up");
         launch_convert(x, P.ctmp.ptr, n, false, s, P.skip);
-        dst_apply(P.dstM_S.as<double>(), P.dstM_mu.as<double>(), P.coarse.n1, P.dim, P.ctmp.as<double>(),
-                  P.dc64.as<double>(), t1, P.skip, s);
+        mass_apply(P, P.ctmp.as<double>(), P.dc64.as<double>(), t1, s);
         launch_convert(P.dc64.ptr, x, n, true, s, P.skip);
     }
 }

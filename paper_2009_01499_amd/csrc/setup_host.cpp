@@ -143,12 +143,56 @@ inline void split(int64_t idx, int dim, int64_t n, int *out) {
 
 }  // namespace
 
+// ------------------------------------------------------------ transfers --
+// 1-D factors of the transfer between the degree-p space and the degree-plow
+// space on the same knots (Section 3.1.2): Mmix1 = M_p^{plow} by Gauss
+// quadrature, entry (I, j) at [I][j - I + plow], j - I in [-plow, p]; R1 =
+// D1^{-1} Mmix1 with D1 the row sums of the Dirichlet-reduced degree-plow
+// mass matrix (row-sum lumping).  Sets the coarse grid (m + plow - 2 points
+// per direction).
+void host_transfer_factors(Problem &P, int plow) {
+    const int p = P.p, m = P.m, d = P.dim;
+    const int n1 = P.fine.n1, n1c = m + plow - 2, w = p + plow + 1;
+    P.plow = plow;
+    P.coarse = Grid{d, n1c, ipow(n1c, d)};
+    auto tf = open_uniform_knots(p, m), tc = open_uniform_knots(plow, m);
+    double gx[kMaxP + 4], gw[kMaxP + 4];
+    const int q = p + 1;   // exact for the degree p + plow <= 2p integrands
+    gauss_rule(q, gx, gw);
+    const double h = 1.0 / m;
+    std::vector<double> mix(size_t(n1c) * w, 0.0), lump(n1c, 0.0);
+    double v[kMaxP + 1], vc[kMaxP + 1];
+    for (int e = 0; e < m; ++e)
+        for (int k = 0; k < q; ++k) {
+            double x = (e + 0.5 * (gx[k] + 1.0)) * h, wq = 0.5 * h * gw[k];
+            live_values(tf, p, p + e, x, v, nullptr);
+            live_values(tc, plow, plow + e, x, vc, nullptr);
+            for (int c = 0; c <= plow; ++c) {
+                int I = e + c - 1;
+                if (I < 0 || I >= n1c) continue;
+                for (int c2 = 0; c2 <= plow; ++c2) {
+                    int J = e + c2 - 1;
+                    if (J < 0 || J >= n1c) continue;
+                    lump[I] += wq * vc[c] * vc[c2];
+                }
+                for (int a = 0; a <= p; ++a) {
+                    int j = e + a - 1;
+                    if (j < 0 || j >= n1) continue;
+                    mix[size_t(I) * w + (j - I + plow)] += wq * vc[c] * v[a];
+                }
+            }
+        }
+    P.Mx1 = mix;
+    P.R1.assign(mix.size(), 0.0);
+    for (int I = 0; I < n1c; ++I)
+        for (int a = 0; a < w; ++a) P.R1[size_t(I) * w + a] = mix[size_t(I) * w + a] / lump[I];
+}
+
 // ------------------------------------------------------------ assembly --
 void host_assemble(Problem &P) {
     const int p = P.p, m = P.m, d = P.dim;
-    const int n1 = m + p - 2, n1c = m - 1;
+    const int n1 = m + p - 2;
     P.fine = Grid{d, n1, ipow(n1, d)};
-    P.coarse = Grid{d, n1c, ipow(n1c, d)};
     P.ne = ipow(m, d);
 
     element_matrices(p, m, P.Ke, P.Me);
@@ -166,41 +210,7 @@ void host_assemble(Problem &P) {
                 P.M1[size_t(i) * w1 + (j - i + p)] += P.Me[e][a * (p + 1) + b];
             }
 
-    // restriction factor: R1 = D1^{-1} Mmix1 with D1 the row sums of the
-    // Dirichlet-reduced degree-1 mass matrix (row-sum lumping)
-    {
-        auto tf = open_uniform_knots(p, m), tc = open_uniform_knots(1, m);
-        double gx[kMaxP + 4], gw[kMaxP + 4];
-        int q = p + 1;
-        gauss_rule(q, gx, gw);
-        double h = 1.0 / m;
-        std::vector<double> mix(size_t(n1c) * (p + 2), 0.0), lump(n1c, 0.0);
-        double v[kMaxP + 1], vc[2];
-        for (int e = 0; e < m; ++e)
-            for (int k = 0; k < q; ++k) {
-                double x = (e + 0.5 * (gx[k] + 1.0)) * h, wq = 0.5 * h * gw[k];
-                live_values(tf, p, p + e, x, v, nullptr);
-                live_values(tc, 1, 1 + e, x, vc, nullptr);
-                for (int c = 0; c < 2; ++c) {
-                    int I = e + c - 1;
-                    if (I < 0 || I >= n1c) continue;
-                    for (int c2 = 0; c2 < 2; ++c2) {
-                        int J = e + c2 - 1;
-                        if (J < 0 || J >= n1c) continue;
-                        lump[I] += wq * vc[c] * vc[c2];
-                    }
-                    for (int a = 0; a <= p; ++a) {
-                        int j = e + a - 1;
-                        if (j < 0 || j >= n1) continue;
-                        mix[size_t(I) * (p + 2) + (j - I + 1)] += wq * vc[c] * v[a];
-                    }
-                }
-            }
-        P.Mx1 = mix;
-        P.R1.assign(mix.size(), 0.0);
-        for (int I = 0; I < n1c; ++I)
-            for (int a = 0; a < p + 2; ++a) P.R1[size_t(I) * (p + 2) + a] = mix[size_t(I) * (p + 2) + a] / lump[I];
-    }
+    host_transfer_factors(P, 1);
 
     // 1-D element matrices (assembly and gradient kernels): [m][2][(p+1)^2] (K then M)
     const int nl = p + 1;
@@ -337,15 +347,181 @@ void host_assemble(Problem &P) {
     P.rhs_w.alloc(nf * sizeof(double));
     P.dfine.alloc(nf * sizeof(double));
     P.lam_tmp.alloc(nf * sizeof(double));
-    P.dc.alloc(nc * sizeof(double));
-    P.ec.alloc(nc * sizeof(double));
-    P.ctmp.alloc(nc * sizeof(double));
+    (void)nc;
+    host_coarse_workspaces(P);
     P.npartial = int(residual_workgroups(P));
     P.partial.alloc(size_t(P.npartial) * sizeof(double));
     P.hist_cap = 128;
     P.scal.alloc(status_bytes(P.hist_cap));
     IGA2L_HIP(hipMemset(P.scal.ptr, 0, status_bytes(P.hist_cap)));
     IGA2L_HIP(hipHostMalloc(&P.host_status, status_bytes(P.hist_cap), hipHostMallocDefault));
+}
+
+// coarse vectors of the cycle, sized by the coarse grid
+void host_coarse_workspaces(Problem &P) {
+    const size_t nc = size_t(P.coarse.n);
+    P.dc.alloc(nc * sizeof(double));
+    P.ec.alloc(nc * sizeof(double));
+    P.ctmp.alloc(nc * sizeof(double));
+    if (P.fp32_ready) {
+        P.dc64.alloc(nc * sizeof(double));
+        P.ec64.alloc(nc * sizeof(double));
+    }
+}
+
+// Changes the degree of the coarse space (1 or 2): new transfer factors and
+// coarse vectors; every coarse solver and exact-transfer table is dropped
+// (they belong to the previous coarse space) and rebuilt on request.
+void host_set_coarse_degree(Problem &P, int plow) {
+    if (plow == P.plow) return;
+    host_transfer_factors(P, plow);
+    P.R1d64.alloc(P.R1.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.R1d64.ptr, P.R1.data(), P.R1.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (P.fp32_ready) {
+        std::vector<float> f32(P.R1.begin(), P.R1.end());
+        P.R1d32.alloc(f32.size() * sizeof(float));
+        IGA2L_HIP(hipMemcpy(P.R1d32.ptr, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    host_coarse_workspaces(P);
+    P.vcycle_ready = P.direct_ready = P.mass_ready = P.agg_direct_ready = false;
+    P.levels.clear();
+    P.levhost64.clear();
+    P.levhost32.clear();
+    P.ctmp2.free();
+}
+
+// Symmetric eigen-decomposition of the n x n row-major matrix C by cyclic
+// Jacobi rotations: on return C holds the eigenvalues on its diagonal and Q
+// (row-major) the eigenvectors in its columns.
+static void jacobi_eigen(int n, std::vector<double> &C, std::vector<double> &Q) {
+    Q.assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[size_t(i) * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; ++i) {
+            diag += C[size_t(i) * n + i] * C[size_t(i) * n + i];
+            for (int j = i + 1; j < n; ++j) off += C[size_t(i) * n + j] * C[size_t(i) * n + j];
+        }
+        if (off <= 1e-32 * diag) break;
+        for (int pp = 0; pp < n - 1; ++pp)
+            for (int qq = pp + 1; qq < n; ++qq) {
+                const double apq = C[size_t(pp) * n + qq];
+                if (std::fabs(apq) < 1e-300) continue;
+                const double app = C[size_t(pp) * n + pp], aqq = C[size_t(qq) * n + qq];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {   // columns pp, qq
+                    const double ckp = C[size_t(k) * n + pp], ckq = C[size_t(k) * n + qq];
+                    C[size_t(k) * n + pp] = c * ckp - sn * ckq;
+                    C[size_t(k) * n + qq] = sn * ckp + c * ckq;
+                }
+                for (int k = 0; k < n; ++k) {   // rows pp, qq
+                    const double cpk = C[size_t(pp) * n + k], cqk = C[size_t(qq) * n + k];
+                    C[size_t(pp) * n + k] = c * cpk - sn * cqk;
+                    C[size_t(qq) * n + k] = sn * cpk + c * cqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double qkp = Q[size_t(k) * n + pp], qkq = Q[size_t(k) * n + qq];
+                    Q[size_t(k) * n + pp] = c * qkp - sn * qkq;
+                    Q[size_t(k) * n + qq] = sn * qkp + c * qkq;
+                }
+            }
+    }
+}
+
+// Degree-2 coarse space, kappa = 1: the Dirichlet-reduced 1-D stiffness K2
+// and mass M2 (degree 2 on the same knots) give the generalised eigenvectors V
+// with V^T M2 V = I, V^T K2 V = diag(lambda) (M2 = L L^T, C = L^{-1} K2 L^{-T} =
+// Q diag(lambda) Q^T, V = L^{-T} Q).  The d-dimensional coarse operator
+// sum_c (x)_k (k == c ? K2 : M2) is then (V (x) V ..) diag(sum_k lambda_k)
+// (V (x) V ..)^T, inverted by one transform per axis each way ("fast
+// diagonalisation"); M2^{-1} = (V V^T) per direction for the exact transfers.
+void host_build_fdm(Problem &P) {
+    IGA2L_REQUIRE(P.plow == 2, IGA2L_EINVAL, "fast diagonalisation is the coarse solver of the degree-2 space");
+    IGA2L_REQUIRE(P.kappa_one, IGA2L_EUNSUPPORTED, "the exact degree-2 coarse solve needs kappa = 1");
+    const int m = P.m, n = P.coarse.n1, d = P.dim;
+    IGA2L_REQUIRE(n <= 1024, IGA2L_EUNSUPPORTED, "degree-2 coarse space limited to m <= 1024");
+    std::vector<std::vector<double>> Ke, Me;
+    element_matrices(2, m, Ke, Me);
+    std::vector<double> K(size_t(n) * n, 0.0), M(size_t(n) * n, 0.0);
+    for (int e = 0; e < m; ++e)
+        for (int a = 0; a <= 2; ++a)
+            for (int b = 0; b <= 2; ++b) {
+                const int i = e + a - 1, j = e + b - 1;
+                if (i < 0 || i >= n || j < 0 || j >= n) continue;
+                K[size_t(i) * n + j] += Ke[e][a * 3 + b];
+                M[size_t(i) * n + j] += Me[e][a * 3 + b];
+            }
+    // M = L L^T (dense Cholesky, lower)
+    std::vector<double> L(M);
+    for (int j = 0; j < n; ++j) {
+        double s = L[size_t(j) * n + j];
+        for (int k = 0; k < j; ++k) s -= L[size_t(j) * n + k] * L[size_t(j) * n + k];
+        IGA2L_REQUIRE(s > 0.0, IGA2L_ENUMERIC, "degree-2 mass matrix not positive definite");
+        const double ljj = std::sqrt(s);
+        L[size_t(j) * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = L[size_t(i) * n + j];
+            for (int k = 0; k < j; ++k) t -= L[size_t(i) * n + k] * L[size_t(j) * n + k];
+            L[size_t(i) * n + j] = t / ljj;
+        }
+        for (int k = j + 1; k < n; ++k) L[size_t(j) * n + k] = 0.0;
+    }
+    // C = L^{-1} K L^{-T}: solve L X = K, then C^T: L C^T = X^T (C symmetric)
+    auto lower_solve = [&](std::vector<double> &B) {   // B <- L^{-1} B, column by column
+        for (int c = 0; c < n; ++c)
+            for (int i = 0; i < n; ++i) {
+                double t = B[size_t(i) * n + c];
+                for (int k = 0; k < i; ++k) t -= L[size_t(i) * n + k] * B[size_t(k) * n + c];
+                B[size_t(i) * n + c] = t / L[size_t(i) * n + i];
+            }
+    };
+    std::vector<double> X(K);
+    lower_solve(X);
+    std::vector<double> C(size_t(n) * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) C[size_t(i) * n + j] = X[size_t(j) * n + i];
+    lower_solve(C);
+    for (int i = 0; i < n; ++i)           // symmetrise the rounding
+        for (int j = i + 1; j < n; ++j) {
+            const double a = 0.5 * (C[size_t(i) * n + j] + C[size_t(j) * n + i]);
+            C[size_t(i) * n + j] = C[size_t(j) * n + i] = a;
+        }
+    std::vector<double> Q;
+    jacobi_eigen(n, C, Q);
+    std::vector<double> lam(n);
+    for (int i = 0; i < n; ++i) lam[i] = C[size_t(i) * n + i];
+    // V = L^{-T} Q: back substitution with L^T, column by column
+    std::vector<double> V(Q);
+    for (int c = 0; c < n; ++c)
+        for (int i = n - 1; i >= 0; --i) {
+            double t = V[size_t(i) * n + c];
+            for (int k = i + 1; k < n; ++k) t -= L[size_t(k) * n + i] * V[size_t(k) * n + c];
+            V[size_t(i) * n + c] = t / L[size_t(i) * n + i];
+        }
+    // forward transform matrix V^T (row k = column k of V), backward V
+    std::vector<double> Vt(size_t(n) * n);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) Vt[size_t(k) * n + i] = V[size_t(i) * n + k];
+    const int64_t nc = ipow(n, d);
+    std::vector<double> mu(nc), ones(nc, 1.0);
+    int ix[kMaxDim] = {0, 0, 0};
+    for (int64_t i = 0; i < nc; ++i) {
+        split(i, d, n, ix);
+        double sl = 0.0;
+        for (int k = 0; k < d; ++k) sl += lam[ix[k]];
+        mu[i] = sl;
+    }
+    P.fdm_Vt.alloc(Vt.size() * sizeof(double));
+    P.fdm_V.alloc(V.size() * sizeof(double));
+    P.dst_mu.alloc(mu.size() * sizeof(double));
+    P.dstM_mu.alloc(ones.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.fdm_Vt.ptr, Vt.data(), Vt.size() * sizeof(double), hipMemcpyHostToDevice));
+    IGA2L_HIP(hipMemcpy(P.fdm_V.ptr, V.data(), V.size() * sizeof(double), hipMemcpyHostToDevice));
+    IGA2L_HIP(hipMemcpy(P.dst_mu.ptr, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice));
+    IGA2L_HIP(hipMemcpy(P.dstM_mu.ptr, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
+    P.direct_ready = true;
 }
 
 // ---------------------------------------------------- V-cycle hierarchy --
@@ -592,6 +768,10 @@ static void dst_tables(int m, int d, bool stiffness, DevBuf &Sd, DevBuf &mud) {
 }
 
 void host_build_dst(Problem &P) {
+    if (P.plow == 2) {
+        host_build_fdm(P);
+        return;
+    }
     dst_tables(P.m, P.dim, true, P.dst_S, P.dst_mu);
     P.direct_ready = true;
 }
@@ -599,7 +779,12 @@ void host_build_dst(Problem &P) {
 // exact transfers (Section 3.1.2 without lumping): the unlumped factor and
 // the DST-I of the degree-1 mass matrix
 void host_build_mass(Problem &P) {
-    dst_tables(P.m, P.dim, false, P.dstM_S, P.dstM_mu);
+    if (P.plow == 2) {
+        // M2^{-1} = (V V^T) per direction: the fast-diagonalisation tables with unit eigenvalues
+        if (!P.direct_ready) host_build_fdm(P);
+    } else {
+        dst_tables(P.m, P.dim, false, P.dstM_S, P.dstM_mu);
+    }
     P.Mx64.alloc(P.Mx1.size() * sizeof(double));
     IGA2L_HIP(hipMemcpy(P.Mx64.ptr, P.Mx1.data(), P.Mx1.size() * sizeof(double), hipMemcpyHostToDevice));
     std::vector<float> f32(P.Mx1.begin(), P.Mx1.end());

@@ -38,14 +38,14 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def _pair(d, p, m, kappa=None, bw=0, vcycle=True, direct=True, mixed=False, lumped=1, aggressive=0):
+def _pair(d, p, m, kappa=None, bw=0, vcycle=True, direct=True, mixed=False, lumped=1, aggressive=0, plow=1):
     G = _gpu()
     print(f"\n[case] d={d} p={p} m={m} kappa={'grf' if kappa is not None else 1} bw={bw} lumped={lumped} "
-          f"aggressive={aggressive}", flush=True)
+          f"aggressive={aggressive} plow={plow}", flush=True)
     orc = O.Problem(d, p, m, kappa=kappa, block_width=bw, coarse_direct=direct and not aggressive,
-                    vcycle=vcycle or bool(aggressive), lumped=bool(lumped))
+                    vcycle=vcycle or bool(aggressive), lumped=bool(lumped), plow=plow)
     gp = G.Problem(d, p, m, kappa=kappa)
-    extra = dict(precision=G.MIXED_FP32 if mixed else G.FP64, lumped=lumped, aggressive=aggressive)
+    extra = dict(precision=G.MIXED_FP32 if mixed else G.FP64, lumped=lumped, aggressive=aggressive, plow=plow)
     if vcycle:
         gp.setup(bw, G.Opts(coarse=G.COARSE_VCYCLE, **extra))
     if direct and kappa is None:
@@ -186,6 +186,27 @@ def test_exact_transfer_parity(d, p, m):
     assert e < 1e-13, e
 
 
+@pytest.mark.parametrize("d,p,m,lumped", [(2, 3, 16, 1), (2, 4, 13, 0), (2, 2, 10, 1), (3, 3, 6, 1), (3, 2, 5, 0)])
+def test_degree2_transfer_and_coarse_parity(d, p, m, lumped):
+    """Degree-2 coarse space (plow = 2): restriction, prolongation (lumped and
+    exact projection) and the exact coarse solve (fast diagonalisation of the
+    1-D degree-2 matrices on the GPU, banded Cholesky in the oracle)."""
+    G, orc, gp = _pair(d, p, m, vcycle=False, direct=True, lumped=lumped, plow=2)
+    assert gp.nc == orc.nc == m ** d
+    x = synth.rhs_normal(d, p, m, seed=3)
+    xc = synth.rhs_normal(d, 2, m, seed=4)
+    e = rel(host(gp.restrict(dev(x))), orc.restrict(x))
+    assert e < 1e-13, e
+    u0 = synth.initial_guess(d, p, m, seed=5)
+    ug = dev(u0)
+    gp.prolong_add(dev(xc), ug)
+    e = rel(host(ug) - u0, orc.prolong_add(xc, u0) - u0)
+    assert e < 1e-13, e
+    ec = host(gp.coarse_solve(dev(xc), opts=G.Opts(coarse=G.COARSE_DIRECT, plow=2, lumped=lumped)))
+    e = rel(ec, orc.coarse_direct(xc))
+    assert e < 1e-12, e
+
+
 @pytest.mark.parametrize("d,m,coarse,nu", [(2, 32, "vcycle", (1, 1)), (2, 32, "direct", (1, 1)),
                                            (2, 128, "vcycle", (2, 2)), (2, 64, "direct", (1, 1)),
                                            (3, 12, "vcycle", (1, 1)), (3, 16, "direct", (1, 1))])
@@ -199,6 +220,46 @@ def test_coarse_aggressive_parity(d, m, coarse, nu):
     ref = orc.coarse_aggressive(dc, coarse=O.VCYCLE if coarse == "vcycle" else O.DIRECT, nu1=nu[0], nu2=nu[1])
     e = rel(ec, ref)
     assert e < 1e-12, e
+
+
+@pytest.mark.parametrize("name,d,p,m,ordering,lumped", [
+    ("plow2-colour", 2, 3, 24, "colour", 1), ("plow2-exact-mass", 2, 4, 20, "colour", 0),
+    ("plow2-lex", 2, 2, 16, "lex", 1), ("plow2-3d", 3, 3, 8, "colour", 1)])
+def test_cycle_iterates_parity_degree2(name, d, p, m, ordering, lumped):
+    """Per-iterate FP64 parity of the cycle with the degree-2 coarse space."""
+    G, orc, gp = _pair(d, p, m, vcycle=False, direct=True, lumped=lumped, plow=2)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    u0 = synth.initial_guess(d, p, m, seed=11)
+    gopts = G.Opts(ordering=G.LEX if ordering == "lex" else G.COLOUR, coarse=G.COARSE_DIRECT, lumped=lumped,
+                   plow=2)
+    its = _iterates_gpu(G, gp, b, u0, gopts, 3)
+    u = u0.copy()
+    for k in range(3):
+        u = orc.cycle(u, b, ordering=O.LEX if ordering == "lex" else O.COLOUR, coarse=O.DIRECT)
+        e = rel(its[k], u)
+        assert e < 1e-12, (name, k, e)
+
+
+def test_degree2_mixed_and_switch_back():
+    """Mixed precision with the degree-2 coarse space reaches 1e-10 within
+    cond(A) times its relative residual of the direct solution; setting the
+    problem up again with plow = 1 restores the degree-1 coarse space (sizes
+    and results of the first set-up)."""
+    d, p, m = 2, 3, 48
+    G, orc, gp = _pair(d, p, m, vcycle=False, direct=True, mixed=True, plow=2)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    u_star = orc.direct_solve(b)
+    u32, i32 = gp.solve(dev(b), opts=G.Opts(coarse=G.COARSE_DIRECT, precision=G.MIXED_FP32, plow=2))
+    e32 = rel(host(u32), u_star)
+    kappa_A = _cond_A(orc, d)
+    print(f"[degree-2 mixed] cycles={i32.iters} relres={i32.relres:.2e} err={e32:.2e}")
+    assert i32.relres <= 1e-10 and e32 <= kappa_A * i32.relres
+    gp.setup(0, G.Opts(coarse=G.COARSE_DIRECT))
+    assert gp.nc == (m - 1) ** d
+    orc1 = O.Problem(d, p, m)
+    u1, i1 = gp.solve(dev(b), opts=G.Opts(coarse=G.COARSE_DIRECT))
+    ur, kr, _ = orc1.solve(b, coarse=O.DIRECT, tol=1e-10)
+    assert i1.iters == kr and rel(host(u1), ur) < 1e-12
 
 
 @pytest.mark.parametrize("name,d,p,m,kap,ordering,period,coarse,nu,lumped,aggr", [

@@ -346,6 +346,57 @@ def test_mixed_mass_polynomial_reproduction(p):
                            atol=1e-14 * np.abs(want).max() ** 2), (p, k)
 
 
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_mixed_mass_degree2_polynomial_reproduction(p):
+    """Every row of M_p^2 (the degree-2 coarse space of Section 5): for a
+    polynomial g of degree <= p vanishing at 0 and 1, M_p^2 c = (phi_I^2, g)
+    with c its interior degree-p B-spline coefficients; the degree-2 basis
+    functions and the integrals come from scipy's B-spline elements and Gauss
+    rules on every element."""
+    from scipy.interpolate import BSpline, make_interp_spline
+    m = 8
+    t = np.r_[np.zeros(p + 1), np.arange(1, m) / m, np.ones(p + 1)]
+    tau = np.array([t[i + 1:i + p + 1].mean() for i in range(m + p)])
+    t2 = np.r_[np.zeros(3), np.arange(1, m) / m, np.ones(3)]
+    xg, wg = np.polynomial.legendre.leggauss(p + 4)
+    M2 = O.mix_to_dense(O.assemble_mix(1, p, 2, m), 1, p, 2, m)
+    assert M2.shape == (m, m + p - 2)
+    for k in range(p - 1):
+        def g(x, k=k):
+            return x * (1.0 - x) * (x - 0.3) ** k
+        c = make_interp_spline(tau, g(tau), k=p, t=t).c[1:-1]
+        want = np.zeros(m)
+        for I in range(m):                       # interior degree-2 function I = full index I + 1
+            phi = BSpline.basis_element(t2[I + 1:I + 5], extrapolate=False)
+            for e in range(m):
+                a, b = e / m, (e + 1) / m
+                x = 0.5 * (b - a) * xg + 0.5 * (a + b)
+                want[I] += 0.5 * (b - a) * np.sum(wg * np.nan_to_num(phi(x)) * g(x))
+        assert np.allclose(M2 @ c, want, rtol=0, atol=1e-14 * np.abs(want).max()), (p, k)
+
+
+@pytest.mark.parametrize("lumped", [True, False])
+def test_degree2_coarse_cycle_dense(lumped):
+    """The two-level cycle with the degree-2 coarse space (plow = 2, exact
+    coarse solve): after the sweep, u1 = u_s + R^T A_2^{-1} R (b - A u_s) with
+    R = D^{-1} M_p^2 (lumped: row sums of the degree-2 mass matrix) or
+    M_2^{-1} M_p^2, built densely from the oracle's assembled matrices."""
+    d, p, m = 2, 3, 6
+    P = O.Problem(d, p, m, plow=2, lumped=lumped)
+    A = O.offsets_to_dense(P.A(), d, P.n1, p)
+    A2 = O.offsets_to_dense(P.Alow(), d, P.n1c, 2)
+    M2 = O.offsets_to_dense(P.Mlow(), d, P.n1c, 2)
+    Mmix = O.mix_to_dense(P.Mmix(), d, p, 2, m)
+    assert np.allclose(P.Dlump(), M2.sum(axis=1), atol=1e-15)
+    R = Mmix / P.Dlump()[:, None] if lumped else np.linalg.solve(M2, Mmix)
+    b = synth.rhs_normal(d, p, m, seed=41)
+    u0 = synth.initial_guess(d, p, m, seed=42)
+    us = P.sweep(u0, b, ordering=O.COLOUR)
+    ref = us + R.T @ np.linalg.solve(A2, R @ (b - A @ us))
+    got = P.cycle(u0, b, ordering=O.COLOUR, coarse=O.DIRECT)
+    assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
 def test_seven_by_seven_sweep_sensitivity():
     """The 7x7-block sweep (p = 7) of the oracle against the same sweep carried
     out in extended precision (numpy longdouble, Gaussian elimination) on the
