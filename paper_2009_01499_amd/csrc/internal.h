@@ -185,6 +185,8 @@ struct Problem {
     int expected_cycles = 8;      // cycles of the last solve: size of the first batch
     DevBuf cs64, cs32;            // interior stencil of kappa = 1 rows, (2p+1)^d (empty otherwise)
     DevBuf kron64, kron32;        // kappa = 1, 3-D: K1 then M1, [n1][2p+1] each (empty otherwise)
+    DevBuf cf64, cf32;            // kappa = 1: interior row of K1 then of M1, 2 (2p+1) (empty otherwise)
+    DevBuf fac64, fac32;          // kappa = 1, 2-D: K1 then M1, [n1][2p+1] each (empty otherwise)
     int ulo = 1, uhi = 0;         // rows with all coordinates in [ulo, uhi] carry that stencil
     DevBuf scal;                  // status block: kScalCount doubles, kFlagCount ints, hist_cap doubles
     DevBuf lam_tmp;               // adjoint workspace

@@ -4,6 +4,8 @@
 // value needs p+2 taps per direction instead of (p+2)^2 gathers).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "internal.h"
@@ -22,26 +24,94 @@ inline unsigned nblk(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
 
 // ------------------------------------------------------------------------
-// r = b - A x on tiles of 64 x (4*RY) points.  Each thread owns a column of
-// RY consecutive points (x fixed); the LDS rows it needs are read once into
-// registers and reused by every output of the column they touch.  Columns
-// whose rows all carry the interior stencil (kappa = 1) take it from cs; the
-// others read the diagonals of the symmetric padded-diagonal operator.
-constexpr int kResTX = 64, kResTYT = 4, kResRY = 8;
+// shared pieces of the 2-D residual kernels
+constexpr int kResTX = 64, kResTYT = 4, kResRY = 8, kResCH = kResTYT * kResRY, kResRing = 64;
+constexpr int kResTargetGroups = 1024;  // four resident workgroups per CU
+
+// the workgroup's sum of rr (a fixed order: wavefront reductions, then the
+// wavefronts in turn), written by thread 0
+template <int NT>
+__device__ __forceinline__ void block_partial(double rr, double *out) {
+    __shared__ double red[NT / 64];
+    for (int off = 32; off > 0; off >>= 1) rr += __shfl_down(rr, off, 64);
+    if ((threadIdx.x % 64) == 0) red[threadIdx.x / 64] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < NT / 64; ++k) s += red[k];
+        *out = s;
+    }
+}
+
+// r = b - A x at frame point f (kappa = 1): the points with a coordinate
+// outside [ulo, uhi], numbered by the bands above and below the interior rows
+// (whole grid rows), then by the rows in between (their ulo + (n1-1-uhi)
+// outer columns).  The row of A is K1 (x) M1 + M1 (x) K1 of the point's own
+// 1-D rows (fac: K1 then M1, [n1][2P+1] each), applied by sum factorisation
+// like the interior stencil; entries that would leave the grid are zero in
+// the 1-D rows.
+template <int P, class T>
+__device__ __forceinline__ void residual_frame_point(const T *__restrict__ fac, int n1, int ulo, int uhi, int64_t f,
+                                                     const T *__restrict__ x, const T *__restrict__ b,
+                                                     T *__restrict__ r, double &rr) {
+    constexpr int W1 = 2 * P + 1;
+    const int L = ulo, R = n1 - 1 - uhi, LR = L + R;
+    const int64_t nband = int64_t(LR) * n1, nf = nband + int64_t(uhi - ulo + 1) * LR;
+    if (f >= nf) return;
+    int gx, gy;
+    if (f < nband) {
+        const int row = int(f / n1);
+        gx = int(f % n1);
+        gy = row < L ? row : uhi + 1 + (row - L);
+    } else {
+        const int64_t g = f - nband;
+        const int c = int(g % LR);
+        gy = ulo + int(g / LR);
+        gx = c < L ? c : uhi + 1 + (c - L);
+    }
+    const T *K = fac, *M = fac + int64_t(n1) * W1;
+    const T *Kx = K + int64_t(gx) * W1, *Mx = M + int64_t(gx) * W1;
+    const T *Ky = K + int64_t(gy) * W1, *My = M + int64_t(gy) * W1;
+    T acc = T(0);
+#pragma unroll
+    for (int oy = 0; oy < W1; ++oy) {
+        const int jy = min(max(gy + oy - P, 0), n1 - 1);
+        T mx = T(0), kx = T(0);
+#pragma unroll
+        for (int ox = 0; ox < W1; ++ox) {
+            const int jx = min(max(gx + ox - P, 0), n1 - 1);
+            // clamped reads: the factor entry of a neighbour outside the grid is zero
+            const T v = x[int64_t(jy) * n1 + jx];
+            kx += Kx[ox] * v;
+            mx += Mx[ox] * v;
+        }
+        acc += Ky[oy] * mx + My[oy] * kx;
+    }
+    const int64_t gi = int64_t(gy) * n1 + gx;
+    const T res = b[gi] - acc;
+    r[gi] = res;
+    rr = double(res) * double(res);
+}
+
+// ------------------------------------------------------------------------
+// r = b - A x for a variable coefficient, on tiles of 64 x (4*RY) points.
+// Each thread owns a column of RY consecutive points (x fixed); the LDS rows
+// it needs are read once into registers and reused by every output of the
+// column they touch, and the (2P+1)^2 diagonals of each output are read with
+// all their loads in flight together.
 
 template <int P, class T, bool NORM>
-__global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d(const T *__restrict__ val, int64_t npad, int pitch1,
+__global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d_tiled(const T *__restrict__ val, int64_t npad, int pitch1,
                                                                 int n1, const T *__restrict__ x,
                                                                 const T *__restrict__ b, T *__restrict__ r,
                                                                 double *__restrict__ partial,
-                                                                const T *__restrict__ cs, int ulo, int uhi,
                                                                 const int *__restrict__ skip) {
     constexpr int TX = kResTX, TY = kResTYT * kResRY, RY = kResRY;
     constexpr int HX = TX + 2 * P, HY = TY + 2 * P;
     constexpr int W1 = 2 * P + 1, W = W1 * W1, C0 = (W - 1) / 2;
     constexpr int NT = kResTX * kResTYT;
     __shared__ T xs[HX * HY];
-    const int stop = skip ? *skip : 0;
+    if (skip && *skip) return;
     int bx, by;
     xcd_tile_2d(bx, by);
     const int gx0 = bx * TX, gy0 = by * TY;
@@ -54,29 +124,10 @@ __global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d(const T *__restr
         return (hgx >= 0 && hgx < n1 && hgy >= 0 && hgy < n1) ? x[int64_t(hgy) * n1 + hgx] : T(0);
     });
     __syncthreads();
-    // per column: the interior stencil when all its rows carry it (columns next
-    // to the grid boundary read the operator; a wavefront holds one row band)
-    const bool uni = cs != nullptr && gx >= ulo && gx <= uhi && gyb >= ulo && min(gyb + RY, n1) - 1 <= uhi;
     T acc[RY];
 #pragma unroll
     for (int k = 0; k < RY; ++k) acc[k] = T(0);
-    if (uni) {
-        // row yy of the column window (0 .. RY+2P-1) feeds output k with oy = yy - P - k
-#pragma unroll
-        for (int yy = 0; yy < RY + 2 * P; ++yy) {
-            T v[W1];
-#pragma unroll
-            for (int ox = 0; ox < W1; ++ox) v[ox] = xs[(ty * RY + yy) * HX + tx + ox];
-#pragma unroll
-            for (int k = 0; k < RY; ++k) {
-                const int oy = yy - k;  // 0 .. 2P when the row touches output k
-                if (oy >= 0 && oy < W1) {
-#pragma unroll
-                    for (int ox = 0; ox < W1; ++ox) acc[k] += cs[oy * W1 + ox] * v[ox];
-                }
-            }
-        }
-    } else if (gx < n1) {
+    if (gx < n1) {
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             const int gy = gyb + k;
@@ -93,7 +144,6 @@ __global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d(const T *__restr
                 }
         }
     }
-    if (stop) return;
     double rr = 0.0;
     if (gx < n1) {
 #pragma unroll
@@ -120,6 +170,180 @@ __global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d(const T *__restr
     }
 }
 
+
+// ------------------------------------------------------------------------
+// r = b - A x for kappa = 1, streamed.  Points whose coordinates all lie in
+// [ulo, uhi] carry the interior stencil, K1 (x) M1 + M1 (x) K1 of the interior
+// 1-D rows cf (K1 then M1), applied by sum factorisation (per window row the x
+// sums of both factors, then the y taps).  A workgroup owns a strip of 64
+// columns over a segment of rows and walks down it in chunks of 32 rows; a
+// thread owns a column of RY consecutive points of the chunk.  The x window
+// lives in an LDS ring of 64 rows, so the 2P halo rows shared by consecutive
+// chunks are read from memory once, and the rows of the next chunk (and its
+// right-hand side) are loaded into registers while the current chunk
+// computes, which keeps memory requests in flight through the arithmetic.
+// The first workgroups of the grid instead take the frame of points within
+// ulo of the boundary, one point per thread, from the 1-D rows of the factors.
+
+template <int P, class T, bool NORM>
+__global__ void __launch_bounds__(kResTX *kResTYT, (sizeof(T) == 8 && P == 8) ? 3 : 4)
+    k_residual2d(const T *__restrict__ fac, int n1, int nframe_groups, int nsx, int nseg, int seg_rows,
+                 const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ r, double *__restrict__ partial,
+                 const T *__restrict__ cf, int ulo, int uhi, const int *__restrict__ skip) {
+    constexpr int TX = kResTX, CH = kResCH, RY = kResRY, RING = kResRing;
+    constexpr int HX = TX + 2 * P;
+    constexpr int W1 = 2 * P + 1, NT = kResTX * kResTYT;
+    static_assert(CH + 2 * P <= RING && (RING & (RING - 1)) == 0, "ring: a power of two holding the window");
+    __shared__ T ring[RING * HX];
+    if (skip && *skip) return;
+    const int id = int(blockIdx.x);
+    const int tid = int(threadIdx.x);
+    double rr = 0.0;
+    if (id < nframe_groups) {
+        residual_frame_point<P, T>(fac, n1, ulo, uhi, int64_t(id) * NT + tid, x, b, r, rr);
+        if constexpr (NORM) block_partial<NT>(rr, partial + id);
+        return;
+    }
+    // nframe_groups is a multiple of the XCD count: strip workgroups keep the
+    // XCD-banded tile order of a grid of their own
+    int bx, bs;
+    xcd_relabel(id - nframe_groups, nsx, nsx * nseg, bx, bs);
+    const int gx0 = bx * TX, y0 = bs * seg_rows;
+    const int y1 = min(y0 + seg_rows, n1);
+    const int nch = (y1 - y0 + CH - 1) / CH;
+    const int tx = tid % TX, ty = tid / TX;
+    const int gx = gx0 + tx;
+    // window row q (0-based from global row y0 - P) sits in ring slot q % RING,
+    // window column hx at global column gx0 - P + hx
+    // the 2P rows above the first chunk
+    stage_lds<(2 * P * HX + NT - 1) / NT>(ring, 2 * P * HX, [&](int h) {
+        const int hgx = gx0 + h % HX - P, hgy = y0 - P + h / HX;
+        return (hgx >= 0 && hgx < n1 && hgy >= 0 && hgy < n1) ? x[int64_t(hgy) * n1 + hgx] : T(0);
+    });
+    // rows 2P .. CH+2P-1 of chunk c's window are new (global rows y0 + c CH + P + j):
+    // the 64 columns of the strip, row ty + 4u for thread (tx, ty), and the 2P
+    // halo columns, thread t taking row t % CH of halo column t / CH.  Loads
+    // read clamped addresses, unpredicated; positions outside the grid are
+    // zeroed where the values enter the ring, so no instruction consumes a
+    // loaded value before the chunk's arithmetic is done.
+    constexpr int NI = CH / kResTYT, NH = (2 * P * CH + NT - 1) / NT;
+    const int gxc = min(gx, n1 - 1);
+    T xi[NI], xh[NH];
+    auto halo_col = [&](int hc) { return hc < P ? gx0 - P + hc : gx0 + TX - P + hc; };
+    auto prefetch = [&](int c) {
+        const int ybase = y0 + c * CH + P;
+#pragma unroll
+        for (int u = 0; u < NI; ++u) xi[u] = x[int64_t(min(ybase + ty + kResTYT * u, n1 - 1)) * n1 + gxc];
+#pragma unroll
+        for (int u = 0; u < NH; ++u) {
+            const int t = tid + u * NT;
+            const int gxh = halo_col(t / CH);
+            xh[u] = x[int64_t(min(ybase + t % CH, n1 - 1)) * n1 + min(max(gxh, 0), n1 - 1)];
+        }
+    };
+    auto store_ring = [&](int c) {
+        const int q = c * CH + 2 * P, ybase = y0 + c * CH + P;
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int j = ty + kResTYT * u;
+            ring[((q + j) & (RING - 1)) * HX + P + tx] = (gx < n1 && ybase + j < n1) ? xi[u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NH; ++u) {
+            const int t = tid + u * NT, j = t % CH, hc = t / CH;
+            const int gxh = halo_col(hc);
+            if (t < 2 * P * CH)
+                ring[((q + j) & (RING - 1)) * HX + (hc < P ? hc : TX + hc)] =
+                    (gxh >= 0 && gxh < n1 && ybase + j < n1) ? xh[u] : T(0);
+        }
+    };
+    // the right-hand side of the column (read where the output exists only)
+    T bv[RY], bn[RY];
+    auto prefetch_b = [&](int c, T *dst) {
+#pragma unroll
+        for (int k = 0; k < RY; ++k) dst[k] = b[int64_t(min(y0 + c * CH + ty * RY + k, n1 - 1)) * n1 + gxc];
+    };
+    prefetch_b(0, bv);
+    prefetch(0);
+    store_ring(0);
+    __syncthreads();
+    const bool col_in = gx >= ulo && gx <= uhi;
+    // per chunk: issue the next chunk's loads (right-hand side first), compute
+    // from the ring, move the loaded rows in once every wavefront is done with
+    // the ring, and only then store the results.  Each wait is on loads issued
+    // before the arithmetic, and every store is older than the loads waited
+    // on next, so neither the stores nor the next loads stall a chunk.
+    for (int c = 0; c < nch; ++c) {
+        const bool more = c + 1 < nch;
+        if (more) {
+            prefetch_b(c + 1, bn);
+            prefetch(c + 1);
+        }
+        const int gyb = y0 + c * CH + ty * RY;
+        const int q0 = c * CH + ty * RY;  // window row of the column's first point, minus P
+        T acc[RY];
+#pragma unroll
+        for (int k = 0; k < RY; ++k) acc[k] = T(0);
+        // (threads whose rows all lie past the segment have nothing to compute;
+        // keeping the arithmetic under this chunk-dependent test also keeps
+        // the compiler from holding the whole unrolled window in registers)
+        if (gyb < y1) {
+            // row yy of the column window (0 .. RY+2P-1) feeds output k with oy = yy - k
+#pragma unroll
+            for (int yy = 0; yy < RY + 2 * P; ++yy) {
+                const T *row = ring + ((q0 + yy) & (RING - 1)) * HX + tx;
+                T mx = T(0), kx = T(0);
+#pragma unroll
+                for (int ox = 0; ox < W1; ++ox) {
+                    const T v = row[ox];
+                    kx += cf[ox] * v;
+                    mx += cf[W1 + ox] * v;
+                }
+#pragma unroll
+                for (int k = 0; k < RY; ++k) {
+                    const int oy = yy - k;
+                    if (oy >= 0 && oy < W1) acc[k] += cf[oy] * mx + cf[W1 + oy] * kx;
+                }
+            }
+        }
+        if (more) {
+            __syncthreads();  // the next chunk's rows overwrite slots this one read
+            store_ring(c + 1);
+            __syncthreads();
+        }
+        if (col_in) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                const int gy = gyb + k;
+                if (gy < y1 && gy >= ulo && gy <= uhi) {
+                    const T res = bv[k] - acc[k];
+                    r[int64_t(gy) * n1 + gx] = res;
+                    rr += double(res) * double(res);
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k) bv[k] = bn[k];
+        }
+    }
+    if constexpr (NORM) block_partial<NT>(rr, partial + id);
+}
+
+// rows per segment of the streamed residual: whole chunks, as many segments
+// as bring the launch to about kResTargetGroups workgroups (the environment
+// variable IGA2L_RESIDUAL_GROUPS sets another target: tests use a small one
+// to send many chunks through each ring)
+int residual2d_segment_rows(int64_t n1) {
+    int64_t target = kResTargetGroups;
+    if (const char *e = std::getenv("IGA2L_RESIDUAL_GROUPS")) target = std::max(1L, std::atol(e));
+    const int64_t nsx = (n1 + kResTX - 1) / kResTX;
+    const int64_t nch = (n1 + kResCH - 1) / kResCH;
+    const int64_t want = std::max<int64_t>(1, target / nsx);
+    const int64_t per = (nch + want - 1) / want;
+    return int(per * kResCH);
+}
+
 // ------------------------------------------------------------------------
 // d_c = (R1 (x) R1) d on tiles of CX x CY coarse points.  Coarse I uses fine
 // I-1 .. I+p per direction.  Pass 1 (x): t[row][I] for every fine row of the
@@ -140,11 +364,13 @@ __device__ __forceinline__ void restrict2d_body(const T *__restrict__ R1, int p,
     T *ry = rx + CX * w;                                 // [CY][w]
     const int stop = skip ? *skip : 0;
     const int I0 = bx * CX, J0 = by * CY;
-    for (int h = threadIdx.x; h < FX * FY; h += blockDim.x) {
+    // the fine window in one memory round trip (at most 8 loads per thread:
+    // 64 x 16 coarse tiles of p <= 8 with 256 threads)
+    stage_lds<8>(ds, FX * FY, [&](int h) {
         const int hx = h % FX, hy = h / FX;
         const int jx = I0 - 1 + hx, jy = J0 - 1 + hy;
-        ds[h] = (jx >= 0 && jx < n1f && jy >= 0 && jy < n1f) ? df[int64_t(jy) * n1f + jx] : T(0);
-    }
+        return (jx >= 0 && jx < n1f && jy >= 0 && jy < n1f) ? df[int64_t(jy) * n1f + jx] : T(0);
+    });
     for (int h = threadIdx.x; h < CX * w; h += blockDim.x) {
         const int I = I0 + h / w;
         rx[h] = (I < n1c) ? R1[int64_t(I) * w + h % w] : T(0);
@@ -201,7 +427,7 @@ __device__ __forceinline__ void prolong2d_body(const T *__restrict__ R1, int p, 
     T *ry = rx + KX * w;                           // [KY][w]
     const int stop = skip ? *skip : 0;
     const int i0 = bx * TX, j0 = by * TY;
-    stage_lds<4>(es, KX * KY, [&](int h) {
+    stage_lds<8>(es, KX * KY, [&](int h) {
         const int hx = h % KX, hy = h / KX;
         const int Ix = i0 - p + hx, Iy = j0 - p + hy;
         return (Ix >= 0 && Ix < n1c && Iy >= 0 && Iy < n1c) ? ec[int64_t(Iy) * n1c + Ix] : T(0);
@@ -325,17 +551,45 @@ const T *R1_of(const Problem &P) {
 }
 
 template <class T>
-const T *cs_of(const Problem &P) {
-    return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.cs64.ptr)
-                                          : reinterpret_cast<const T *>(P.cs32.ptr);
+const T *fac_of(const Problem &P) {
+    return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.fac64.ptr)
+                                          : reinterpret_cast<const T *>(P.fac32.ptr);
+}
+
+template <class T>
+const T *cf_of(const Problem &P) {
+    return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.cf64.ptr)
+                                          : reinterpret_cast<const T *>(P.cf32.ptr);
+}
+
+// frame workgroups of the streamed residual: enough for the frame's points,
+// rounded up to a multiple of the XCD count
+int64_t residual2d_frame_groups(const Problem &Pb) {
+    const int64_t n1 = Pb.fine.n1, lr = Pb.ulo + (n1 - 1 - Pb.uhi);
+    const int64_t nf = lr * n1 + (Pb.uhi - Pb.ulo + 1) * lr;
+    const int64_t g = (nf + kResTX * kResTYT - 1) / (kResTX * kResTYT);
+    return (g + kNumXcd - 1) / kNumXcd * kNumXcd;
+}
+
+bool residual2d_streamed(const Problem &Pb) {
+    return Pb.cf64.ptr != nullptr && Pb.fac64.ptr != nullptr && Pb.uhi >= Pb.ulo;
 }
 
 template <int P, class T, bool NORM>
 void res2d_launch(const Problem &Pb, const T *val, const T *x, const T *b, T *r, double *partial, hipStream_t s) {
     const int n1 = Pb.fine.n1;
-    const dim3 grid(nblk(n1, kResTX), nblk(n1, kResTYT * kResRY));
-    hipLaunchKernelGGL((k_residual2d<P, T, NORM>), grid, dim3(kResTX * kResTYT), 0, s, val, Pb.A.npad,
-                       Pb.A.pitch[1], n1, x, b, r, partial, cs_of<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip);
+    if (!residual2d_streamed(Pb)) {
+        const dim3 grid(nblk(n1, kResTX), nblk(n1, kResCH));
+        hipLaunchKernelGGL((k_residual2d_tiled<P, T, NORM>), grid, dim3(kResTX * kResTYT), 0, s, val, Pb.A.npad,
+                           Pb.A.pitch[1], n1, x, b, r, partial, Pb.skip);
+        return;
+    }
+    const int seg = residual2d_segment_rows(n1);
+    const int nsx = int(nblk(n1, kResTX)), nseg = int(nblk(n1, seg));
+    const int nfg = int(residual2d_frame_groups(Pb));
+    hipLaunchKernelGGL((k_residual2d<P, T, NORM>), dim3(nfg + nsx * nseg), dim3(kResTX * kResTYT), 0, s,
+                       fac_of<T>(Pb), n1, nfg, nsx, nseg, seg, x, b, r, partial, cf_of<T>(Pb), Pb.ulo, Pb.uhi,
+                       Pb.skip);
 }
 
 template <class T, bool NORM>
@@ -357,7 +611,9 @@ void res2d_dispatch(const Problem &Pb, const T *val, const T *x, const T *b, T *
 
 int64_t residual2d_workgroups(const Problem &P) {
     const int64_t n1 = P.fine.n1;
-    return ((n1 + kResTX - 1) / kResTX) * ((n1 + kResTYT * kResRY - 1) / (kResTYT * kResRY));
+    if (!residual2d_streamed(P)) return ((n1 + kResTX - 1) / kResTX) * ((n1 + kResCH - 1) / kResCH);
+    const int64_t seg = residual2d_segment_rows(n1);
+    return residual2d_frame_groups(P) + ((n1 + kResTX - 1) / kResTX) * ((n1 + seg - 1) / seg);
 }
 
 template <class T>

@@ -1143,6 +1143,7 @@ template void launch_defect<float>(const Problem &, const float *, const float *
 // number of workgroups of the FP64 residual launch (one partial sum each)
 int64_t residual_workgroups(const Problem &Pb) {
     if (residual3d_sf_ok(Pb)) return residual3d_sf_workgroups(Pb);
+    if (Pb.dim == 2 && Pb.fine.n >= (int64_t(1) << 20)) return residual2d_workgroups(Pb);
     const int64_t n1 = Pb.fine.n1;
     if (Pb.dim == 2) return ((n1 + TileShape<2, 1>::TX - 1) / TileShape<2, 1>::TX) * ((n1 + TileShape<2, 1>::TY - 1) / TileShape<2, 1>::TY);
     return ((n1 + TileShape<3, 1>::TX - 1) / TileShape<3, 1>::TX) * ((n1 + TileShape<3, 1>::TY - 1) / TileShape<3, 1>::TY) *

@@ -284,6 +284,10 @@ void host_assemble(Problem &P) {
     P.uhi = n1 - 2 * p;
     P.cs64.free();
     P.cs32.free();
+    P.cf64.free();
+    P.cf32.free();
+    P.fac64.free();
+    P.fac32.free();
     if (P.kappa_one && P.uhi >= P.ulo) {
         int64_t padc = 0;
         for (int k = 0; k < d; ++k) padc += int64_t(n1 / 2 + p) * A.pitch[k];
@@ -301,6 +305,26 @@ void host_assemble(Problem &P) {
         P.cs32.alloc(cs32.size() * sizeof(float));
         IGA2L_HIP(hipMemcpy(P.cs64.ptr, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice));
         IGA2L_HIP(hipMemcpy(P.cs32.ptr, cs32.data(), cs32.size() * sizeof(float), hipMemcpyHostToDevice));
+        // the same stencil as K1 (x) M1 + M1 (x) K1 of the interior 1-D rows, for
+        // kernels that apply it by sum factorisation
+        const size_t ic = size_t(n1 / 2) * w1;
+        std::vector<double> cf(P.K1.begin() + ic, P.K1.begin() + ic + w1);
+        cf.insert(cf.end(), P.M1.begin() + ic, P.M1.begin() + ic + w1);
+        std::vector<float> cf32(cf.begin(), cf.end());
+        P.cf64.alloc(cf.size() * sizeof(double));
+        P.cf32.alloc(cf32.size() * sizeof(float));
+        IGA2L_HIP(hipMemcpy(P.cf64.ptr, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice));
+        IGA2L_HIP(hipMemcpy(P.cf32.ptr, cf32.data(), cf32.size() * sizeof(float), hipMemcpyHostToDevice));
+        if (d == 2) {
+            // every row of both factors, for the rows next to the boundary
+            std::vector<double> fac(P.K1);
+            fac.insert(fac.end(), P.M1.begin(), P.M1.end());
+            std::vector<float> fac32(fac.begin(), fac.end());
+            P.fac64.alloc(fac.size() * sizeof(double));
+            P.fac32.alloc(fac32.size() * sizeof(float));
+            IGA2L_HIP(hipMemcpy(P.fac64.ptr, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice));
+            IGA2L_HIP(hipMemcpy(P.fac32.ptr, fac32.data(), fac32.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
     } else {
         P.ulo = 1;
         P.uhi = 0;

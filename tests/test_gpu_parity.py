@@ -416,16 +416,22 @@ def test_full_size_cycle_parity_256(m):
 GOLDEN_LARGE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_grid_2d_p3_m1024.json")
 
 
-def test_large_grid_kernels_sampled():
+@pytest.mark.parametrize("groups", [None, "40"])
+def test_large_grid_kernels_sampled(groups, monkeypatch):
     """2-D p=3 on 1024x1024 elements (1.05 M DOFs), where the residual runs as
-    the column-blocked kernel and the transfers on 64x16 tiles:
-    sampled entries and the 2-norms of the whole vectors against the oracle
-    (values written by tests/golden/make_large_grid.py, which calls only the
-    oracle)."""
+    the streamed strip kernel with its boundary-frame workgroups and the
+    transfers on 64x16 tiles: sampled entries and the 2-norms of the whole
+    vectors against the oracle (values written by
+    tests/golden/make_large_grid.py, which calls only the oracle).  With a
+    target of 40 residual workgroups each strip runs 17 chunks of 32 rows
+    through its 64-row ring (the default gives one chunk per workgroup at
+    this size)."""
     G = _gpu()
+    if groups is not None:
+        monkeypatch.setenv("IGA2L_RESIDUAL_GROUPS", groups)
     ref = json.load(open(GOLDEN_LARGE))
     d, p, m = 2, 3, 1024
-    print(f"\n[case] large grid d={d} p={p} m={m}", flush=True)
+    print(f"\n[case] large grid d={d} p={p} m={m} residual groups={groups}", flush=True)
     gp = G.Problem(d, p, m)
     gp.setup(0, G.Opts())
     assert gp.n == ref["n"] and gp.nc == ref["nc"]
@@ -452,6 +458,74 @@ def test_large_grid_kernels_sampled():
     ug = dev(u)
     gp.smooth(ug, dev(b), 1, G.Opts(ordering=G.COLOUR, colour_period=3))
     check("sweep", host(ug))
+
+
+def _oracle_residual_offsets(d, p, m, kappa, u, b):
+    """r = b - A u with A from the oracle's offset-stored assembly (2-D), by
+    the (2p+1)^2 shifted products (equal to the oracle problem's residual)."""
+    S = O.assemble(d, p, m, kappa=kappa)
+    n1, w1 = m + p - 2, 2 * p + 1
+    U = np.zeros((n1 + 2 * p, n1 + 2 * p))
+    U[p:-p, p:-p] = u.reshape(n1, n1)
+    Au = np.zeros((n1, n1))
+    for w in range(w1 * w1):
+        ox, oy = w % w1, w // w1
+        Au += S[:, w].reshape(n1, n1) * U[oy:oy + n1, ox:ox + n1]
+    return b - Au.ravel()
+
+
+def test_large_grid_variable_kappa_residual():
+    """2-D p=2 on 1024x1024 elements with kappa = exp(GRF): the residual of
+    a variable coefficient on a large grid (tiled kernel reading the
+    (2p+1)^2 diagonals), entry by entry against the oracle's assembly.  The
+    reference is computed here, not stored: the field's square-root factor
+    keeps round-off eigenvalues, whose eigenvectors (and so kappa, at the
+    1e-7 level) differ between machines."""
+    G = _gpu()
+    d, p, m = 2, 2, 1024
+    print(f"\n[case] large grid variable kappa d={d} p={p} m={m}", flush=True)
+    kappa = synth.kappa_grf(d, m, 1.0, 0.1, seed=7)
+    u = synth.initial_guess(d, p, m, seed=1)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    want = _oracle_residual_offsets(d, p, m, kappa, u, b)
+    gp = G.Problem(d, p, m, kappa=kappa)
+    gp.setup(0, G.Opts())
+    for _ in range(2):
+        r = host(gp.residual(dev(u), dev(b)))
+        e = float(np.max(np.abs(r - want)) / np.max(np.abs(want)))
+        print(f"[large kappa] residual: max rel {e:.2e}", flush=True)
+        assert e < 1e-12, e
+
+
+@pytest.mark.parametrize("groups", [None, "40"])
+def test_large_grid_mixed_solve(groups, monkeypatch):
+    """2-D p=3 on 1024x1024 elements: the mixed-precision solve, whose FP32
+    correction cycle takes its defect from the streamed residual kernel in
+    FP32, reaches the 1e-10 reduction within two cycles of the FP64 solve.
+    The reduction is re-measured from the returned solutions with the FP64
+    residual (checked against the oracle above), not taken from the solver."""
+    G = _gpu()
+    if groups is not None:
+        monkeypatch.setenv("IGA2L_RESIDUAL_GROUPS", groups)
+    d, p, m = 2, 3, 1024
+    print(f"\n[case] large grid mixed solve d={d} p={p} m={m} residual groups={groups}", flush=True)
+    gp = G.Problem(d, p, m)
+    o64 = G.Opts(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2, tol=1e-10)
+    o32 = G.Opts(coarse=G.COARSE_VCYCLE, nu1=2, nu2=2, tol=1e-10, precision=G.MIXED_FP32)
+    gp.setup(0, o32)
+    b = dev(synth.rhs_normal(d, p, m, seed=0))
+    u64, i64 = gp.solve(b, opts=o64)
+    u32, i32 = gp.solve(b, opts=o32)
+    bn = float(np.linalg.norm(host(b)))
+    t64 = float(np.linalg.norm(host(gp.residual(u64, b)))) / bn
+    t32 = float(np.linalg.norm(host(gp.residual(u32, b)))) / bn
+    e = rel(host(u32), host(u64))
+    print(f"[large mixed] cycles fp64={i64.iters} mixed={i32.iters} relres {i64.relres:.2e} {i32.relres:.2e} "
+          f"re-measured {t64:.2e} {t32:.2e} difference {e:.2e}", flush=True)
+    assert i64.relres <= 1e-10 and i32.relres <= 1e-10
+    assert t64 <= 1e-10 and t32 <= 1e-10
+    assert i32.iters <= i64.iters + 2
+    assert e < 1e-4
 
 
 GOLDEN_3D = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grid_3d_p3_m64.json")
