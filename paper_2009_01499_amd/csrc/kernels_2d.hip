@@ -25,8 +25,8 @@ inline unsigned nblk(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
 // ------------------------------------------------------------------------
 // shared pieces of the 2-D residual kernels
-constexpr int kResTX = 64, kResTYT = 4, kResRY = 8, kResCH = kResTYT * kResRY, kResRing = 64;
-constexpr int kResTargetGroups = 1024;  // four resident workgroups per CU
+constexpr int kResTX = 64, kResTYT = 4, kResRY = 4, kResCH = kResTYT * kResRY, kResRing = 32;
+constexpr int kResTargetGroups = 8192;  // about four rounds of the resident workgroups
 
 // the workgroup's sum of rr (a fixed order: wavefront reductions, then the
 // wavefronts in turn), written by thread 0
@@ -73,7 +73,10 @@ __device__ __forceinline__ void residual_frame_point(const T *__restrict__ fac, 
     const T *Kx = K + int64_t(gx) * W1, *Mx = M + int64_t(gx) * W1;
     const T *Ky = K + int64_t(gy) * W1, *My = M + int64_t(gy) * W1;
     T acc = T(0);
-#pragma unroll
+    // every load in flight at once for P <= 3; a run-time loop over the
+    // stencil rows above, where the unrolled loads would set the register
+    // count of the whole kernel
+#pragma unroll(P <= 3 ? W1 : 1)
     for (int oy = 0; oy < W1; ++oy) {
         const int jy = min(max(gy + oy - P, 0), n1 - 1);
         T mx = T(0), kx = T(0);
@@ -176,9 +179,9 @@ __global__ void __launch_bounds__(kResTX *kResTYT) k_residual2d_tiled(const T *_
 // [ulo, uhi] carry the interior stencil, K1 (x) M1 + M1 (x) K1 of the interior
 // 1-D rows cf (K1 then M1), applied by sum factorisation (per window row the x
 // sums of both factors, then the y taps).  A workgroup owns a strip of 64
-// columns over a segment of rows and walks down it in chunks of 32 rows; a
+// columns over a segment of rows and walks down it in chunks of 16 rows; a
 // thread owns a column of RY consecutive points of the chunk.  The x window
-// lives in an LDS ring of 64 rows, so the 2P halo rows shared by consecutive
+// lives in an LDS ring of 32 rows, so the 2P halo rows shared by consecutive
 // chunks are read from memory once, and the rows of the next chunk (and its
 // right-hand side) are loaded into registers while the current chunk
 // computes, which keeps memory requests in flight through the arithmetic.
@@ -330,18 +333,13 @@ __global__ void __launch_bounds__(kResTX *kResTYT, (sizeof(T) == 8 && P == 8) ? 
     if constexpr (NORM) block_partial<NT>(rr, partial + id);
 }
 
-// rows per segment of the streamed residual: whole chunks, as many segments
-// as bring the launch to about kResTargetGroups workgroups (the environment
-// variable IGA2L_RESIDUAL_GROUPS sets another target: tests use a small one
+int stream_segment_rows(int64_t n1, int tx, int ch, int64_t target, const char *env);
+
+// rows per segment of the streamed residual (the environment variable
+// IGA2L_RESIDUAL_GROUPS sets another workgroup target: tests use a small one
 // to send many chunks through each ring)
 int residual2d_segment_rows(int64_t n1) {
-    int64_t target = kResTargetGroups;
-    if (const char *e = std::getenv("IGA2L_RESIDUAL_GROUPS")) target = std::max(1L, std::atol(e));
-    const int64_t nsx = (n1 + kResTX - 1) / kResTX;
-    const int64_t nch = (n1 + kResCH - 1) / kResCH;
-    const int64_t want = std::max<int64_t>(1, target / nsx);
-    const int64_t per = (nch + want - 1) / want;
-    return int(per * kResCH);
+    return stream_segment_rows(n1, kResTX, kResCH, kResTargetGroups, "IGA2L_RESIDUAL_GROUPS");
 }
 
 // ------------------------------------------------------------------------
@@ -506,6 +504,261 @@ __global__ void __launch_bounds__(256) k_prolong2d(const T *__restrict__ R1, int
                       reinterpret_cast<T *>(smem_raw));
 }
 
+// ------------------------------------------------------------------------
+// Streamed transfers for large grids (degree-1 coarse space).  As in the
+// streamed residual, a workgroup owns a strip of 64 output columns over a
+// segment of output rows and walks down it in chunks (here 16 rows, 4 per
+// thread); the input rows it needs pass once through an LDS ring of 32 rows,
+// the next chunk's rows (and the update's operands) are loaded into registers
+// while the current chunk computes, and the two passes of the separable
+// transfer are fused per thread: for each input row of its window a thread
+// forms the x sum of its column, then adds it with the y weight to each of
+// its outputs.  Sums run in the tiled kernels' order.
+constexpr int kTrTX = 64, kTrTYT = 4, kTrRY = 4, kTrCH = kTrTYT * kTrRY, kTrRing = 32;
+constexpr int kTrTargetGroups = 8192;  // four rounds of eight resident workgroups per CU
+
+// the input window of a streamed transfer: window row q holds input row
+// r0 + q at ring slot q % RING, window column hx input column c0 + hx.  Rows
+// 0 .. LEAD-1 are staged before the first chunk; chunk c brings rows
+// c CH + LEAD .. c CH + LEAD + CH - 1, the strip's 64 columns at window
+// columns IX .. IX+63 (row ty + 4u for thread (tx, ty)) and the HX-64 others
+// (thread t: row t % CH of halo column t / CH).  Loads read clamped addresses
+// unpredicated; positions outside the nin x nin input are zeroed on the way
+// into the ring.
+template <int HX, int IX, int LEAD, class T>
+struct TrWindow {
+    static constexpr int TX = kTrTX, CH = kTrCH, RING = kTrRing, NT = kTrTX * kTrTYT;
+    static constexpr int NI = CH / kTrTYT, NHC = HX - TX, NH = (NHC * CH + NT - 1) / NT;
+    static_assert(CH + LEAD <= RING && (RING & (RING - 1)) == 0, "ring: a power of two holding the window");
+    const T *in;
+    int nin, r0, c0, tid, tx, ty;
+    T xi[NI], xh[NH];
+    __device__ int halo_hx(int hc) const { return hc < IX ? hc : TX + hc; }
+    __device__ void prefetch(int c) {
+        const int rb = r0 + c * CH + LEAD;
+        const int cc = min(max(c0 + IX + tx, 0), nin - 1);
+#pragma unroll
+        for (int u = 0; u < NI; ++u)
+            xi[u] = in[int64_t(min(max(rb + ty + kTrTYT * u, 0), nin - 1)) * nin + cc];
+#pragma unroll
+        for (int u = 0; u < NH; ++u) {
+            const int t = tid + u * NT;
+            const int gc = c0 + halo_hx(t / CH);
+            xh[u] = in[int64_t(min(max(rb + t % CH, 0), nin - 1)) * nin + min(max(gc, 0), nin - 1)];
+        }
+    }
+    __device__ void store(T *ring, int c) const {
+        const int q = c * CH + LEAD, rb = r0 + q;
+        const int gcol = c0 + IX + tx;
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int j = ty + kTrTYT * u, gr = rb + j;
+            ring[((q + j) & (RING - 1)) * HX + IX + tx] =
+                (gcol >= 0 && gcol < nin && gr >= 0 && gr < nin) ? xi[u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NH; ++u) {
+            const int t = tid + u * NT, j = t % CH, hx = halo_hx(t / CH);
+            const int gc = c0 + hx, gr = rb + j;
+            if (t < NHC * CH)
+                ring[((q + j) & (RING - 1)) * HX + hx] = (gc >= 0 && gc < nin && gr >= 0 && gr < nin) ? xh[u] : T(0);
+        }
+    }
+    __device__ void stage_lead(T *ring) const {
+        stage_lds<(LEAD * HX + NT - 1) / NT>(ring, LEAD * HX, [&](int h) {
+            const int gc = c0 + h % HX, gr = r0 + h / HX;
+            return (gc >= 0 && gc < nin && gr >= 0 && gr < nin) ? in[int64_t(gr) * nin + gc] : T(0);
+        });
+    }
+};
+
+// output rows per segment of a streamed 2-D kernel: whole chunks of ch rows,
+// as many segments as bring the launch to about target workgroups (the
+// environment variable env, when set, gives another target)
+int stream_segment_rows(int64_t n1, int tx, int ch, int64_t target, const char *env) {
+    if (const char *e = std::getenv(env)) target = std::max(1L, std::atol(e));
+    const int64_t nsx = (n1 + tx - 1) / tx;
+    const int64_t nch = (n1 + ch - 1) / ch;
+    const int64_t want = std::max<int64_t>(1, target / nsx);
+    return int(((nch + want - 1) / want) * ch);
+}
+
+// d_c = (R1 (x) R1) d_f: coarse (I, J) takes fine I-1 .. I+P per direction
+// with weights R1[I][a], R1[J][b].  Window: fine rows from y0 - 1, fine
+// columns from I0 - 1.
+template <int P, class T>
+__global__ void __launch_bounds__(kTrTX *kTrTYT) k_restrict2d_stream(const T *__restrict__ R1, int n1f, int n1c,
+                                                                     int nsx, int nseg, int seg_rows,
+                                                                     const T *__restrict__ df, T *__restrict__ dc,
+                                                                     const int *__restrict__ skip) {
+    constexpr int W = P + 2, HX = kTrTX + P + 1, RY = kTrRY, CH = kTrCH, RING = kTrRing;
+    __shared__ T ring[RING * HX];
+    if (skip && *skip) return;
+    int bx, bs;
+    xcd_relabel(int(blockIdx.x), nsx, nsx * nseg, bx, bs);
+    const int I0 = bx * kTrTX, y0 = bs * seg_rows, y1 = min(y0 + seg_rows, n1c);
+    const int nch = (y1 - y0 + CH - 1) / CH;
+    const int tid = int(threadIdx.x), tx = tid % kTrTX;
+    const int ty = __builtin_amdgcn_readfirstlane(tid / kTrTX);
+    const int I = I0 + tx;
+    T rx[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) rx[a] = I < n1c ? R1[int64_t(I) * W + a] : T(0);
+    TrWindow<HX, 1, P + 1, T> win{df, n1f, y0 - 1, I0 - 1, tid, tx, ty, {}, {}};
+    win.stage_lead(ring);
+    win.prefetch(0);
+    win.store(ring, 0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const bool more = c + 1 < nch;
+        if (more) win.prefetch(c + 1);
+        const int J0 = y0 + c * CH + ty * RY, q0 = c * CH + ty * RY;
+        T acc[RY];
+#pragma unroll
+        for (int k = 0; k < RY; ++k) acc[k] = T(0);
+        if (J0 < y1) {
+            T ry[RY][W];
+#pragma unroll
+            for (int k = 0; k < RY; ++k)
+#pragma unroll
+                for (int bb = 0; bb < W; ++bb) ry[k][bb] = J0 + k < n1c ? R1[int64_t(J0 + k) * W + bb] : T(0);
+#pragma unroll
+            for (int yy = 0; yy < RY + W - 1; ++yy) {
+                const T *row = ring + ((q0 + yy) & (RING - 1)) * HX + tx;
+                T xs = T(0);
+#pragma unroll
+                for (int a = 0; a < W; ++a) xs += rx[a] * row[a];
+#pragma unroll
+                for (int k = 0; k < RY; ++k) {
+                    const int bb = yy - k;
+                    if (bb >= 0 && bb < W) acc[k] += ry[k][bb] * xs;
+                }
+            }
+        }
+        if (more) {
+            __syncthreads();
+            win.store(ring, c + 1);
+            __syncthreads();
+        }
+        if (I < n1c) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k)
+                if (J0 + k < y1) dc[int64_t(J0 + k) * n1c + I] = acc[k];
+        }
+    }
+}
+
+// (R1 (x) R1)^T e_c: fine (i, j) takes coarse I = i-P .. i+1 (and J alike)
+// with weight R1[I][i-I+1] R1[J][j-J+1].  MODE 0: uf += P e_c; MODE 1:
+// u64 += sigma (e + P e_c) (sigma from scal when scaled, else 1).  Window:
+// coarse rows from y0 - P, coarse columns from i0 - P.
+template <int P, class T, int MODE>
+__global__ void __launch_bounds__(kTrTX *kTrTYT) k_prolong2d_stream(const T *__restrict__ R1, int n1f, int n1c,
+                                                                    int nsx, int nseg, int seg_rows,
+                                                                    const T *__restrict__ ec, T *__restrict__ uf,
+                                                                    const T *__restrict__ e, double *__restrict__ u64,
+                                                                    const double *__restrict__ scal, int scaled,
+                                                                    const int *__restrict__ skip) {
+    constexpr int W = P + 2, HX = kTrTX + P + 1, RY = kTrRY, CH = kTrCH, RING = kTrRing;
+    __shared__ T ring[RING * HX];
+    if (skip && *skip) return;
+    int bx, bs;
+    xcd_relabel(int(blockIdx.x), nsx, nsx * nseg, bx, bs);
+    const int i0 = bx * kTrTX, y0 = bs * seg_rows, y1 = min(y0 + seg_rows, n1f);
+    const int nch = (y1 - y0 + CH - 1) / CH;
+    const int tid = int(threadIdx.x), tx = tid % kTrTX;
+    const int ty = __builtin_amdgcn_readfirstlane(tid / kTrTX);
+    const int i = i0 + tx, ic = min(i, n1f - 1);
+    // weight of window column tx + q (coarse I = i - P + q): R1[I][P+1-q]
+    T cx[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        const int Ic = i - P + q;
+        cx[q] = (Ic >= 0 && Ic < n1c) ? R1[int64_t(Ic) * W + (P + 1 - q)] : T(0);
+    }
+    const double sigma = (MODE == 1 && scaled) ? scal[kScalSigma] : 1.0;
+    TrWindow<HX, P, P + 1, T> win{ec, n1c, y0 - P, i0 - P, tid, tx, ty, {}, {}};
+    // the update's operands at the thread's outputs, double-buffered
+    T ov[RY], on[RY];
+    double uv[RY], un[RY];
+    auto prefetch_out = [&](int c, T *o, double *uu) {
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int64_t g = int64_t(min(y0 + c * CH + ty * RY + k, n1f - 1)) * n1f + ic;
+            if constexpr (MODE == 0) {
+                o[k] = uf[g];
+            } else {
+                o[k] = e[g];
+                uu[k] = u64[g];
+            }
+        }
+    };
+    win.stage_lead(ring);
+    prefetch_out(0, ov, uv);
+    win.prefetch(0);
+    win.store(ring, 0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const bool more = c + 1 < nch;
+        if (more) {
+            prefetch_out(c + 1, on, un);
+            win.prefetch(c + 1);
+        }
+        const int j0 = y0 + c * CH + ty * RY, q0 = c * CH + ty * RY;
+        T acc[RY];
+#pragma unroll
+        for (int k = 0; k < RY; ++k) acc[k] = T(0);
+        if (j0 < y1) {
+            T cy[RY][W];
+#pragma unroll
+            for (int k = 0; k < RY; ++k)
+#pragma unroll
+                for (int bb = 0; bb < W; ++bb) {
+                    const int J = j0 + k - P + bb;
+                    cy[k][bb] = (J >= 0 && J < n1c) ? R1[int64_t(J) * W + (P + 1 - bb)] : T(0);
+                }
+#pragma unroll
+            for (int yy = 0; yy < RY + W - 1; ++yy) {
+                const T *row = ring + ((q0 + yy) & (RING - 1)) * HX + tx;
+                T xs = T(0);
+#pragma unroll
+                for (int q = 0; q < W; ++q) xs += cx[q] * row[q];
+#pragma unroll
+                for (int k = 0; k < RY; ++k) {
+                    const int bb = yy - k;
+                    if (bb >= 0 && bb < W) acc[k] += cy[k][bb] * xs;
+                }
+            }
+        }
+        if (more) {
+            __syncthreads();
+            win.store(ring, c + 1);
+            __syncthreads();
+        }
+        if (i < n1f) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                const int j = j0 + k;
+                if (j >= y1) continue;
+                const int64_t g = int64_t(j) * n1f + i;
+                if constexpr (MODE == 0) {
+                    uf[g] = ov[k] + acc[k];
+                } else {
+                    const T corr = ov[k] + acc[k];
+                    u64[g] = uv[k] + (scaled ? sigma * double(corr) : double(corr));
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                ov[k] = on[k];
+                if constexpr (MODE == 1) uv[k] = un[k];
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- batched --
 template <class T>
 constexpr int prec_slot() { return std::is_same<T, double>::value ? 0 : 1; }
@@ -627,8 +880,57 @@ template void launch_residual2d<double>(const Problem &, const double *, const d
 template void launch_residual2d<float>(const Problem &, const float *, const float *, const float *, float *,
                                        double *, hipStream_t);
 
+namespace {
+
+template <int P, class T>
+void restrict2d_stream_launch(const Problem &Pb, const T *df, T *dc, hipStream_t s) {
+    const int n1c = Pb.coarse.n1;
+    const int seg = stream_segment_rows(n1c, kTrTX, kTrCH, kTrTargetGroups, "IGA2L_TRANSFER_GROUPS");
+    const int nsx = int(nblk(n1c, kTrTX)), nseg = int(nblk(n1c, seg));
+    hipLaunchKernelGGL((k_restrict2d_stream<P, T>), dim3(nsx * nseg), dim3(kTrTX * kTrTYT), 0, s, R1_of<T>(Pb),
+                       Pb.fine.n1, n1c, nsx, nseg, seg, df, dc, Pb.skip);
+}
+
+template <int P, class T>
+void prolong2d_stream_launch(const Problem &Pb, const T *ec, T *uf, const T *e, double *u64, bool scaled,
+                             hipStream_t s) {
+    const int n1f = Pb.fine.n1;
+    const int seg = stream_segment_rows(n1f, kTrTX, kTrCH, kTrTargetGroups, "IGA2L_TRANSFER_GROUPS");
+    const int nsx = int(nblk(n1f, kTrTX)), nseg = int(nblk(n1f, seg));
+    if (u64)
+        hipLaunchKernelGGL((k_prolong2d_stream<P, T, 1>), dim3(nsx * nseg), dim3(kTrTX * kTrTYT), 0, s,
+                           R1_of<T>(Pb), n1f, Pb.coarse.n1, nsx, nseg, seg, ec, static_cast<T *>(nullptr), e, u64,
+                           Pb.scal.as<double>(), scaled ? 1 : 0, Pb.skip);
+    else
+        hipLaunchKernelGGL((k_prolong2d_stream<P, T, 0>), dim3(nsx * nseg), dim3(kTrTX * kTrTYT), 0, s,
+                           R1_of<T>(Pb), n1f, Pb.coarse.n1, nsx, nseg, seg, ec, uf, static_cast<const T *>(nullptr),
+                           static_cast<double *>(nullptr), static_cast<const double *>(nullptr), 0, Pb.skip);
+}
+
+// the streamed transfers serve grids of at least 2^20 fine points
+bool transfer2d_streamed(const Problem &P) { return P.plow == 1 && P.fine.n >= (int64_t(1) << 20); }
+
+}  // namespace
+
+#define IGA2L_TR_DISPATCH(F, ...)                                        \
+    switch (P.p) {                                                       \
+        case 1: F<1, T>(__VA_ARGS__); break;                             \
+        case 2: F<2, T>(__VA_ARGS__); break;                             \
+        case 3: F<3, T>(__VA_ARGS__); break;                             \
+        case 4: F<4, T>(__VA_ARGS__); break;                             \
+        case 5: F<5, T>(__VA_ARGS__); break;                             \
+        case 6: F<6, T>(__VA_ARGS__); break;                             \
+        case 7: F<7, T>(__VA_ARGS__); break;                             \
+        case 8: F<8, T>(__VA_ARGS__); break;                             \
+        default: throw Error{IGA2L_EUNSUPPORTED, "degree out of range"}; \
+    }
+
 template <class T>
 void launch_restrict2d(const Problem &P, const T *df, T *dc, hipStream_t s) {
+    if (transfer2d_streamed(P)) {
+        IGA2L_TR_DISPATCH(restrict2d_stream_launch, P, df, dc, s);
+        return;
+    }
     const int p = P.p;
     int CX, CY;
     transfer_tile_2d(P.coarse.n1, CX, CY);
@@ -642,6 +944,10 @@ template void launch_restrict2d<float>(const Problem &, const float *, float *, 
 
 template <class T>
 void launch_prolong2d(const Problem &P, const T *ec, T *uf, const T *e, double *u64, bool scaled, hipStream_t s) {
+    if (transfer2d_streamed(P)) {
+        IGA2L_TR_DISPATCH(prolong2d_stream_launch, P, ec, uf, e, u64, scaled, s);
+        return;
+    }
     const int p = P.p;
     int TX, TY;
     transfer_tile_2d(P.fine.n1, TX, TY);
@@ -654,6 +960,8 @@ template void launch_prolong2d<double>(const Problem &, const double *, double *
                                        hipStream_t);
 template void launch_prolong2d<float>(const Problem &, const float *, float *, const float *, double *, bool,
                                       hipStream_t);
+
+#undef IGA2L_TR_DISPATCH
 
 size_t restrict2d_lds(int p, int cx, int cy, size_t elem) {
     const size_t w = p + 2, FX = cx + p + 1, FY = cy + p + 1;

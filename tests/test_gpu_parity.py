@@ -420,15 +420,16 @@ GOLDEN_LARGE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"
 def test_large_grid_kernels_sampled(groups, monkeypatch):
     """2-D p=3 on 1024x1024 elements (1.05 M DOFs), where the residual runs as
     the streamed strip kernel with its boundary-frame workgroups and the
-    transfers on 64x16 tiles: sampled entries and the 2-norms of the whole
-    vectors against the oracle (values written by
+    transfers as streamed strips too: sampled entries and the 2-norms of the
+    whole vectors against the oracle (values written by
     tests/golden/make_large_grid.py, which calls only the oracle).  With a
-    target of 40 residual workgroups each strip runs 17 chunks of 32 rows
-    through its 64-row ring (the default gives one chunk per workgroup at
-    this size)."""
+    target of 40 workgroups each residual strip runs 33 chunks and each
+    transfer strip 32 chunks of 16 rows through its 32-row ring (the
+    defaults give one chunk per workgroup at this size)."""
     G = _gpu()
     if groups is not None:
         monkeypatch.setenv("IGA2L_RESIDUAL_GROUPS", groups)
+        monkeypatch.setenv("IGA2L_TRANSFER_GROUPS", groups)
     ref = json.load(open(GOLDEN_LARGE))
     d, p, m = 2, 3, 1024
     print(f"\n[case] large grid d={d} p={p} m={m} residual groups={groups}", flush=True)
@@ -501,12 +502,13 @@ def test_large_grid_variable_kappa_residual():
 def test_large_grid_mixed_solve(groups, monkeypatch):
     """2-D p=3 on 1024x1024 elements: the mixed-precision solve, whose FP32
     correction cycle takes its defect from the streamed residual kernel in
-    FP32, reaches the 1e-10 reduction within two cycles of the FP64 solve.
+    FP32 (and whose update is the streamed prolongation into FP64), reaches the 1e-10 reduction within two cycles of the FP64 solve.
     The reduction is re-measured from the returned solutions with the FP64
     residual (checked against the oracle above), not taken from the solver."""
     G = _gpu()
     if groups is not None:
         monkeypatch.setenv("IGA2L_RESIDUAL_GROUPS", groups)
+        monkeypatch.setenv("IGA2L_TRANSFER_GROUPS", groups)
     d, p, m = 2, 3, 1024
     print(f"\n[case] large grid mixed solve d={d} p={p} m={m} residual groups={groups}", flush=True)
     gp = G.Problem(d, p, m)
