@@ -81,6 +81,12 @@ def lib():
             "or_direct_solve": (i, [vp, dp, dp]),
             "or_grad_kappa": (i, [vp, dp, dp, dp]),
             "or_element_apply": (i, [vp, l, dp, dp]),
+            "or_annulus_weights": (i, [i, i, dp]),
+            "or_load_annulus": (i, [i, i, d, d, dp]),
+            "or_l2_error_annulus": (d, [i, i, d, d, dp]),
+            "or_annulus_point": (None, [d, d, d, d, dp]),
+            "or_assemble_annulus": (i, [i, i, i, d, d, i, dp]),
+            "or_create_annulus": (vp, [i, i, i, i, i, i, d, d]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -195,15 +201,23 @@ class Problem:
     """The oracle's problem object: operators, Schwarz blocks, coarse solvers."""
 
     def __init__(self, d: int, p: int, m: int, kappa=None, plow: int = 1, block_width: int = 0,
-                 lumped: bool = True, coarse_direct: bool = True, vcycle: bool = False):
+                 lumped: bool = True, coarse_direct: bool = True, vcycle: bool = False, annulus=None):
+        """annulus=(r, R): the quarter-annulus NURBS problem of Section 5.2
+        (d = 2, kappa unused) instead of the unit square."""
         self.d, self.p, self.m, self.plow = d, p, m, plow
         self._kappa = None
         kp = None
         if kappa is not None:
             self._kappa = np.ascontiguousarray(kappa, dtype=np.float64).ravel()
             kp = _p(self._kappa)
-        h = lib().or_create(d, p, m, kp, plow, block_width, 1 if lumped else 0,
-                            1 if coarse_direct else 0, 1 if vcycle else 0)
+        if annulus is not None:
+            if d != 2 or kappa is not None or vcycle:
+                raise ValueError("the annulus problem is 2-D, with no coefficient and no V-cycle hierarchy")
+            h = lib().or_create_annulus(p, m, plow, block_width, 1 if lumped else 0, 1 if coarse_direct else 0,
+                                        float(annulus[0]), float(annulus[1]))
+        else:
+            h = lib().or_create(d, p, m, kp, plow, block_width, 1 if lumped else 0,
+                                1 if coarse_direct else 0, 1 if vcycle else 0)
         if not h:
             raise ValueError(_err())
         self._h = ctypes.c_void_p(h)
@@ -360,3 +374,47 @@ class Problem:
         g = np.zeros(self.ne)
         lib().or_grad_kappa(self._h, _p(u), _p(lam), _p(g))
         return g
+
+
+# ------------------------------------------------------------- annulus --
+ANNULUS = (0.3, 0.5)   # inner and outer radius of Section 5.2
+
+
+def annulus_weights(q: int, m: int) -> np.ndarray:
+    """Weights of the degree-q, m-element basis (all m+q functions) that
+    reproduce the denominator of the rational quadratic quarter circle."""
+    w = np.zeros(m + q)
+    if lib().or_annulus_weights(q, m, _p(w)):
+        raise ValueError(_err())
+    return w
+
+
+def load_annulus(p: int, m: int, radii=ANNULUS) -> np.ndarray:
+    b = np.zeros((m + p - 2) ** 2)
+    if lib().or_load_annulus(p, m, float(radii[0]), float(radii[1]), _p(b)):
+        raise ValueError(_err())
+    return b
+
+
+def l2_error_annulus(p: int, m: int, u: np.ndarray, radii=ANNULUS) -> float:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return lib().or_l2_error_annulus(p, m, float(radii[0]), float(radii[1]), _p(u))
+
+
+def annulus_point(xi: float, eta: float, radii=ANNULUS) -> np.ndarray:
+    out = np.zeros(2)
+    lib().or_annulus_point(float(radii[0]), float(radii[1]), float(xi), float(eta), _p(out))
+    return out
+
+
+def assemble_annulus(p: int, plow: int, m: int, kind: str, radii=ANNULUS) -> np.ndarray:
+    """kind: 'stiff', 'mass' (degree p, by offset of radius p) or 'mix'
+    (rows degree plow, columns degree p, offsets [-plow, p])."""
+    k = {"stiff": 0, "mass": 1, "mix": 2}[kind]
+    if k == 2:
+        out = np.zeros(((m + plow - 2) ** 2, (p + plow + 1) ** 2))
+    else:
+        out = np.zeros(((m + p - 2) ** 2, (2 * p + 1) ** 2))
+    if lib().or_assemble_annulus(p, plow, m, float(radii[0]), float(radii[1]), k, _p(out)):
+        raise ValueError(_err())
+    return out

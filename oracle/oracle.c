@@ -1232,3 +1232,328 @@ int or_element_apply(const or_problem *P, long el, const double *u, double *out)
     free(t);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* NURBS discretisation of the quarter annulus (Sections 2.2 and 5.2) */
+/* ------------------------------------------------------------------ */
+/*
+ * Domain: {(x,y) : r^2 <= x^2+y^2 <= R^2, x, y >= 0}.  Geometry: the map
+ * F(xi, eta) = rho(eta) (c(xi), s(xi)), rho = r + (R - r) eta, where
+ * (c, s) is the quarter of the unit circle written as the rational quadratic
+ * with control points (1,0), (1,1), (0,1) and weights 1, sqrt(2)/2, 1 (the
+ * standard exact conic; Section 2.2 uses quadratic NURBS for this domain).
+ * The radial direction eta is linear, so after raising both directions to
+ * degree q and refining to m elements the weight net is w_i(xi) x 1: the
+ * weights w_i are the coefficients of the quadratic denominator
+ * w(xi) = (1-xi)^2 + sqrt(2) xi (1-xi) + xi^2 in the degree-q basis of the
+ * refined knot vector (computed here by the L2 projection onto that basis,
+ * which reproduces w exactly because w lies in the spline space).
+ *
+ * Basis (Section 2.2): R_ij = w_ij N_i(xi) N_j(eta) / W(xi,eta),
+ * W = sum_kl w_kl N_k(xi) N_l(eta) over every function of the full basis
+ * (the Dirichlet-eliminated ones included).  The discrete space of degree q
+ * is the span of the interior R_ij composed with F^{-1}.  Integrals are
+ * pulled back to (0,1)^2 with the Jacobian J of F: stiffness
+ * int grad_xi R_a^T (J^T J)^{-1} grad_xi R_b |det J|, mass
+ * int R_a R_b |det J|.  Quadrature: Gauss with QPTS(pfine) points per
+ * direction per element (the integrands are rational; the rule is fixed by
+ * the fine degree and shared by every annulus integral of a problem).
+ */
+#define OR_ANN_QPTS(pf) ((pf) + 3)
+
+static void circle_arc(double xi, double *c, double *s, double *dc, double *ds) {
+    const double r2 = sqrt(2.0);
+    double nx = (1 - xi) * (1 - xi) + r2 * xi * (1 - xi);
+    double ny = r2 * xi * (1 - xi) + xi * xi;
+    double w = nx + xi * xi;   /* (1-xi)^2 + sqrt2 xi(1-xi) + xi^2 */
+    double dnx = -2 * (1 - xi) + r2 * (1 - 2 * xi);
+    double dny = r2 * (1 - 2 * xi) + 2 * xi;
+    double dw = dnx + 2 * xi;
+    *c = nx / w; *s = ny / w;
+    *dc = (dnx * w - nx * dw) / (w * w);
+    *ds = (dny * w - ny * dw) / (w * w);
+}
+
+static double arc_denominator(double xi) {
+    return (1 - xi) * (1 - xi) + sqrt(2.0) * xi * (1 - xi) + xi * xi;
+}
+
+/* the weights of the degree-q, m-element basis (all m+q functions): the L2
+ * projection of w(xi), Gram system solved by dense Cholesky */
+int or_annulus_weights(int q, int m, double *wts) {
+    int nb = m + q;
+    double *t = malloc(sizeof(double) * (2 * q + m + 1));
+    or_knots(q, m, t);
+    double *G = calloc((size_t)nb * nb, sizeof(double));
+    double *g = calloc(nb, sizeof(double));
+    double gx[64], gw[64], val[16];
+    int nq = q + 3;
+    or_gauss_legendre(nq, gx, gw);
+    double h = 1.0 / m;
+    for (int e = 0; e < m; e++)
+        for (int k = 0; k < nq; k++) {
+            double x = (e + 0.5 * (gx[k] + 1.0)) * h, wq = 0.5 * h * gw[k];
+            live_basis(t, q, e, x, val, NULL);
+            double wx = arc_denominator(x);
+            for (int a = 0; a <= q; a++) {
+                g[e + a] += wq * val[a] * wx;
+                for (int b = 0; b <= q; b++) G[(size_t)(e + a) * nb + e + b] += wq * val[a] * val[b];
+            }
+        }
+    int rc = dense_cholesky(nb, G);
+    if (rc == 0) {
+        dense_chol_solve(nb, G, g);
+        memcpy(wts, g, sizeof(double) * nb);
+    }
+    free(t); free(G); free(g);
+    return rc ? fail("or_annulus_weights: Gram matrix not positive definite") : 0;
+}
+
+/* basis values and parametric gradients of the live functions of element
+ * (ex, ey) at (xi, eta) for degree q: R[la], dR[la][2], la = a + (q+1) b
+ * (a along xi); W includes every live function (boundary ones too) */
+static void nurbs_live(const double *t, int q, const double *wts, int ex, int ey, double xi, double eta,
+                       double *R, double *dR) {
+    double vx[16], dx[16], vy[16], dy[16];
+    live_basis(t, q, ex, xi, vx, dx);
+    live_basis(t, q, ey, eta, vy, dy);
+    double W = 0, Wx = 0, Wy = 0;
+    int nl = q + 1;
+    for (int b = 0; b < nl; b++)
+        for (int a = 0; a < nl; a++) {
+            double w = wts[ex + a];   /* w_ij = w_i (xi) x 1 (eta) */
+            W += w * vx[a] * vy[b];
+            Wx += w * dx[a] * vy[b];
+            Wy += w * vx[a] * dy[b];
+        }
+    for (int b = 0; b < nl; b++)
+        for (int a = 0; a < nl; a++) {
+            double w = wts[ex + a];
+            double Nv = vx[a] * vy[b];
+            int la = a + nl * b;
+            R[la] = w * Nv / W;
+            dR[2 * la + 0] = w * (dx[a] * vy[b] * W - Nv * Wx) / (W * W);
+            dR[2 * la + 1] = w * (vx[a] * dy[b] * W - Nv * Wy) / (W * W);
+        }
+}
+
+/* Jacobian of F at (xi, eta): J[0]=dx/dxi J[1]=dx/deta J[2]=dy/dxi J[3]=dy/deta */
+static void annulus_map(double rin, double rout, double xi, double eta, double *x, double *y, double *J) {
+    double c, s, dc, ds;
+    circle_arc(xi, &c, &s, &dc, &ds);
+    double rho = rin + (rout - rin) * eta;
+    *x = rho * c; *y = rho * s;
+    J[0] = rho * dc; J[1] = (rout - rin) * c;
+    J[2] = rho * ds; J[3] = (rout - rin) * s;
+}
+
+/*
+ * Bilinear form between the interior functions of degree qa (rows) and qb
+ * (columns) on the annulus, stored by offset in [-qa, qb]^2 with width
+ * qa+qb+1 per direction (for qa == qb this is the symmetric offset storage
+ * of radius q).  kind: OR_STIFF or OR_MASS.  pf: the fine degree (fixes the
+ * quadrature).
+ */
+static int annulus_form(int qa, int qb, int pf, int m, double rin, double rout, int kind, double *out) {
+    int n1a = m + qa - 2, n1b = m + qb - 2, wd = qa + qb + 1;
+    long W = (long)wd * wd;
+    memset(out, 0, sizeof(double) * (long)n1a * n1a * W);
+    double *ta = malloc(sizeof(double) * (2 * qa + m + 1)), *tb = malloc(sizeof(double) * (2 * qb + m + 1));
+    double *wa = malloc(sizeof(double) * (m + qa)), *wb = malloc(sizeof(double) * (m + qb));
+    or_knots(qa, m, ta); or_knots(qb, m, tb);
+    if (or_annulus_weights(qa, m, wa) || or_annulus_weights(qb, m, wb)) { free(ta); free(tb); free(wa); free(wb); return 1; }
+    int nq = OR_ANN_QPTS(pf);
+    double gx[64], gw[64];
+    or_gauss_legendre(nq, gx, gw);
+    double h = 1.0 / m;
+    int nla = qa + 1, nlb = qb + 1;
+    double Ra[256], dRa[512], Rb[256], dRb[512];
+    for (int ey = 0; ey < m; ey++)
+        for (int ex = 0; ex < m; ex++)
+            for (int ky = 0; ky < nq; ky++)
+                for (int kx = 0; kx < nq; kx++) {
+                    double xi = (ex + 0.5 * (gx[kx] + 1.0)) * h, eta = (ey + 0.5 * (gx[ky] + 1.0)) * h;
+                    double wq = 0.25 * h * h * gw[kx] * gw[ky];
+                    double X, Y, J[4];
+                    annulus_map(rin, rout, xi, eta, &X, &Y, J);
+                    double det = J[0] * J[3] - J[1] * J[2];
+                    /* (J^T J)^{-1} */
+                    double g00 = J[0] * J[0] + J[2] * J[2], g01 = J[0] * J[1] + J[2] * J[3], g11 = J[1] * J[1] + J[3] * J[3];
+                    double gd = g00 * g11 - g01 * g01;
+                    double i00 = g11 / gd, i01 = -g01 / gd, i11 = g00 / gd;
+                    nurbs_live(ta, qa, wa, ex, ey, xi, eta, Ra, dRa);
+                    nurbs_live(tb, qb, wb, ex, ey, xi, eta, Rb, dRb);
+                    for (int bA = 0; bA < nla; bA++)
+                        for (int aA = 0; aA < nla; aA++) {
+                            int I = ex + aA - 1, Jr = ey + bA - 1;
+                            if (I < 0 || I >= n1a || Jr < 0 || Jr >= n1a) continue;
+                            int la = aA + nla * bA;
+                            for (int bB = 0; bB < nlb; bB++)
+                                for (int aB = 0; aB < nlb; aB++) {
+                                    int K = ex + aB - 1, L = ey + bB - 1;
+                                    if (K < 0 || K >= n1b || L < 0 || L >= n1b) continue;
+                                    int lb = aB + nlb * bB;
+                                    double v;
+                                    if (kind == OR_STIFF) {
+                                        double ax = dRa[2 * la], ay = dRa[2 * la + 1], bx = dRb[2 * lb], by = dRb[2 * lb + 1];
+                                        v = (ax * (i00 * bx + i01 * by) + ay * (i01 * bx + i11 * by)) * fabs(det);
+                                    } else {
+                                        v = Ra[la] * Rb[lb] * fabs(det);
+                                    }
+                                    long off = (long)(K - I + qa) + (long)(L - Jr + qa) * wd;
+                                    out[((long)Jr * n1a + I) * W + off] += wq * v;
+                                }
+                        }
+                }
+    free(ta); free(tb); free(wa); free(wb);
+    return 0;
+}
+
+/* the exact solution of the annulus experiment and minus its Laplacian
+ * (Section 5.2): u = sin(pi x) sin(pi y) (x^2+y^2-r^2)(x^2+y^2-R^2) */
+static double annulus_exact(double x, double y, double rin, double rout) {
+    double s = x * x + y * y;
+    return sin(M_PI * x) * sin(M_PI * y) * (s - rin * rin) * (s - rout * rout);
+}
+static double annulus_f(double x, double y, double rin, double rout) {
+    double s = x * x + y * y, S = sin(M_PI * x) * sin(M_PI * y);
+    double Q = (s - rin * rin) * (s - rout * rout);
+    double Sx = M_PI * cos(M_PI * x) * sin(M_PI * y), Sy = M_PI * sin(M_PI * x) * cos(M_PI * y);
+    double dQ = 2 * s - rin * rin - rout * rout;           /* dQ/ds */
+    double Qx = dQ * 2 * x, Qy = dQ * 2 * y;
+    double lapS = -2 * M_PI * M_PI * S, lapQ = 16 * s - 4 * (rin * rin + rout * rout);
+    return -(Q * lapS + 2 * (Sx * Qx + Sy * Qy) + S * lapQ);
+}
+
+/* load vector b_i = int f R_i |det J| (interior functions, degree p) */
+int or_load_annulus(int p, int m, double rin, double rout, double *bvec) {
+    int n1 = m + p - 2;
+    memset(bvec, 0, sizeof(double) * (long)n1 * n1);
+    double *t = malloc(sizeof(double) * (2 * p + m + 1)), *wts = malloc(sizeof(double) * (m + p));
+    or_knots(p, m, t);
+    if (or_annulus_weights(p, m, wts)) { free(t); free(wts); return 1; }
+    int nq = OR_ANN_QPTS(p), nl = p + 1;
+    double gx[64], gw[64], R[256], dR[512];
+    or_gauss_legendre(nq, gx, gw);
+    double h = 1.0 / m;
+    for (int ey = 0; ey < m; ey++)
+        for (int ex = 0; ex < m; ex++)
+            for (int ky = 0; ky < nq; ky++)
+                for (int kx = 0; kx < nq; kx++) {
+                    double xi = (ex + 0.5 * (gx[kx] + 1.0)) * h, eta = (ey + 0.5 * (gx[ky] + 1.0)) * h;
+                    double wq = 0.25 * h * h * gw[kx] * gw[ky];
+                    double X, Y, J[4];
+                    annulus_map(rin, rout, xi, eta, &X, &Y, J);
+                    double det = fabs(J[0] * J[3] - J[1] * J[2]);
+                    double f = annulus_f(X, Y, rin, rout);
+                    nurbs_live(t, p, wts, ex, ey, xi, eta, R, dR);
+                    for (int b = 0; b < nl; b++)
+                        for (int a = 0; a < nl; a++) {
+                            int I = ex + a - 1, Jr = ey + b - 1;
+                            if (I < 0 || I >= n1 || Jr < 0 || Jr >= n1) continue;
+                            bvec[(long)Jr * n1 + I] += wq * f * R[a + nl * b] * det;
+                        }
+                }
+    free(t); free(wts);
+    return 0;
+}
+
+/* || u_h - u ||_{L2(Omega)} for the coefficient vector u (interior, degree p) */
+double or_l2_error_annulus(int p, int m, double rin, double rout, const double *u) {
+    int n1 = m + p - 2;
+    double *t = malloc(sizeof(double) * (2 * p + m + 1)), *wts = malloc(sizeof(double) * (m + p));
+    or_knots(p, m, t);
+    if (or_annulus_weights(p, m, wts)) { free(t); free(wts); return -1.0; }
+    int nq = OR_ANN_QPTS(p), nl = p + 1;
+    double gx[64], gw[64], R[256], dR[512];
+    or_gauss_legendre(nq, gx, gw);
+    double h = 1.0 / m, err = 0.0;
+    for (int ey = 0; ey < m; ey++)
+        for (int ex = 0; ex < m; ex++)
+            for (int ky = 0; ky < nq; ky++)
+                for (int kx = 0; kx < nq; kx++) {
+                    double xi = (ex + 0.5 * (gx[kx] + 1.0)) * h, eta = (ey + 0.5 * (gx[ky] + 1.0)) * h;
+                    double wq = 0.25 * h * h * gw[kx] * gw[ky];
+                    double X, Y, J[4];
+                    annulus_map(rin, rout, xi, eta, &X, &Y, J);
+                    double det = fabs(J[0] * J[3] - J[1] * J[2]);
+                    nurbs_live(t, p, wts, ex, ey, xi, eta, R, dR);
+                    double uh = 0.0;
+                    for (int b = 0; b < nl; b++)
+                        for (int a = 0; a < nl; a++) {
+                            int I = ex + a - 1, Jr = ey + b - 1;
+                            if (I < 0 || I >= n1 || Jr < 0 || Jr >= n1) continue;
+                            uh += u[(long)Jr * n1 + I] * R[a + nl * b];
+                        }
+                    double d = uh - annulus_exact(X, Y, rin, rout);
+                    err += wq * d * d * det;
+                }
+    free(t); free(wts);
+    return sqrt(err);
+}
+
+/* the physical point of parameter (xi, eta) and the NURBS curve of the arc
+ * evaluated by the rational formula of Section 2.2 (pins the map) */
+void or_annulus_point(double rin, double rout, double xi, double eta, double *xy) {
+    double J[4];
+    annulus_map(rin, rout, xi, eta, &xy[0], &xy[1], J);
+}
+
+/* assembled annulus operators, for tests: kind 0 stiffness, 1 mass, 2 mixed
+ * mass (rows degree plow, columns degree p), by offset as in or_create */
+int or_assemble_annulus(int p, int plow, int m, double rin, double rout, int kind, double *out) {
+    if (kind == 2) return annulus_form(plow, p, p, m, rin, rout, OR_MASS, out);
+    return annulus_form(p, p, p, m, rin, rout, kind == 0 ? OR_STIFF : OR_MASS, out);
+}
+
+/*
+ * The two-level problem on the annulus (Section 5.2): degree p on the fine
+ * level, plow (2 in the paper) on the coarse level, both NURBS spaces over
+ * the same m x m elements; A, Alow, Mlow and Mmix from the forms above,
+ * everything else (Schwarz blocks, lumped restriction, exact coarse solve)
+ * as for the square.  The V-cycle hierarchy of the degree-1 coarse problem
+ * is for the square only.
+ */
+or_problem *or_create_annulus(int p, int m, int plow, int block_width, int lumped, int want_coarse_direct,
+                              double rin, double rout) {
+    const int d = 2;
+    if (p < 2 || p > 8 || m < 2 || plow < 1 || plow > p || !(rin > 0.0) || !(rout > rin)) {
+        fail("or_create_annulus: bad arguments"); return NULL;
+    }
+    if (block_width < 0 || (block_width && block_width % 2 == 0)) { fail("or_create_annulus: block width must be odd"); return NULL; }
+    or_problem *P = calloc(1, sizeof *P);
+    P->d = d; P->p = p; P->m = m; P->plow = plow;
+    P->bw = block_width ? block_width : or_default_block_width(p);
+    P->lumped = lumped;
+    P->n1 = m + p - 2; P->n1c = m + plow - 2;
+    P->n = ipow(P->n1, d); P->nc = ipow(P->n1c, d); P->ne = ipow(m, d);
+    P->W = ipow(2 * p + 1, d); P->Wc = ipow(2 * plow + 1, d); P->Wm = ipow(p + plow + 1, d);
+    if (P->n1 < 1 || P->n1c < 1) { fail("or_create_annulus: mesh too small"); free(P); return NULL; }
+    P->kappa = malloc(sizeof(double) * P->ne);
+    for (long e = 0; e < P->ne; e++) P->kappa[e] = 1.0;
+    P->A = malloc(sizeof(double) * P->n * P->W);
+    P->Alow = malloc(sizeof(double) * P->nc * P->Wc);
+    P->Mlow = malloc(sizeof(double) * P->nc * P->Wc);
+    P->Mmix = malloc(sizeof(double) * P->nc * P->Wm);
+    P->Dlump = malloc(sizeof(double) * P->nc);
+    if (!P->A || !P->Alow || !P->Mlow || !P->Mmix || !P->Dlump) { fail("or_create_annulus: out of memory"); or_destroy(P); return NULL; }
+    if (annulus_form(p, p, p, m, rin, rout, OR_STIFF, P->A) ||
+        annulus_form(plow, plow, p, m, rin, rout, OR_STIFF, P->Alow) ||
+        annulus_form(plow, plow, p, m, rin, rout, OR_MASS, P->Mlow) ||
+        annulus_form(plow, p, p, m, rin, rout, OR_MASS, P->Mmix)) { or_destroy(P); return NULL; }
+    for (long i = 0; i < P->nc; i++) {
+        double s = 0.0;
+        for (long w = 0; w < P->Wc; w++) s += P->Mlow[i * P->Wc + w];
+        P->Dlump[i] = s;
+    }
+    if (build_blocks(P)) { or_destroy(P); return NULL; }
+    if (want_coarse_direct) {
+        P->coarse_chol = band_factor_stencil(d, P->n1c, plow, P->Alow);
+        if (!P->coarse_chol) { fail("or_create_annulus: coarse factorisation failed"); or_destroy(P); return NULL; }
+    }
+    if (!lumped) {
+        P->mass_chol = band_factor_stencil(d, P->n1c, plow, P->Mlow);
+        if (!P->mass_chol) { fail("or_create_annulus: mass factorisation failed"); or_destroy(P); return NULL; }
+    }
+    return P;
+}
