@@ -116,6 +116,29 @@ int iga2l_assemble(int dim, const double *const *knots, const int *nknots, int p
                    const double *kappa, int device, iga2l_problem **out);
 
 /*
+ * The quarter-annulus problem of Section 5.2: -Laplace u = f on
+ * {r_in^2 <= x^2 + y^2 <= r_out^2, x, y >= 0}, u = 0 on the boundary,
+ * discretised with the NURBS space of Section 2.2 (eq. for R_ij^p): the
+ * exact quadratic-NURBS geometry (the quarter circle as the rational
+ * quadratic with weights 1, sqrt(2)/2, 1 along the angular parameter, linear
+ * along the radial one) raised to degree p with maximal smoothness on m x m
+ * elements, the Dirichlet functions removed (n_fine = (m+p-2)^2, x index =
+ * angular parameter, fastest).  The coarse level is the degree-2 NURBS space
+ * on the same elements (Section 5.2: p_low = 2), reached by the lumped L2
+ * transfers of Section 3.1.2; setup_blocks / solve then need opts->plow = 2,
+ * lumped = 1, coarse = COARSE_DIRECT (solved exactly, by fast
+ * diagonalisation of the tensor-sum coarse operator) and no aggressive
+ * coarsening.  The Schwarz blocks invert each block of the assembled operator
+ * (no shared interior inverse).  Integrals use p+3 Gauss points per element
+ * and direction.  solve_backward works without its grad_kappa output.
+ *   p       fine degree, 2..8;  m  elements per direction, >= 2;
+ *   r_in, r_out  radii, 0 < r_in < r_out (the paper: 0.3, 0.5);
+ *   device  HIP device ordinal.
+ * Errors: EINVAL (m < 2, radii, NULL out), EUNSUPPORTED (p), ENOMEM, EDEVICE.
+ */
+int iga2l_assemble_annulus(int p, int m, double r_in, double r_out, int device, iga2l_problem **out);
+
+/*
  * Build the Schwarz blocks of Section 3.1.1 (one block per DOF: the DOFs
  * within (block_width-1)/2 of it in every direction, truncated at the
  * boundary) and invert every block matrix A^{B_j} = V_j A V_j^T on the device,

@@ -88,6 +88,8 @@ _EXPORTS = {
     "iga2l_last_error": (ctypes.c_char_p, []),
     "iga2l_assemble": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int),
                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "iga2l_assemble_annulus": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
     "iga2l_setup_blocks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(CIgaOpts)]),
     "iga2l_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64)]),
@@ -163,8 +165,21 @@ def open_uniform_knots(p: int, m: int) -> np.ndarray:
 class Problem:
     """An assembled problem on one device (``iga2l_assemble``)."""
 
-    def __init__(self, dim: int, p: int, m: int, kappa=None, device: int = 0):
+    def __init__(self, dim: int, p: int, m: int, kappa=None, device: int = 0, annulus=None):
+        """annulus=(r_in, r_out): the quarter-annulus NURBS problem
+        (``iga2l_assemble_annulus``; dim must be 2, no kappa)."""
         self.dim, self.p, self.m, self.device = dim, p, m, device
+        if annulus is not None:
+            if dim != 2 or kappa is not None:
+                raise ValueError("the annulus problem is 2-D without a coefficient")
+            h = ctypes.c_void_p()
+            _check(lib().iga2l_assemble_annulus(p, m, float(annulus[0]), float(annulus[1]), device,
+                                                ctypes.byref(h)))
+            self._h = h
+            nf, nc, ne = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+            _check(lib().iga2l_sizes(self._h, ctypes.byref(nf), ctypes.byref(nc), ctypes.byref(ne)))
+            self.n, self.nc, self.ne = nf.value, nc.value, ne.value
+            return
         t = open_uniform_knots(p, m)
         self._knots = [np.ascontiguousarray(t, dtype=np.float64) for _ in range(dim)]
         kptrs = (ctypes.c_void_p * dim)(*[k.ctypes.data for k in self._knots])

@@ -90,6 +90,9 @@ void check_opts(const Problem &P, const iga2l_opts &o) {
     IGA2L_REQUIRE(o.plow == 1 || o.plow <= P.p, IGA2L_EINVAL, "plow may not exceed p");
     IGA2L_REQUIRE(o.plow == 1 || (o.coarse == IGA2L_COARSE_DIRECT && !o.aggressive), IGA2L_EUNSUPPORTED,
                   "the degree-2 coarse space is solved exactly (coarse = COARSE_DIRECT, no aggressive coarsening)");
+    if (P.geometry == kGeomAnnulus)
+        IGA2L_REQUIRE(o.plow == 2 && o.lumped == 1, IGA2L_EUNSUPPORTED,
+                      "the annulus uses the degree-2 coarse space (plow = 2) with the lumped transfers");
 }
 
 // Applies the exact (not lumped) transfers while a call runs.
@@ -430,6 +433,40 @@ int iga2l_assemble(int dim, const double *const *knots, const int *nknots, int p
     });
 }
 
+int iga2l_assemble_annulus(int p, int m, double r_in, double r_out, int device, iga2l_problem **out) {
+    return guarded([&] {
+        IGA2L_REQUIRE(out, IGA2L_EINVAL, "out is NULL");
+        *out = nullptr;
+        IGA2L_REQUIRE(p >= 2 && p <= kMaxP, IGA2L_EUNSUPPORTED, "annulus degree must be 2..8");
+        IGA2L_REQUIRE(m >= 2, IGA2L_EINVAL, "need at least 2 elements per direction");
+        IGA2L_REQUIRE(std::isfinite(r_in) && std::isfinite(r_out) && r_in > 0.0 && r_out > r_in, IGA2L_EINVAL,
+                      "radii must satisfy 0 < r_in < r_out");
+        const auto t_start = std::chrono::steady_clock::now();
+        auto *h = new iga2l_problem();
+        try {
+            Problem &P = h->P;
+            P.device = device;
+            P.dim = 2;
+            P.p = p;
+            P.m = m;
+            P.geometry = kGeomAnnulus;
+            P.r_in = r_in;
+            P.r_out = r_out;
+            P.kappa_one = false;   // no interior stencil: the annulus rows all differ
+            P.kappa.assign(size_t(m) * m, 1.0);
+            set_device(P);
+            host_assemble(P);
+            P.layout_id = next_layout_id();
+            IGA2L_HIP(hipDeviceSynchronize());
+            P.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
 int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *opts) {
     return guarded([&] {
         IGA2L_REQUIRE(prob, IGA2L_EINVAL, "problem is NULL");
@@ -482,6 +519,10 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             launch_convert(P.Inv64.ptr, P.Inv32.ptr, P.nslots * P.bd * P.bd, true, s);
             P.R1d32.alloc(P.R1.size() * sizeof(float));
             launch_convert(P.R1d64.ptr, P.R1d32.ptr, int64_t(P.R1.size()), true, s);
+            if (P.geometry == kGeomAnnulus) {
+                P.R1yd32.alloc(P.R1y.size() * sizeof(float));
+                launch_convert(P.R1yd64.ptr, P.R1yd32.ptr, int64_t(P.R1y.size()), true, s);
+            }
             P.dc64.alloc(size_t(P.coarse.n) * sizeof(double));
             P.ec64.alloc(size_t(P.coarse.n) * sizeof(double));
             IGA2L_HIP(hipStreamSynchronize(s));
@@ -498,7 +539,7 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
                           "unknowns)");
             if (o.coarse == IGA2L_COARSE_DIRECT && !P.agg_direct_ready) host_build_agg_direct(P);
         } else if (o.coarse == IGA2L_COARSE_DIRECT && !P.direct_ready) {
-            IGA2L_REQUIRE(P.kappa_one, IGA2L_EUNSUPPORTED,
+            IGA2L_REQUIRE(P.kappa_one || P.geometry == kGeomAnnulus, IGA2L_EUNSUPPORTED,
                           "the exact coarse solve needs kappa = 1; use the V-cycle for variable kappa");
             host_build_dst(P);
         }
@@ -747,6 +788,8 @@ int iga2l_solve_backward(const iga2l_problem *prob, const double *u, const doubl
     return guarded([&] {
         IGA2L_REQUIRE(prob && u && grad_u && lambda, IGA2L_EINVAL, "null argument");
         Problem &P = const_cast<Problem &>(prob->P);
+        IGA2L_REQUIRE(!grad_kappa || P.geometry == kGeomSquare, IGA2L_EUNSUPPORTED,
+                      "the coefficient gradient is defined on the square (the annulus has no kappa)");
         iga2l_opts o = effective_opts(opts);
         check_opts(P, o);
         set_device(P);

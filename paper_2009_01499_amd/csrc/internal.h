@@ -116,6 +116,13 @@ struct Problem {
     Grid fine, coarse;      // fine: n1 = m+p-2; coarse: n1 = m-1 (degree 1)
     int64_t ne = 0;
     bool kappa_one = true;
+    // geometry: the unit square (B-splines) or the quarter annulus of radii
+    // r_in < r_out (NURBS, Section 5.2).  For the annulus the operator and the
+    // transfers are tensor sums/products of direction-dependent 1-D factors:
+    // K1, M1, R1 hold the angular (x) direction, K1y, M1y, R1y the radial (y)
+    int geometry = 0;   // kGeomSquare or kGeomAnnulus
+    double r_in = 0.0, r_out = 0.0;
+    std::vector<double> K1y, M1y, R1y;
     std::vector<double> kappa;
 
     // host copies of the 1-D factors (per direction identical)
@@ -127,6 +134,8 @@ struct Problem {
 
     SymDia A;                     // fine stiffness
     DevBuf R1d64, R1d32;          // restriction factor on the device
+    DevBuf R1yd64, R1yd32;        // the radial factor of the annulus (empty otherwise: R1 serves every axis)
+    int64_t fdm_axis_stride = 0;  // fast diagonalisation: 0 one matrix for every axis, n1c^2 one per axis
     DevBuf Ke_d, Me_d;            // 1-D element matrices (FP64) for the gradient kernel
     DevBuf kappa_d;
 
@@ -347,6 +356,7 @@ void solve_batch_fused(Problem *const *probs, int nprob, const double *const *b,
                        const iga2l_opts &o, iga2l_info *infos, hipStream_t s, int &worst, std::string &msg);
 
 // ------------------------------------------------------------ host set-up --
+enum { kGeomSquare = 0, kGeomAnnulus = 1 };
 void host_assemble(Problem &P);                 // 1-D factors, DIA, transfers, kappa
 void host_build_levels(Problem &P);             // V-cycle hierarchy (Galerkin)
 void host_build_dst(Problem &P);                // exact coarse solver (kappa = 1)

@@ -20,8 +20,8 @@ inline unsigned nblocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 // d_c[I] = sum_a R1[Ix][ax] R1[Iy][ay] (R1[Iz][az]) d[I - plow + a],
 // a in [0, p+plow]^D (coarse space of degree plow)
 template <int D, class T>
-__global__ void k_restrict(const T *__restrict__ R1, int p, int plow, int n1f, int n1c, const T *__restrict__ df,
-                           T *__restrict__ dc, const int *__restrict__ skip) {
+__global__ void k_restrict(const T *__restrict__ R1, const T *__restrict__ R1y, int p, int plow, int n1f, int n1c,
+                           const T *__restrict__ df, T *__restrict__ dc, const int *__restrict__ skip) {
     const int stop = skip ? *skip : 0;  // tested before the store (hides the load latency)
     const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nc = (D == 3) ? int64_t(n1c) * n1c * n1c : int64_t(n1c) * n1c;
@@ -32,11 +32,11 @@ __global__ void k_restrict(const T *__restrict__ R1, int p, int plow, int n1f, i
     for (int az = 0; az < ((D == 3) ? w : 1); ++az) {
         const int jz = (D == 3) ? Iz - plow + az : 0;
         if (D == 3 && (jz < 0 || jz >= n1f)) continue;
-        const T rz = (D == 3) ? R1[Iz * w + az] : T(1);
+        const T rz = (D == 3) ? R1y[Iz * w + az] : T(1);
         for (int ay = 0; ay < w; ++ay) {
             const int jy = Iy - plow + ay;
             if (jy < 0 || jy >= n1f) continue;
-            const T ry = R1[Iy * w + ay] * rz;
+            const T ry = R1y[Iy * w + ay] * rz;
             T line = T(0);
             for (int ax = 0; ax < w; ++ax) {
                 const int jx = Ix - plow + ax;
@@ -54,16 +54,16 @@ __global__ void k_restrict(const T *__restrict__ R1, int p, int plow, int n1f, i
 // of R1[Ix][ix-Ix+plow] R1[Iy][iy-Iy+plow] (..) e_c[I]: the exact transpose of
 // k_restrict.
 template <int D, class T>
-__device__ __forceinline__ T prolong_value(const T *__restrict__ R1, int p, int plow, int n1f, int n1c,
-                                           const T *__restrict__ ec, int ix, int iy, int iz) {
+__device__ __forceinline__ T prolong_value(const T *__restrict__ R1, const T *__restrict__ R1y, int p, int plow,
+                                           int n1f, int n1c, const T *__restrict__ ec, int ix, int iy, int iz) {
     const int w = p + plow + 1;
     T acc = T(0);
     for (int Iz = ((D == 3) ? iz - p : 0); Iz <= ((D == 3) ? iz + plow : 0); ++Iz) {
         if (D == 3 && (Iz < 0 || Iz >= n1c)) continue;
-        const T rz = (D == 3) ? R1[Iz * w + (iz - Iz + plow)] : T(1);
+        const T rz = (D == 3) ? R1y[Iz * w + (iz - Iz + plow)] : T(1);
         for (int Iy = iy - p; Iy <= iy + plow; ++Iy) {
             if (Iy < 0 || Iy >= n1c) continue;
-            const T ry = R1[Iy * w + (iy - Iy + plow)] * rz;
+            const T ry = R1y[Iy * w + (iy - Iy + plow)] * rz;
             T line = T(0);
             for (int Ix = ix - p; Ix <= ix + plow; ++Ix) {
                 if (Ix < 0 || Ix >= n1c) continue;
@@ -76,27 +76,27 @@ __device__ __forceinline__ T prolong_value(const T *__restrict__ R1, int p, int 
 }
 
 template <int D, class T>
-__global__ void k_prolong_add(const T *__restrict__ R1, int p, int plow, int n1f, int n1c, const T *__restrict__ ec,
-                              T *__restrict__ uf, const int *__restrict__ skip) {
+__global__ void k_prolong_add(const T *__restrict__ R1, const T *__restrict__ R1y, int p, int plow, int n1f, int n1c,
+                              const T *__restrict__ ec, T *__restrict__ uf, const int *__restrict__ skip) {
     if (skip && *skip) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nf = (D == 3) ? int64_t(n1f) * n1f * n1f : int64_t(n1f) * n1f;
     if (i >= nf) return;
     const int ix = int(i % n1f), iy = int((i / n1f) % n1f), iz = (D == 3) ? int(i / (int64_t(n1f) * n1f)) : 0;
-    uf[i] += prolong_value<D, T>(R1, p, plow, n1f, n1c, ec, ix, iy, iz);
+    uf[i] += prolong_value<D, T>(R1, R1y, p, plow, n1f, n1c, ec, ix, iy, iz);
 }
 
 // u64 += sigma * (e + P e_c): end of a correction cycle
 template <int D, class T>
-__global__ void k_prolong_update(const T *__restrict__ R1, int p, int plow, int n1f, int n1c,
-                                 const T *__restrict__ ec, const T *__restrict__ e, double *__restrict__ u,
+__global__ void k_prolong_update(const T *__restrict__ R1, const T *__restrict__ R1y, int p, int plow, int n1f,
+                                 int n1c, const T *__restrict__ ec, const T *__restrict__ e, double *__restrict__ u,
                                  const double *__restrict__ scal, int scaled, const int *__restrict__ skip) {
     const int stop = skip ? *skip : 0;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nf = (D == 3) ? int64_t(n1f) * n1f * n1f : int64_t(n1f) * n1f;
     if (i >= nf) return;
     const int ix = int(i % n1f), iy = int((i / n1f) % n1f), iz = (D == 3) ? int(i / (int64_t(n1f) * n1f)) : 0;
-    const T corr = e[i] + prolong_value<D, T>(R1, p, plow, n1f, n1c, ec, ix, iy, iz);
+    const T corr = e[i] + prolong_value<D, T>(R1, R1y, p, plow, n1f, n1c, ec, ix, iy, iz);
     if (stop) return;
     u[i] += scaled ? scal[kScalSigma] * double(corr) : double(corr);
 }
@@ -320,6 +320,10 @@ __global__ void k_galerkin(const double *__restrict__ Sf, int nf1, double *__res
 
 // the 1-D transfer factor: D1^{-1} Mmix1 (lumped), or Mmix1 when the exact
 // transfers apply M_1^{-1} separately
+// the factor of the y (and z) axis: the annulus's radial one, else R1
+template <class T>
+const T *R1y_of(const Problem &P);
+
 template <class T>
 const T *R1_of(const Problem &P) {
     if (P.transfer_exact)
@@ -329,6 +333,13 @@ const T *R1_of(const Problem &P) {
                                           : reinterpret_cast<const T *>(P.R1d32.ptr);
 }
 
+template <class T>
+const T *R1y_of(const Problem &P) {
+    if (P.geometry != kGeomAnnulus) return R1_of<T>(P);
+    return std::is_same<T, double>::value ? reinterpret_cast<const T *>(P.R1yd64.ptr)
+                                          : reinterpret_cast<const T *>(P.R1yd32.ptr);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers --
@@ -336,42 +347,42 @@ const T *R1_of(const Problem &P) {
 // kernels_2d.hip; otherwise one thread per output point
 template <class T>
 void launch_restrict(const Problem &P, const T *df, T *dc, hipStream_t s) {
-    if (P.dim == 2 && P.plow == 1) {
+    if (P.dim == 2 && P.plow == 1 && P.geometry == kGeomSquare) {
         launch_restrict2d<T>(P, df, dc, s);
         return;
     }
     const int64_t nc = P.coarse.n;
     auto kern = P.dim == 2 ? k_restrict<2, T> : k_restrict<3, T>;
-    hipLaunchKernelGGL(kern, dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.plow, P.fine.n1,
-                       P.coarse.n1, df, dc, P.skip);
+    hipLaunchKernelGGL(kern, dim3(nblocks(nc, 256)), dim3(256), 0, s, R1_of<T>(P), R1y_of<T>(P), P.p, P.plow,
+                       P.fine.n1, P.coarse.n1, df, dc, P.skip);
 }
 template void launch_restrict<double>(const Problem &, const double *, double *, hipStream_t);
 template void launch_restrict<float>(const Problem &, const float *, float *, hipStream_t);
 
 template <class T>
 void launch_prolong_add(const Problem &P, const T *ec, T *uf, hipStream_t s) {
-    if (P.dim == 2 && P.plow == 1) {
+    if (P.dim == 2 && P.plow == 1 && P.geometry == kGeomSquare) {
         launch_prolong2d<T>(P, ec, uf, nullptr, nullptr, false, s);
         return;
     }
     const int64_t nf = P.fine.n;
     auto kern = P.dim == 2 ? k_prolong_add<2, T> : k_prolong_add<3, T>;
-    hipLaunchKernelGGL(kern, dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.plow, P.fine.n1,
-                       P.coarse.n1, ec, uf, P.skip);
+    hipLaunchKernelGGL(kern, dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), R1y_of<T>(P), P.p, P.plow,
+                       P.fine.n1, P.coarse.n1, ec, uf, P.skip);
 }
 template void launch_prolong_add<double>(const Problem &, const double *, double *, hipStream_t);
 template void launch_prolong_add<float>(const Problem &, const float *, float *, hipStream_t);
 
 template <class T>
 void launch_prolong_update(const Problem &P, const T *ec, const T *e, double *u, bool scaled, hipStream_t s) {
-    if (P.dim == 2 && P.plow == 1) {
+    if (P.dim == 2 && P.plow == 1 && P.geometry == kGeomSquare) {
         launch_prolong2d<T>(P, ec, nullptr, e, u, scaled, s);
         return;
     }
     const int64_t nf = P.fine.n;
     auto kern = P.dim == 2 ? k_prolong_update<2, T> : k_prolong_update<3, T>;
-    hipLaunchKernelGGL(kern, dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), P.p, P.plow, P.fine.n1,
-                       P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0, P.skip);
+    hipLaunchKernelGGL(kern, dim3(nblocks(nf, 256)), dim3(256), 0, s, R1_of<T>(P), R1y_of<T>(P), P.p, P.plow,
+                       P.fine.n1, P.coarse.n1, ec, e, u, P.scal.as<double>(), scaled ? 1 : 0, P.skip);
 }
 template void launch_prolong_update<double>(const Problem &, const double *, const double *, double *, bool,
                                             hipStream_t);
@@ -385,20 +396,20 @@ template void launch_prolong_update<float>(const Problem &, const float *, const
 // Sb = nullptr: Sb = S (the DST-I is its own inverse); the fast
 // diagonalisation of the degree-2 space passes V^T forward and V backward.
 static void dst_apply(const double *S, const double *mu, int n1, int dim, const double *d, double *e, double *t1,
-                      const int *skip, hipStream_t s, const double *Sb = nullptr) {
+                      const int *skip, hipStream_t s, const double *Sb = nullptr, int64_t axis_stride = 0) {
     const int64_t n = (dim == 3) ? int64_t(n1) * n1 * n1 : int64_t(n1) * n1;
     const double *src = d;
     double *bufs[2] = {t1, e};
     int cur = 0;
     for (int ax = 0; ax < dim; ++ax) {
-        hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, S, n1, dim, ax, src, bufs[cur],
-                           (ax == dim - 1) ? mu : nullptr, skip);
+        hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, S + ax * axis_stride, n1, dim, ax, src,
+                           bufs[cur], (ax == dim - 1) ? mu : nullptr, skip);
         src = bufs[cur];
         cur = 1 - cur;
     }
     for (int ax = 0; ax < dim; ++ax) {
-        hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, Sb ? Sb : S, n1, dim, ax, src,
-                           bufs[cur], nullptr, skip);
+        hipLaunchKernelGGL(k_dst_axis, dim3(nblocks(n, 256)), dim3(256), 0, s, (Sb ? Sb : S) + ax * axis_stride, n1,
+                           dim, ax, src, bufs[cur], nullptr, skip);
         src = bufs[cur];
         cur = 1 - cur;
     }
@@ -414,7 +425,7 @@ void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s) {
     IGA2L_REQUIRE(P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");
     if (P.plow == 2)
         dst_apply(P.fdm_Vt.as<double>(), P.dst_mu.as<double>(), P.coarse.n1, P.dim, d, e, P.ctmp.as<double>(), P.skip,
-                  s, P.fdm_V.as<double>());
+                  s, P.fdm_V.as<double>(), P.fdm_axis_stride);
     else
         dst_apply(P.dst_S.as<double>(), P.dst_mu.as<double>(), P.coarse.n1, P.dim, d, e, P.ctmp.as<double>(), P.skip,
                   s);

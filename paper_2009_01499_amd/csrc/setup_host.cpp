@@ -133,6 +133,143 @@ void element_matrices(int p, int m, std::vector<std::vector<double>> &Ke, std::v
     }
 }
 
+// ------------------------------------------------------------ annulus --
+// The quarter annulus (Section 5.2) is the image of the unit square under
+// F(xi, eta) = rho(eta) (c(xi), s(xi)), rho = r_in + (r_out - r_in) eta, with
+// (c, s) the quarter of the unit circle written as the rational quadratic
+// (control points (1,0), (1,1), (0,1), weights 1, sqrt(2)/2, 1).  The
+// NURBS basis of degree q on m elements is R_ij = w_i N_i(xi) N_j(eta) / w(xi):
+// the radial direction is linear, so the weight net is w_i x 1 and the
+// denominator is the arc's quadratic denominator w(xi), whose coefficients
+// in the degree-q basis are the w_i.  The columns of the Jacobian are
+// rho (c', s') and (r_out - r_in) (c, s), orthogonal, with |(c', s')| = the
+// arc's speed v(xi).  So int grad R_a . grad R_b dx pulls back to
+// int phi_i' phi_k' / v  x  int N_j N_l (r_out-r_in)/rho
+//   + int phi_i phi_k v  x  int N_j' N_l' rho/(r_out-r_in),
+// phi_i = w_i N_i / w, and int R_a R_b dx to int phi_i phi_k v x
+// int N_j N_l rho (r_out-r_in): tensor sums/products of weighted 1-D forms.
+// Quadrature: kAnnulusExtraPts more Gauss points per element than the fine
+// degree, in both directions and for every form of a problem.
+constexpr int kAnnulusExtraPts = 3;
+
+struct ArcPoint {
+    double w, dw, speed;
+};
+
+ArcPoint arc_point(double xi) {
+    const double r2 = std::sqrt(2.0), a = 1.0 - xi;
+    const double nx = a * a + r2 * xi * a, ny = r2 * xi * a + xi * xi, w = nx + xi * xi;
+    const double dnx = -2.0 * a + r2 * (1.0 - 2.0 * xi), dny = r2 * (1.0 - 2.0 * xi) + 2.0 * xi;
+    const double dw = dnx + 2.0 * xi;
+    const double dc = (dnx * w - nx * dw) / (w * w), ds = (dny * w - ny * dw) / (w * w);
+    return {w, dw, std::sqrt(dc * dc + ds * ds)};
+}
+
+// coefficients of the arc's denominator in the degree-q basis on m elements
+// (all m+q functions): L2 projection, Gram system by dense Cholesky
+std::vector<double> arc_weights(int q, int m) {
+    const int nb = m + q;
+    auto t = open_uniform_knots(q, m);
+    std::vector<double> G(size_t(nb) * nb, 0.0), g(nb, 0.0);
+    double gx[kMaxP + 4], gw[kMaxP + 4], v[kMaxP + 1];
+    const int nq = q + 2;   // exact for the degree-2q Gram entries
+    gauss_rule(nq, gx, gw);
+    for (int e = 0; e < m; ++e)
+        for (int k = 0; k < nq; ++k) {
+            const double x = (e + 0.5 * (gx[k] + 1.0)) / m, wq = 0.5 * gw[k] / m;
+            live_values(t, q, q + e, x, v, nullptr);
+            const double wx = arc_point(x).w;
+            for (int a = 0; a <= q; ++a) {
+                g[e + a] += wq * v[a] * wx;
+                for (int b = 0; b <= q; ++b) G[size_t(e + a) * nb + e + b] += wq * v[a] * v[b];
+            }
+        }
+    for (int j = 0; j < nb; ++j) {   // G = L L^T in place (lower)
+        double d = G[size_t(j) * nb + j];
+        for (int k = 0; k < j; ++k) d -= G[size_t(j) * nb + k] * G[size_t(j) * nb + k];
+        IGA2L_REQUIRE(d > 0.0, IGA2L_ENUMERIC, "annulus weights: Gram matrix not positive definite");
+        d = std::sqrt(d);
+        G[size_t(j) * nb + j] = d;
+        for (int i = j + 1; i < nb; ++i) {
+            double t2 = G[size_t(i) * nb + j];
+            for (int k = 0; k < j; ++k) t2 -= G[size_t(i) * nb + k] * G[size_t(j) * nb + k];
+            G[size_t(i) * nb + j] = t2 / d;
+        }
+    }
+    for (int i = 0; i < nb; ++i) {
+        double t2 = g[i];
+        for (int k = 0; k < i; ++k) t2 -= G[size_t(i) * nb + k] * g[k];
+        g[i] = t2 / G[size_t(i) * nb + i];
+    }
+    for (int i = nb - 1; i >= 0; --i) {
+        double t2 = g[i];
+        for (int k = i + 1; k < nb; ++k) t2 -= G[size_t(k) * nb + i] * g[k];
+        g[i] = t2 / G[size_t(i) * nb + i];
+    }
+    return g;
+}
+
+enum AnnForm { kAnnStiff = 0, kAnnOpMass = 1, kAnnL2Mass = 2 };
+
+// A weighted 1-D form on the annulus between the interior functions of
+// degree qa (rows) and qb (columns), by offset: out[i][j - i + qa], width
+// qa + qb + 1.  axis 0: angular (NURBS phi, weights as above), axis 1: radial
+// (B-splines).  Weights per form and axis:
+//   stiffness       1/v (angular)     rho/(r_out-r_in) (radial)
+//   operator mass   v                 (r_out-r_in)/rho
+//   L2 mass         v                 rho (r_out-r_in)
+std::vector<double> annulus_form_1d(const Problem &P, int qa, int qb, int axis, AnnForm form) {
+    const int m = P.m, n1a = m + qa - 2, n1b = m + qb - 2, wd = qa + qb + 1;
+    const double rin = P.r_in, dr = P.r_out - P.r_in;
+    auto ta = open_uniform_knots(qa, m), tb = open_uniform_knots(qb, m);
+    std::vector<double> wa, wb;
+    if (axis == 0) {
+        wa = arc_weights(qa, m);
+        wb = arc_weights(qb, m);
+    }
+    const int nq = P.p + kAnnulusExtraPts;
+    double gx[kMaxP + 4], gw[kMaxP + 4];
+    gauss_rule(nq, gx, gw);
+    std::vector<double> out(size_t(std::max(n1a, 0)) * wd, 0.0);
+    double va[kMaxP + 1], da[kMaxP + 1], vb[kMaxP + 1], db[kMaxP + 1];
+    for (int e = 0; e < m; ++e)
+        for (int k = 0; k < nq; ++k) {
+            const double x = (e + 0.5 * (gx[k] + 1.0)) / m, wq = 0.5 * gw[k] / m;
+            live_values(ta, qa, qa + e, x, va, da);
+            live_values(tb, qb, qb + e, x, vb, db);
+            double wgt;
+            if (axis == 0) {
+                const ArcPoint ap = arc_point(x);
+                // phi = w_i N / w, phi' = w_i (N' w - N w') / w^2
+                for (int a = 0; a <= qa; ++a) {
+                    const double om = wa[e + a];
+                    da[a] = om * (da[a] * ap.w - va[a] * ap.dw) / (ap.w * ap.w);
+                    va[a] = om * va[a] / ap.w;
+                }
+                for (int b = 0; b <= qb; ++b) {
+                    const double om = wb[e + b];
+                    db[b] = om * (db[b] * ap.w - vb[b] * ap.dw) / (ap.w * ap.w);
+                    vb[b] = om * vb[b] / ap.w;
+                }
+                wgt = (form == kAnnStiff) ? 1.0 / ap.speed : ap.speed;
+            } else {
+                const double rho = rin + dr * x;
+                wgt = (form == kAnnStiff) ? rho / dr : (form == kAnnOpMass ? dr / rho : rho * dr);
+            }
+            for (int a = 0; a <= qa; ++a) {
+                const int i = e + a - 1;
+                if (i < 0 || i >= n1a) continue;
+                for (int b = 0; b <= qb; ++b) {
+                    const int j = e + b - 1;
+                    if (j < 0 || j >= n1b) continue;
+                    const double f = (form == kAnnStiff) ? da[a] * db[b] : va[a] * vb[b];
+                    out[size_t(i) * wd + (j - i + qa)] += wq * wgt * f;
+                }
+            }
+        }
+    return out;
+}
+
 // linear index <-> multi-index over a box of extent n in each of dim directions
 inline void split(int64_t idx, int dim, int64_t n, int *out) {
     for (int k = 0; k < dim; ++k) {
@@ -155,6 +292,27 @@ void host_transfer_factors(Problem &P, int plow) {
     const int n1 = P.fine.n1, n1c = m + plow - 2, w = p + plow + 1;
     P.plow = plow;
     P.coarse = Grid{d, n1c, ipow(n1c, d)};
+    if (P.geometry == kGeomAnnulus) {
+        // per axis: the L2 mixed mass and the row sums of the L2 coarse mass
+        // (the 2-D mass is their tensor product, so is its row-sum lumping)
+        for (int axis = 0; axis < 2; ++axis) {
+            const auto mix = annulus_form_1d(P, plow, p, axis, kAnnL2Mass);
+            const auto mc = annulus_form_1d(P, plow, plow, axis, kAnnL2Mass);
+            std::vector<double> R(mix.size());
+            for (int I = 0; I < n1c; ++I) {
+                double lump = 0.0;
+                for (int a = 0; a < 2 * plow + 1; ++a) lump += mc[size_t(I) * (2 * plow + 1) + a];
+                for (int a = 0; a < w; ++a) R[size_t(I) * w + a] = mix[size_t(I) * w + a] / lump;
+            }
+            if (axis == 0) {
+                P.Mx1 = mix;
+                P.R1 = R;
+            } else {
+                P.R1y = R;
+            }
+        }
+        return;
+    }
     auto tf = open_uniform_knots(p, m), tc = open_uniform_knots(plow, m);
     double gx[kMaxP + 4], gw[kMaxP + 4];
     const int q = p + 1;   // exact for the degree p + plow <= 2p integrands
@@ -199,18 +357,29 @@ void host_assemble(Problem &P) {
 
     // interior 1-D factors K1, M1: entry (i, i+o) at [i][o+p]
     const int w1 = 2 * p + 1;
-    P.K1.assign(size_t(n1) * w1, 0.0);
-    P.M1.assign(size_t(n1) * w1, 0.0);
-    for (int e = 0; e < m; ++e)
-        for (int a = 0; a <= p; ++a)
-            for (int b = 0; b <= p; ++b) {
-                int i = e + a - 1, j = e + b - 1;
-                if (i < 0 || i >= n1 || j < 0 || j >= n1) continue;
-                P.K1[size_t(i) * w1 + (j - i + p)] += P.Ke[e][a * (p + 1) + b];
-                P.M1[size_t(i) * w1 + (j - i + p)] += P.Me[e][a * (p + 1) + b];
-            }
+    const bool annulus = P.geometry == kGeomAnnulus;
+    if (annulus) {
+        // angular factors in K1, M1, radial in K1y, M1y (operator weights)
+        P.K1 = annulus_form_1d(P, p, p, 0, kAnnStiff);
+        P.M1 = annulus_form_1d(P, p, p, 0, kAnnOpMass);
+        P.K1y = annulus_form_1d(P, p, p, 1, kAnnStiff);
+        P.M1y = annulus_form_1d(P, p, p, 1, kAnnOpMass);
+    } else {
+        P.K1.assign(size_t(n1) * w1, 0.0);
+        P.M1.assign(size_t(n1) * w1, 0.0);
+        for (int e = 0; e < m; ++e)
+            for (int a = 0; a <= p; ++a)
+                for (int b = 0; b <= p; ++b) {
+                    int i = e + a - 1, j = e + b - 1;
+                    if (i < 0 || i >= n1 || j < 0 || j >= n1) continue;
+                    P.K1[size_t(i) * w1 + (j - i + p)] += P.Ke[e][a * (p + 1) + b];
+                    P.M1[size_t(i) * w1 + (j - i + p)] += P.Me[e][a * (p + 1) + b];
+                }
+    }
 
-    host_transfer_factors(P, 1);
+    // the annulus is discretised with a degree-2 coarse space (its geometry is
+    // quadratic, Section 5.2); the square starts from degree 1
+    host_transfer_factors(P, annulus ? 2 : 1);
 
     // 1-D element matrices (assembly and gradient kernels): [m][2][(p+1)^2] (K then M)
     const int nl = p + 1;
@@ -237,9 +406,16 @@ void host_assemble(Problem &P) {
     A.pitch[1] = np1;
     A.pitch[2] = np1 * np1;
     A.npad = ipow(np1, d);
-    std::vector<double> val(P.kappa_one ? size_t(A.Wh) * A.npad : 0, 0.0);
+    const bool host_dia = P.kappa_one || annulus;
+    std::vector<double> val(host_dia ? size_t(A.Wh) * A.npad : 0, 0.0);
     const int c0 = (A.W - 1) / 2;
-    if (P.kappa_one) {
+    // factor of axis k: the stiffness one in the derivative's direction, the
+    // mass one elsewhere (the radial axis of the annulus has its own)
+    auto factor = [&](int k, bool stiff) -> const std::vector<double> & {
+        if (annulus && k == 1) return stiff ? P.K1y : P.M1y;
+        return stiff ? P.K1 : P.M1;
+    };
+    if (host_dia) {
         // kappa = 1: A = sum_c (x)_k (k == c ? K1 : M1), entry by entry from the
         // assembled 1-D factors (O(n Wh) instead of the element loop)
         int ix[kMaxDim] = {0, 0, 0}, o[kMaxDim] = {0, 0, 0};
@@ -261,7 +437,7 @@ void host_assemble(Problem &P) {
                 double term = 0.0;
                 for (int c = 0; c < d; ++c) {
                     double f[kMaxDim];
-                    for (int k = 0; k < d; ++k) f[k] = ((k == c) ? P.K1 : P.M1)[size_t(ix[k]) * w1 + o[k]];
+                    for (int k = 0; k < d; ++k) f[k] = factor(k, k == c)[size_t(ix[k]) * w1 + o[k]];
                     const double prod = (d == 3) ? f[0] * (f[1] * f[2]) : (d == 2) ? f[0] * f[1] : f[0];
                     term += prod;
                 }
@@ -362,6 +538,10 @@ void host_assemble(Problem &P) {
 
     P.R1d64.alloc(P.R1.size() * sizeof(double));
     IGA2L_HIP(hipMemcpy(P.R1d64.ptr, P.R1.data(), P.R1.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (annulus) {
+        P.R1yd64.alloc(P.R1y.size() * sizeof(double));
+        IGA2L_HIP(hipMemcpy(P.R1yd64.ptr, P.R1y.data(), P.R1y.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
 
     // workspaces sized by the fine grid
     const size_t nf = size_t(P.fine.n), nc = size_t(P.coarse.n);
@@ -405,6 +585,15 @@ void host_set_coarse_degree(Problem &P, int plow) {
         std::vector<float> f32(P.R1.begin(), P.R1.end());
         P.R1d32.alloc(f32.size() * sizeof(float));
         IGA2L_HIP(hipMemcpy(P.R1d32.ptr, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    if (P.geometry == kGeomAnnulus) {
+        P.R1yd64.alloc(P.R1y.size() * sizeof(double));
+        IGA2L_HIP(hipMemcpy(P.R1yd64.ptr, P.R1y.data(), P.R1y.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (P.fp32_ready) {
+            std::vector<float> f32(P.R1y.begin(), P.R1y.end());
+            P.R1yd32.alloc(f32.size() * sizeof(float));
+            IGA2L_HIP(hipMemcpy(P.R1yd32.ptr, f32.data(), f32.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
     }
     host_coarse_workspaces(P);
     P.vcycle_ready = P.direct_ready = P.mass_ready = P.agg_direct_ready = false;
@@ -461,80 +650,110 @@ static void jacobi_eigen(int n, std::vector<double> &C, std::vector<double> &Q) 
 // sum_c (x)_k (k == c ? K2 : M2) is then (V (x) V ..) diag(sum_k lambda_k)
 // (V (x) V ..)^T, inverted by one transform per axis each way ("fast
 // diagonalisation"); M2^{-1} = (V V^T) per direction for the exact transfers.
+// On the annulus each axis has its own weighted K2, M2 (the coarse operator is
+// K2x (x) M2y + M2x (x) K2y), hence its own V and eigenvalues.
 void host_build_fdm(Problem &P) {
     IGA2L_REQUIRE(P.plow == 2, IGA2L_EINVAL, "fast diagonalisation is the coarse solver of the degree-2 space");
-    IGA2L_REQUIRE(P.kappa_one, IGA2L_EUNSUPPORTED, "the exact degree-2 coarse solve needs kappa = 1");
+    const bool annulus = P.geometry == kGeomAnnulus;
+    IGA2L_REQUIRE(P.kappa_one || annulus, IGA2L_EUNSUPPORTED, "the exact degree-2 coarse solve needs kappa = 1");
     const int m = P.m, n = P.coarse.n1, d = P.dim;
     IGA2L_REQUIRE(n <= 1024, IGA2L_EUNSUPPORTED, "degree-2 coarse space limited to m <= 1024");
-    std::vector<std::vector<double>> Ke, Me;
-    element_matrices(2, m, Ke, Me);
-    std::vector<double> K(size_t(n) * n, 0.0), M(size_t(n) * n, 0.0);
-    for (int e = 0; e < m; ++e)
-        for (int a = 0; a <= 2; ++a)
-            for (int b = 0; b <= 2; ++b) {
-                const int i = e + a - 1, j = e + b - 1;
-                if (i < 0 || i >= n || j < 0 || j >= n) continue;
-                K[size_t(i) * n + j] += Ke[e][a * 3 + b];
-                M[size_t(i) * n + j] += Me[e][a * 3 + b];
+    // generalised eigenvectors of one axis: V^T M V = I, V^T K V = diag(lam)
+    auto eigen_axis = [&](const std::vector<double> &K, const std::vector<double> &M, std::vector<double> &V,
+                          std::vector<double> &lam) {
+        // M = L L^T (dense Cholesky, lower)
+        std::vector<double> L(M);
+        for (int j = 0; j < n; ++j) {
+            double s2 = L[size_t(j) * n + j];
+            for (int k = 0; k < j; ++k) s2 -= L[size_t(j) * n + k] * L[size_t(j) * n + k];
+            IGA2L_REQUIRE(s2 > 0.0, IGA2L_ENUMERIC, "degree-2 mass matrix not positive definite");
+            const double ljj = std::sqrt(s2);
+            L[size_t(j) * n + j] = ljj;
+            for (int i = j + 1; i < n; ++i) {
+                double t = L[size_t(i) * n + j];
+                for (int k = 0; k < j; ++k) t -= L[size_t(i) * n + k] * L[size_t(j) * n + k];
+                L[size_t(i) * n + j] = t / ljj;
             }
-    // M = L L^T (dense Cholesky, lower)
-    std::vector<double> L(M);
-    for (int j = 0; j < n; ++j) {
-        double s = L[size_t(j) * n + j];
-        for (int k = 0; k < j; ++k) s -= L[size_t(j) * n + k] * L[size_t(j) * n + k];
-        IGA2L_REQUIRE(s > 0.0, IGA2L_ENUMERIC, "degree-2 mass matrix not positive definite");
-        const double ljj = std::sqrt(s);
-        L[size_t(j) * n + j] = ljj;
-        for (int i = j + 1; i < n; ++i) {
-            double t = L[size_t(i) * n + j];
-            for (int k = 0; k < j; ++k) t -= L[size_t(i) * n + k] * L[size_t(j) * n + k];
-            L[size_t(i) * n + j] = t / ljj;
+            for (int k = j + 1; k < n; ++k) L[size_t(j) * n + k] = 0.0;
         }
-        for (int k = j + 1; k < n; ++k) L[size_t(j) * n + k] = 0.0;
-    }
-    // C = L^{-1} K L^{-T}: solve L X = K, then C^T: L C^T = X^T (C symmetric)
-    auto lower_solve = [&](std::vector<double> &B) {   // B <- L^{-1} B, column by column
+        // C = L^{-1} K L^{-T}: solve L X = K, then C^T: L C^T = X^T (C symmetric)
+        auto lower_solve = [&](std::vector<double> &B) {   // B <- L^{-1} B, column by column
+            for (int c = 0; c < n; ++c)
+                for (int i = 0; i < n; ++i) {
+                    double t = B[size_t(i) * n + c];
+                    for (int k = 0; k < i; ++k) t -= L[size_t(i) * n + k] * B[size_t(k) * n + c];
+                    B[size_t(i) * n + c] = t / L[size_t(i) * n + i];
+                }
+        };
+        std::vector<double> X(K);
+        lower_solve(X);
+        std::vector<double> C(size_t(n) * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) C[size_t(i) * n + j] = X[size_t(j) * n + i];
+        lower_solve(C);
+        for (int i = 0; i < n; ++i)           // symmetrise the rounding
+            for (int j = i + 1; j < n; ++j) {
+                const double a2 = 0.5 * (C[size_t(i) * n + j] + C[size_t(j) * n + i]);
+                C[size_t(i) * n + j] = C[size_t(j) * n + i] = a2;
+            }
+        std::vector<double> Q;
+        jacobi_eigen(n, C, Q);
+        lam.resize(n);
+        for (int i = 0; i < n; ++i) lam[i] = C[size_t(i) * n + i];
+        // V = L^{-T} Q: back substitution with L^T, column by column
+        V = Q;
         for (int c = 0; c < n; ++c)
-            for (int i = 0; i < n; ++i) {
-                double t = B[size_t(i) * n + c];
-                for (int k = 0; k < i; ++k) t -= L[size_t(i) * n + k] * B[size_t(k) * n + c];
-                B[size_t(i) * n + c] = t / L[size_t(i) * n + i];
+            for (int i = n - 1; i >= 0; --i) {
+                double t = V[size_t(i) * n + c];
+                for (int k = i + 1; k < n; ++k) t -= L[size_t(k) * n + i] * V[size_t(k) * n + c];
+                V[size_t(i) * n + c] = t / L[size_t(i) * n + i];
             }
     };
-    std::vector<double> X(K);
-    lower_solve(X);
-    std::vector<double> C(size_t(n) * n);
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) C[size_t(i) * n + j] = X[size_t(j) * n + i];
-    lower_solve(C);
-    for (int i = 0; i < n; ++i)           // symmetrise the rounding
-        for (int j = i + 1; j < n; ++j) {
-            const double a = 0.5 * (C[size_t(i) * n + j] + C[size_t(j) * n + i]);
-            C[size_t(i) * n + j] = C[size_t(j) * n + i] = a;
+    // the 1-D degree-2 stiffness and (operator) mass of each axis, dense
+    auto dense = [&](const std::vector<double> &off) {   // by offset [i][j-i+2] -> n x n
+        std::vector<double> D(size_t(n) * n, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int o = -2; o <= 2; ++o)
+                if (i + o >= 0 && i + o < n) D[size_t(i) * n + i + o] = off[size_t(i) * 5 + o + 2];
+        return D;
+    };
+    const int naxes = annulus ? d : 1;
+    std::vector<std::vector<double>> Vax(naxes), lamax(naxes);
+    for (int ax = 0; ax < naxes; ++ax) {
+        std::vector<double> K(size_t(n) * n, 0.0), M(size_t(n) * n, 0.0);
+        if (annulus) {
+            K = dense(annulus_form_1d(P, 2, 2, ax, kAnnStiff));
+            M = dense(annulus_form_1d(P, 2, 2, ax, kAnnOpMass));
+        } else {
+            std::vector<std::vector<double>> Ke, Me;
+            element_matrices(2, m, Ke, Me);
+            for (int e = 0; e < m; ++e)
+                for (int a = 0; a <= 2; ++a)
+                    for (int b = 0; b <= 2; ++b) {
+                        const int i = e + a - 1, j = e + b - 1;
+                        if (i < 0 || i >= n || j < 0 || j >= n) continue;
+                        K[size_t(i) * n + j] += Ke[e][a * 3 + b];
+                        M[size_t(i) * n + j] += Me[e][a * 3 + b];
+                    }
         }
-    std::vector<double> Q;
-    jacobi_eigen(n, C, Q);
-    std::vector<double> lam(n);
-    for (int i = 0; i < n; ++i) lam[i] = C[size_t(i) * n + i];
-    // V = L^{-T} Q: back substitution with L^T, column by column
-    std::vector<double> V(Q);
-    for (int c = 0; c < n; ++c)
-        for (int i = n - 1; i >= 0; --i) {
-            double t = V[size_t(i) * n + c];
-            for (int k = i + 1; k < n; ++k) t -= L[size_t(k) * n + i] * V[size_t(k) * n + c];
-            V[size_t(i) * n + c] = t / L[size_t(i) * n + i];
-        }
-    // forward transform matrix V^T (row k = column k of V), backward V
-    std::vector<double> Vt(size_t(n) * n);
-    for (int i = 0; i < n; ++i)
-        for (int k = 0; k < n; ++k) Vt[size_t(k) * n + i] = V[size_t(i) * n + k];
+        eigen_axis(K, M, Vax[ax], lamax[ax]);
+    }
+    // forward transform matrices V^T (row k = column k of V), backward V, one
+    // per axis for the annulus (stacked, axis stride n^2), one for all otherwise
+    std::vector<double> Vt, V;
+    for (int ax = 0; ax < naxes; ++ax) {
+        for (int k = 0; k < n; ++k)
+            for (int i = 0; i < n; ++i) Vt.push_back(Vax[ax][size_t(i) * n + k]);
+        V.insert(V.end(), Vax[ax].begin(), Vax[ax].end());
+    }
+    P.fdm_axis_stride = annulus ? int64_t(n) * n : 0;
     const int64_t nc = ipow(n, d);
     std::vector<double> mu(nc), ones(nc, 1.0);
     int ix[kMaxDim] = {0, 0, 0};
     for (int64_t i = 0; i < nc; ++i) {
         split(i, d, n, ix);
         double sl = 0.0;
-        for (int k = 0; k < d; ++k) sl += lam[ix[k]];
+        for (int k = 0; k < d; ++k) sl += lamax[annulus ? k : 0][ix[k]];
         mu[i] = sl;
     }
     P.fdm_Vt.alloc(Vt.size() * sizeof(double));

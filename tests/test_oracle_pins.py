@@ -887,3 +887,81 @@ def test_table5_iteration_counts_in_paper_band():
         b = O.load_annulus(p, m)
         _, cyc, _ = P.solve(b, ordering=O.COLOUR, s=P.block_width + p, coarse=O.DIRECT, tol=1e-8, max_cycles=60)
         assert it_ds - 3 <= cyc <= 3 * it_ds, (p, cyc, it_ds)
+
+
+def test_annulus_seven_by_seven_sweep_sensitivity():
+    """The 7x7-block bar of the annulus (p = 8, m = 10, colour period b+p).
+    The operator assembled as the library does it, tensor sums of weighted
+    1-D forms (built here from the oracle's knots, B-splines, weights and
+    Gauss rule), agrees with the oracle's 2-D quadrature to 2e-14 of its
+    largest entry, the gap of two equally valid FP64 assemblies.  Block
+    condition numbers reach ~1e5 on the annulus, and the same sweep computed
+    on the two operators differs by ~6e-11 (more than 1e-11, less than
+    2e-10): the GPU parity bar for 7x7 blocks on the annulus is 2e-10."""
+    d, p, m = 2, 8, 10
+    r, R = O.ANNULUS
+    n1 = m + p - 2
+    t, w = O.knots(p, m), O.annulus_weights(p, m)
+    gx, gw = O.gauss_legendre(p + 3)
+
+    def arc(x):
+        a, r2 = 1 - x, np.sqrt(2.0)
+        nx, ny = a * a + r2 * x * a, r2 * x * a + x * x
+        W = nx + x * x
+        dnx, dny = -2 * a + r2 * (1 - 2 * x), r2 * (1 - 2 * x) + 2 * x
+        dW = dnx + 2 * x
+        return W, dW, np.hypot((dnx * W - nx * dW) / W ** 2, (dny * W - ny * dW) / W ** 2)
+
+    def forms(axis):
+        K, M = np.zeros((n1, n1)), np.zeros((n1, n1))
+        for e in range(m):
+            for k in range(len(gx)):
+                x, wq = (e + 0.5 * (gx[k] + 1)) / m, 0.5 * gw[k] / m
+                v = np.array([O.bspline(t, p, e + a, x) for a in range(p + 1)])
+                dv = np.array([O.bspline_deriv(t, p, e + a, x) for a in range(p + 1)])
+                if axis == 0:   # angular: phi = w_i N_i / W, weights 1/speed and speed
+                    W, dW, sp = arc(x)
+                    om = w[e:e + p + 1]
+                    dv, v = om * (dv * W - v * dW) / W ** 2, om * v / W
+                    wk, wm = 1 / sp, sp
+                else:           # radial: rho/(R-r) and (R-r)/rho
+                    rho = r + (R - r) * x
+                    wk, wm = rho / (R - r), (R - r) / rho
+                for a in range(p + 1):
+                    for c in range(p + 1):
+                        i, j = e + a - 1, e + c - 1
+                        if 0 <= i < n1 and 0 <= j < n1:
+                            K[i, j] += wq * wk * dv[a] * dv[c]
+                            M[i, j] += wq * wm * v[a] * v[c]
+        return K, M
+
+    Kx, Mx = forms(0)
+    Ky, My = forms(1)
+    Ak = np.kron(My, Kx) + np.kron(Ky, Mx)
+    P = O.Problem(d, p, m, plow=2, annulus=O.ANNULUS)
+    A = O.offsets_to_dense(P.A(), d, n1, p)
+    assert np.max(np.abs(A - Ak)) <= 2e-14 * np.max(np.abs(A))
+    bw, n = P.block_width, P.n
+    s = bw + p
+    members = [_block_members(d, n1, bw, j) for j in range(n)]
+    u0 = synth.initial_guess(d, p, m, seed=1)
+    b = synth.rhs_normal(d, p, m, seed=0)
+
+    def sweep(Aop):
+        u = u0.copy()
+        for cy in range(s):
+            for cx in range(s):
+                res = b - Aop @ u
+                du = np.zeros_like(u)
+                for j in range(n):
+                    if (j % n1) % s == cx and (j // n1) % s == cy:
+                        idx = members[j]
+                        du[idx] += np.linalg.solve(Aop[np.ix_(idx, idx)], res[idx])
+                u = u + du
+        return u
+
+    ref = P.sweep(u0, b, ordering=O.COLOUR, s=s)
+    on_A = sweep(A)
+    assert np.linalg.norm(on_A - ref) <= 1e-12 * np.linalg.norm(ref)
+    gap = np.linalg.norm(sweep(Ak) - on_A) / np.linalg.norm(on_A)
+    assert 1e-11 < gap < 2e-10, gap
