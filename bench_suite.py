@@ -8,6 +8,9 @@ as one JSON line each (the headline line of bench.py stays the first line).
   C5  2-D p=4 256x256 GRF kappa: forward mixed solve + adjoint gradient
   AGG 2-D 256x256, p = 2..5, the paper's timed configuration: aggressive
       coarsening (degree 1 on 2h) with one V(1,1) cycle there
+  ANN quarter annulus (NURBS, Section 5.2), 32^2 .. 256^2, p = 3..8, degree-2
+      coarse space solved exactly, coloured Schwarz (period b+p), to a 1e-8
+      reduction (Table 5's stopping rule), FP64 and mixed
 Each line states the error of the GPU solution against the oracle's (C3:
 against sampled values of a stored oracle solution; C4: four sampled problems).
 Every step is a complete solve to a 1e-10 residual reduction from u = 0 with
@@ -128,11 +131,60 @@ def run(torch, G, steps=5, only=None):
                                {"fp64": G.Opts(**v11a), "mixed": G.Opts(precision=G.MIXED_FP32, **v11a)}, steps)
             line["paper_table4_iterations_1e-8_context"] = {2: 6, 3: 6, 4: 7, 5: 5}[p]
             lines.append(line)
+    if want("ANN"):
+        lines.extend(_annulus(torch, G, steps))
     if want("C4"):
         lines.append(_c4(torch, G, v22))
     if want("C5"):
         lines.append(_c5(torch, G))
     return lines
+
+
+ANNULUS_RADII = (0.3, 0.5)
+TABLE5_DS = {32: {3: 5, 4: 8, 5: 4, 6: 6, 7: 3, 8: 4}, 64: {3: 5, 4: 8, 5: 4, 6: 6, 7: 4, 8: 5},
+             128: {3: 6, 4: 7, 5: 4, 6: 6, 7: 4, 8: 5}, 256: {3: 6, 4: 8, 5: 4, 6: 6, 7: 4, 8: 5}}
+
+
+def _annulus(torch, G, steps):
+    """Quarter annulus: one line per grid, every degree; the right-hand side is
+    seeded N(0,1) (Table 5 uses a manufactured load: its counts are context).
+    At 32^2 and p <= 5 the FP64 solution is compared with the oracle's."""
+    out = []
+    for m in (32, 64, 128, 256):
+        line = {"config": "ANN", "grid": f"{m}x{m}", "radii": ANNULUS_RADII, "plow": 2, "coarse": "exact (FDM)"}
+        for p in (3, 4, 5, 6, 7, 8):
+            bw = 3 if p <= 4 else (5 if p <= 6 else 7)
+            o64 = G.Opts(coarse=G.COARSE_DIRECT, plow=2, colour_period=bw + p, tol=1e-8, max_cycles=100)
+            o32 = G.Opts(coarse=G.COARSE_DIRECT, plow=2, colour_period=bw + p, tol=1e-8, max_cycles=100,
+                         precision=G.MIXED_FP32)
+            t0 = time.perf_counter()
+            prob = G.Problem(2, p, m, annulus=ANNULUS_RADII, device=0)
+            prob.setup(0, o64)
+            prob.setup(0, o32)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            b_np = synth.rhs_normal(2, p, m, seed=0)
+            b = torch.tensor(b_np, device="cuda")
+            u = torch.zeros_like(b)
+            rec = {"n_fine": prob.n, "setup_s": t_setup, "paper_table5_DS_iterations_context": TABLE5_DS[m][p]}
+            for label, o in (("fp64", o64), ("mixed", o32)):
+                def one():
+                    u.zero_()
+                    return prob.solve(b, u, o)[1]
+                t, info = _timed(torch, one, steps)
+                rec[label] = {"time_to_tol_ms": 1e3 * t, "cycles": info.iters, "relres": info.relres}
+                if label == "fp64":
+                    u64 = u.cpu().numpy().copy()
+            if m == 32 and p <= 5:
+                import oracle as O
+                orc = O.Problem(2, p, m, plow=2, annulus=ANNULUS_RADII)
+                uo, ko, _ = orc.solve(b_np, ordering=O.COLOUR, s=bw + p, coarse=O.DIRECT, tol=1e-8, max_cycles=100)
+                rec["error_vs_oracle_fp64"] = _error_vs(uo, u64)
+                rec["oracle_cycles"] = ko
+            line[f"p{p}"] = rec
+            prob.close()
+        out.append(line)
+    return out
 
 
 def _c4(torch, G, v22):
