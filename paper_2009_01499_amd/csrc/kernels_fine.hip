@@ -1340,8 +1340,10 @@ bool tune_log() {
 }
 
 std::vector<std::pair<int, int>> colour_tile_candidates(int S, int n1) {
+    // the last rows serve long colour periods (s = b + p up to 15: a cell of s x s points)
     static const int shapes[][2] = {{4, 4}, {8, 2}, {8, 4},  {16, 1}, {16, 2}, {16, 4}, {32, 1}, {32, 2},
-                                    {4, 8}, {11, 3}, {22, 2}, {28, 2}, {43, 1}, {12, 4}, {64, 1}};
+                                    {4, 8}, {11, 3}, {22, 2}, {28, 2}, {43, 1}, {12, 4}, {64, 1},
+                                    {1, 1}, {2, 1}, {1, 2}, {2, 2}, {3, 1}, {4, 1}, {3, 2}, {4, 2}};
     std::vector<std::pair<int, int>> out;
     const int cells = (n1 + 2 * S - 1) / S;   // cells a colour's grid spans per direction
     for (auto &sh : shapes) {
