@@ -81,13 +81,15 @@ def cpu_baseline(d, p, m, b, nu, cycles_gpu):
     return rec, (u if rel <= 1e-10 else None)
 
 
-def oracle_solution(d, p, m, b, kappa=None, nu=(2, 2), tol=1e-10, max_cycles=200):
+def oracle_solution(d, p, m, b, kappa=None, nu=(2, 2), tol=1e-10, max_cycles=200, aggressive=False):
     """CPU-oracle leg of the suite lines: the oracle's converged solution of the
-    same coloured two-level solve (FP64, V(nu) coarse, from u=0), against which
+    same coloured two-level solve (FP64, V(nu) coarse, from u=0; with
+    aggressive coarsening the V-cycle runs from the 2h level), against which
     the GPU result's error is stated."""
     import oracle as O
     orc = O.Problem(d, p, m, kappa=kappa, vcycle=True, coarse_direct=False)
-    u, k, _ = orc.solve(b, coarse=O.VCYCLE, cnu1=nu[0], cnu2=nu[1], tol=tol, max_cycles=max_cycles)
+    u, k, _ = orc.solve(b, coarse=O.VCYCLE, cnu1=nu[0], cnu2=nu[1], tol=tol, max_cycles=max_cycles,
+                        aggressive=aggressive)
     return u, k
 
 

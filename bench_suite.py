@@ -73,12 +73,12 @@ def _solve_line(torch, G, name, d, p, m, opts_list, steps, kappa=None, block_wid
     return line
 
 
-def _oracle_c2(d, p, m, nu):
+def _oracle_c2(d, p, m, nu, aggressive=False):
     """Errors of every solution against the oracle's converged solution of the
     same FP64 solve (CPU-oracle leg)."""
     def ref(b_np, sols):
         from bench import oracle_solution
-        u_orc, k = oracle_solution(d, p, m, b_np, nu=nu)
+        u_orc, k = oracle_solution(d, p, m, b_np, nu=nu, aggressive=aggressive)
         out = {label: _error_vs(u_orc, v) for label, v in sols.items()}
         out["oracle_cycles"] = k
         return out
@@ -129,7 +129,8 @@ def run(torch, G, steps=5, only=None):
         v11a = dict(coarse=G.COARSE_VCYCLE, nu1=1, nu2=1, tol=1e-10, aggressive=1)
         for p in (2, 3, 4, 5):
             line = _solve_line(torch, G, "C2-aggressive", 2, p, 256,
-                               {"fp64": G.Opts(**v11a), "mixed": G.Opts(precision=G.MIXED_FP32, **v11a)}, steps)
+                               {"fp64": G.Opts(**v11a), "mixed": G.Opts(precision=G.MIXED_FP32, **v11a)}, steps,
+                               oracle_ref=_oracle_c2(2, p, 256, (1, 1), aggressive=True))
             line["paper_table4_iterations_1e-8_context"] = {2: 6, 3: 6, 4: 7, 5: 5}[p]
             lines.append(line)
     if want("ANN"):
