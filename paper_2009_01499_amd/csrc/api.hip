@@ -522,6 +522,9 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
             if (P.geometry == kGeomAnnulus) {
                 P.R1yd32.alloc(P.R1y.size() * sizeof(float));
                 launch_convert(P.R1yd64.ptr, P.R1yd32.ptr, int64_t(P.R1y.size()), true, s);
+                const int64_t nf = 4 * int64_t(P.fine.n1) * (2 * P.p + 1);
+                P.fac2d32.alloc(size_t(nf) * sizeof(float));
+                launch_convert(P.fac2d64.ptr, P.fac2d32.ptr, nf, true, s);
             }
             P.dc64.alloc(size_t(P.coarse.n) * sizeof(double));
             P.ec64.alloc(size_t(P.coarse.n) * sizeof(double));

@@ -196,6 +196,7 @@ struct Problem {
     DevBuf kron64, kron32;        // kappa = 1, 3-D: K1 then M1, [n1][2p+1] each (empty otherwise)
     DevBuf cf64, cf32;            // kappa = 1: interior row of K1 then of M1, 2 (2p+1) (empty otherwise)
     DevBuf fac64, fac32;          // kappa = 1, 2-D: K1 then M1, [n1][2p+1] each (empty otherwise)
+    DevBuf fac2d64, fac2d32;      // annulus: rows of K1, M1, K1y, M1y, [n1][2p+1] each (empty otherwise)
     int ulo = 1, uhi = 0;         // rows with all coordinates in [ulo, uhi] carry that stencil
     DevBuf scal;                  // status block: kScalCount doubles, kFlagCount ints, hist_cap doubles
     DevBuf lam_tmp;               // adjoint workspace

@@ -79,6 +79,34 @@ __device__ __forceinline__ double kron3_entry(double kx, double mx, double myz, 
 // [n1][2P+1] each), accumulated against the LDS halo in the diagonal order.
 // FP64: the entries equal the stored diagonals bit for bit.  FP32 (the
 // correction cycle): FP32 factors, the sum regrouped as
+
+// A row of a 2-D operator that is a tensor sum of direction-dependent 1-D
+// factors, A = Kx (x) My + Mx (x) Ky (the quarter annulus: fac holds the rows
+// of Kx, Mx, Ky, My, each [n1][2P+1]), applied by sum factorisation: per
+// stencil row the x sums of both x factors, then the y weights.  The factor
+// rows of a point next to the boundary are zero beyond the grid.
+template <int P, class T>
+__device__ __forceinline__ T fac2_row_dot(const T *__restrict__ fac, int n1, int gx, int gy, const T *xs, int lc,
+                                         int HX) {
+    constexpr int W1 = 2 * P + 1;
+    const int64_t nw = int64_t(n1) * W1;
+    const T *Kx = fac + int64_t(gx) * W1, *Mx = fac + nw + int64_t(gx) * W1;
+    const T *Ky = fac + 2 * nw + int64_t(gy) * W1, *My = fac + 3 * nw + int64_t(gy) * W1;
+    T acc = T(0);
+#pragma unroll
+    for (int oy = -P; oy <= P; ++oy) {
+        T kx = T(0), mx = T(0);
+#pragma unroll
+        for (int ox = -P; ox <= P; ++ox) {
+            const T v = xs[lc + oy * HX + ox];
+            kx += Kx[ox + P] * v;
+            mx += Mx[ox + P] * v;
+        }
+        acc += My[oy + P] * kx + Ky[oy + P] * mx;
+    }
+    return acc;
+}
+
 // kx (my mz) + mx (ky mz + my kz), the yz part formed once per stencil row.
 template <int P, class T>
 __device__ __forceinline__ T kron3_row_dot(const T *__restrict__ kron, int n1, int gx, int gy, int gz, const T *xs,
@@ -166,6 +194,8 @@ __device__ __forceinline__ void residual_body(const T *__restrict__ val, int64_t
 #pragma unroll
                     for (int ox = -P; ox <= P; ++ox)
                         acc += css[(oy + P) * (2 * P + 1) + (ox + P)] * xs[lc + oy * HX + ox];
+            } else if (kron) {
+                acc = fac2_row_dot<P, T>(kron, n1, gx, gy, xs, lc, HX);
             } else {
 #pragma unroll
                 for (int oy = -P; oy <= P; ++oy)
@@ -320,7 +350,7 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
     constexpr bool kPreVal = PRE && D == 2 && W * sizeof(T) <= 392;
     T arow[kPreVal ? W : 1];
     if constexpr (kPreVal) {
-        if (!uni && mine && in_block && !x_zero) {
+        if (!uni && !kron && mine && in_block && !x_zero) {
             const int64_t padi = int64_t(gx + P) + int64_t(gy + P) * pitch1;
 #pragma unroll
             for (int qy = -P; qy <= P; ++qy)
@@ -373,16 +403,21 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
                                 acc += css[((qz + P) * (2 * P + 1) + (qy + P)) * (2 * P + 1) + (qx + P)] *
                                        xs[lc + (qz * HY + qy) * HX + qx];
                 } else if constexpr (D == 2) {
+                    if (kron) {
+                        acc = fac2_row_dot<P, T>(kron, n1, gx, gy, xs, lc, HX);
+                    } else {
 #pragma unroll
-                    for (int qy = -P; qy <= P; ++qy)
+                        for (int qy = -P; qy <= P; ++qy)
 #pragma unroll
-                        for (int qx = -P; qx <= P; ++qx) {
-                            const int w = (qy + P) * (2 * P + 1) + (qx + P);
-                            T a;
-                            if constexpr (kPreVal) a = arow[w];
-                            else a = dia_entry<D, P, T>(val, npad, padi, w, int64_t(qx) + int64_t(qy) * pitch1);
-                            acc += a * xs[lc + qy * HX + qx];
-                        }
+                            for (int qx = -P; qx <= P; ++qx) {
+                                const int w = (qy + P) * (2 * P + 1) + (qx + P);
+                                T a;
+                                if constexpr (kPreVal) a = arow[w];
+                                else
+                                    a = dia_entry<D, P, T>(val, npad, padi, w, int64_t(qx) + int64_t(qy) * pitch1);
+                                acc += a * xs[lc + qy * HX + qx];
+                            }
+                    }
                 } else if (kron) {
                     acc = kron3_row_dot<P, T>(kron, n1, gx, gy, gz, xs, lc, HX, HY);
                 } else {
@@ -841,6 +876,10 @@ struct TileShape<3, P> {
 // 1-D factors for the 3-D boundary rows (null: read the diagonals)
 template <class T>
 const T *kron_factors(const Problem &Pb) {
+    // 2-D: the direction-dependent factor rows of the annulus (null otherwise)
+    if (Pb.dim == 2)
+        return std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.fac2d64.ptr)
+                                              : reinterpret_cast<const T *>(Pb.fac2d32.ptr);
     return std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.kron64.ptr)
                                           : reinterpret_cast<const T *>(Pb.kron32.ptr);
 }

@@ -541,6 +541,14 @@ void host_assemble(Problem &P) {
     if (annulus) {
         P.R1yd64.alloc(P.R1y.size() * sizeof(double));
         IGA2L_HIP(hipMemcpy(P.R1yd64.ptr, P.R1y.data(), P.R1y.size() * sizeof(double), hipMemcpyHostToDevice));
+        // the operator's 1-D factor rows, for kernels that form its rows by
+        // sum factorisation instead of reading the (2p+1)^2 diagonals
+        std::vector<double> f(P.K1);
+        f.insert(f.end(), P.M1.begin(), P.M1.end());
+        f.insert(f.end(), P.K1y.begin(), P.K1y.end());
+        f.insert(f.end(), P.M1y.begin(), P.M1y.end());
+        P.fac2d64.alloc(f.size() * sizeof(double));
+        IGA2L_HIP(hipMemcpy(P.fac2d64.ptr, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice));
     }
 
     // workspaces sized by the fine grid
