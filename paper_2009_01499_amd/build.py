@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libiga2l.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["setup_host.cpp", "kernels_fine.hip", "kernels_coarse.hip", "kernels_vcycle.hip", "kernels_2d.hip",
-           "kernels_3d.hip", "batch.hip", "api.hip"]
+           "kernels_colour2d.hip", "kernels_3d.hip", "batch.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -268,6 +268,16 @@ __device__ __forceinline__ void stage_lds(T *dst, int nh, Get get) {
 // every position has its own inverse (must match host_block_classes)
 inline int class_split(const Problem &P) { return P.shared_inverses ? (P.ncls1 - 1) / 2 : -1; }
 
+// 1-D class of a block centre j (the index of its inverse along one
+// direction): with shared inverses (kappa = 1, L = p-1+h_b) the first and
+// last L positions have their own classes and all others share class L;
+// otherwise (L < 0) every position is its own class.  Computed instead of
+// looked up, so the inverse rows can be loaded together with the halo.
+__device__ __forceinline__ int block_class(int j, int n1, int L) {
+    if (L < 0) return j;
+    return j < L ? j : (j > n1 - 1 - L ? L + 1 + (j - (n1 - L)) : L);
+}
+
 // views into the status block
 inline int *dev_flags(const Problem &P) { return reinterpret_cast<int *>(P.scal.as<double>() + kScalCount); }
 inline double *dev_hist(const Problem &P) { return P.scal.as<double>() + kScalCount + kFlagCount / 2; }
@@ -410,6 +420,11 @@ void launch_colour3d_sf(const Problem &P, int cx, int cy, int cz, const T *x_src
                         const double *r64, T *rhs_out, hipStream_t s);
 template <class T, bool NORM>
 void launch_residual3d_sf(const Problem &P, const T *x, const T *b, T *r, double *partial, hipStream_t s);
+// 2-D kappa = 1 on large grids (kernels_colour2d.hip): one Schwarz colour with
+// colour period b, streamed along y; false (nothing launched) where it does
+// not apply
+bool colour2d_stream(const Problem &P, int cx, int cy, int S, const void *x_src, void *x_dst, const void *rhs,
+                     bool fp64, hipStream_t s);
 // 2-D bandwidth-oriented variants (kernels_2d.hip)
 template <class T>
 void launch_residual2d(const Problem &P, const T *val, const T *x, const T *b, T *r, double *partial, hipStream_t s);

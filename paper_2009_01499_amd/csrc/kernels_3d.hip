@@ -69,13 +69,6 @@ struct Sf {
     static_assert(NR <= NT, "r and delta live in the tM / tK area");
 };
 
-// 1-D class of a block centre (the index of its inverse along one direction):
-// the first and last L positions have their own classes, all others share
-// class L (the same rule as the host's block classes with shared inverses)
-__device__ __forceinline__ int sf_block_class(int j, int n1, int L) {
-    return j < L ? j : (j > n1 - 1 - L ? L + 1 + (j - (n1 - L)) : L);
-}
-
 // LDS index of point k (0..26, x fastest) of block n of the tile, in the
 // tile-point layout [z][y][x]
 template <int P>
@@ -267,9 +260,9 @@ __global__ void __launch_bounds__(kSfThreads, 4) k_colour3d_sf(
             if (!x_zero) xv[k] = x_src[gi];
             const int ccx = gx0 + 3 * (x / 3) + 1, ccy = gy0 + 3 * (y / 3) + 1, ccz = gz0 + 3 * (z / 3) + 1;
             if (ccx >= 0 && ccx < n1 && ccy >= 0 && ccy < n1 && ccz >= 0 && ccz < n1) {
-                const int cx = clsL >= 0 ? sf_block_class(ccx, n1, clsL) : ccx;
-                const int cy = clsL >= 0 ? sf_block_class(ccy, n1, clsL) : ccy;
-                const int cz = clsL >= 0 ? sf_block_class(ccz, n1, clsL) : ccz;
+                const int cx = clsL >= 0 ? block_class(ccx, n1, clsL) : ccx;
+                const int cy = clsL >= 0 ? block_class(ccy, n1, clsL) : ccy;
+                const int cz = clsL >= 0 ? block_class(ccz, n1, clsL) : ccz;
                 if (clsL >= 0 && cx == clsL && cy == clsL && cz == clsL) {
                     rowoff[k] = -1;
                 } else {

@@ -36,17 +36,6 @@ __device__ __forceinline__ T dia_entry(const T *__restrict__ val, int64_t npad, 
 }
 
 // ------------------------------------------------------------------------
-// 1-D class of a block centre j (the index of its inverse along one
-// direction): with shared inverses (kappa = 1, L = p-1+h_b) the first and
-// last L positions have their own classes and all others share class L;
-// otherwise (L < 0) every position is its own class.  Computed instead of
-// looked up, so the inverse rows can be loaded together with the halo.
-__device__ __forceinline__ int block_class(int j, int n1, int L) {
-    if (L < 0) return j;
-    return j < L ? j : (j > n1 - 1 - L ? L + 1 + (j - (n1 - L)) : L);
-}
-
-// ------------------------------------------------------------------------
 // Interior rows of the kappa = 1 operator are translation invariant: rows whose
 // coordinates all lie in [ulo, uhi] carry the (2p+1)^d stencil cs (bit for
 // bit: the interior element matrices are one copy).  Such rows read cs
@@ -343,7 +332,9 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
         }
     }
     // one path per wavefront: the interior stencil when all its rows carry it
-    const bool uni = cs != nullptr && __all(!mine || point_uniform(gx, gy, gz, ulo, uhi, D));
+    // (2-D operators with 1-D factors take every row from the factors)
+    const bool uni = cs != nullptr && !(D == 2 && kron != nullptr) &&
+                     __all(!mine || point_uniform(gx, gy, gz, ulo, uhi, D));
     // the operator row of a point next to the grid boundary (PRE, 2-D, short
     // rows): loaded with the halo instead of after it
     constexpr int W = cpow(2 * P + 1, D);
@@ -363,6 +354,11 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
     }
     // the interior stencil (kappa = 1) staged in LDS behind the residuals
     T *css = rs + ntile;
+    // 2-D operators that are tensor sums of 1-D factors (kron: rows of Kx, Mx,
+    // Ky, My): the x sums of Kx and Mx, once per tile column and window row,
+    // behind the stencil; every point then takes its row from 2(2P+1) of them
+    T *kxs = css + W, *mxs = kxs + (TY + 2 * P) * TX;
+    const bool sf2 = D == 2 && kron != nullptr;
     if (!x_zero) {
         if (cs)
             for (int w = threadIdx.x; w < W; w += blockDim.x) css[w] = cs[w];
@@ -373,6 +369,27 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
             xs[h] = in ? x_src[(int64_t(hgz) * n1 + hgy) * n1 + hgx] : T(0);
         }
         __syncthreads();
+        if constexpr (D == 2) {
+            if (sf2) {
+                constexpr int W1 = 2 * P + 1;
+                const int64_t nw = int64_t(n1) * W1;
+                for (int h = threadIdx.x; h < (TY + 2 * P) * TX; h += blockDim.x) {
+                    const int c = h % TX, r = h / TX;
+                    const int fx = min(max(gx0 + c, 0), n1 - 1);
+                    const T *Kx = kron + int64_t(fx) * W1, *Mx = kron + nw + int64_t(fx) * W1;
+                    const T *xr = xs + r * HX + c;
+                    T kx = T(0), mx = T(0);
+#pragma unroll
+                    for (int o = 0; o < W1; ++o) {
+                        kx += Kx[o] * xr[o];
+                        mx += Mx[o] * xr[o];
+                    }
+                    kxs[h] = kx;
+                    mxs[h] = mx;
+                }
+                __syncthreads();
+            }
+        }
     }
     const int lc = ((tz + ((D == 3) ? P : 0)) * HY + (ty + P)) * HX + (tx + P);
     T res = T(0);
@@ -403,8 +420,15 @@ __device__ __forceinline__ void colour_body(const T *__restrict__ val, int64_t n
                                 acc += css[((qz + P) * (2 * P + 1) + (qy + P)) * (2 * P + 1) + (qx + P)] *
                                        xs[lc + (qz * HY + qy) * HX + qx];
                 } else if constexpr (D == 2) {
-                    if (kron) {
-                        acc = fac2_row_dot<P, T>(kron, n1, gx, gy, xs, lc, HX);
+                    if (sf2) {
+                        constexpr int W1 = 2 * P + 1;
+                        const int64_t nw = int64_t(n1) * W1;
+                        const T *Ky = kron + 2 * nw + int64_t(gy) * W1, *My = kron + 3 * nw + int64_t(gy) * W1;
+#pragma unroll
+                        for (int qy = -P; qy <= P; ++qy) {
+                            const int hi = (ty + P + qy) * TX + tx;
+                            acc += My[qy + P] * kxs[hi] + Ky[qy + P] * mxs[hi];
+                        }
                     } else {
 #pragma unroll
                         for (int qy = -P; qy <= P; ++qy)
@@ -975,6 +999,12 @@ void defect_dp(const Problem &Pb, const T *e, const T *rhs, T *d, hipStream_t s)
 template <int D, int P, int B, class T>
 void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs,
                    bool x_zero, const double *r64, T *rhs_out, hipStream_t s, int tile_nbx = 0, int tile_nby = 0) {
+    // 2-D kappa = 1 on large grids, colour period b, from a given iterate:
+    // streamed (the tile shapes the autotuner times are for this kernel)
+    if constexpr (D == 2)
+        if (!x_zero && !r64 && tile_nbx == 0 && tile_nby == 0 &&
+            colour2d_stream(Pb, cx, cy, S, x_src, x_dst, rhs, std::is_same<T, double>::value, s))
+            return;
     if constexpr (D == 3 && B == 3) if (colour3d_sf_ok(Pb, S)) {
         // kappa = 1, colour period 3: sum-factorised residual, shared inverse on MFMA
         launch_colour3d_sf<T>(Pb, cx, cy, cz, x_src, x_dst, rhs, x_zero, r64, rhs_out, s);
@@ -1001,8 +1031,10 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
     if (oz > 0) oz -= S;
     dim3 grid((n1 - ox + TX - 1) / TX, (n1 - oy + TY - 1) / TY, D == 3 ? (n1 - oz + TZ - 1) / TZ : 1);
     const int threads = ((TX * TY * TZ + kWave - 1) / kWave) * kWave;
+    const T *fac2 = kron_factors<T>(Pb);
+    const size_t sf2_lds = (D == 2 && fac2) ? 2 * size_t(TY + 2 * Pb.p) * TX : 0;
     const size_t shm = (size_t(TX + 2 * Pb.p) * (TY + 2 * Pb.p) * (D == 3 ? TZ + 2 * Pb.p : 1) + size_t(TX) * TY * TZ +
-                        size_t(cpow(2 * P + 1, D))) *
+                        size_t(cpow(2 * P + 1, D)) + sf2_lds) *
                        sizeof(T);
     const T *val = std::is_same<T, double>::value ? reinterpret_cast<const T *>(Pb.A.v64.ptr)
                                                   : reinterpret_cast<const T *>(Pb.A.v32.ptr);
@@ -1014,7 +1046,7 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
     hipLaunchKernelGGL(kern, grid, dim3(threads), shm, s, val, Pb.A.npad, Pb.A.pitch[1],
                        Pb.A.pitch[2], n1, inv, class_split(Pb), Pb.ncls1, x_src, x_dst, rhs, x_zero ? 1 : 0, ox,
                        oy, oz, S, nbx, nby, nbz, uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, r64,
-                       Pb.scal.as<double>(), rhs_out, kron_factors<T>(Pb));
+                       Pb.scal.as<double>(), rhs_out, fac2);
 }
 
 template <int D, int P, class T>

@@ -430,6 +430,7 @@ def test_large_grid_kernels_sampled(groups, monkeypatch):
     if groups is not None:
         monkeypatch.setenv("IGA2L_RESIDUAL_GROUPS", groups)
         monkeypatch.setenv("IGA2L_TRANSFER_GROUPS", groups)
+        monkeypatch.setenv("IGA2L_COLOUR_GROUPS", groups)
     ref = json.load(open(GOLDEN_LARGE))
     d, p, m = 2, 3, 1024
     print(f"\n[case] large grid d={d} p={p} m={m} residual groups={groups}", flush=True)
@@ -455,10 +456,58 @@ def test_large_grid_kernels_sampled(groups, monkeypatch):
     ug = dev(u)
     gp.prolong_add(dev(ec), ug)
     check("prolong_add", host(ug))
-    # one FP64 coloured sweep: the register-light Schwarz instance of large grids
-    ug = dev(u)
-    gp.smooth(ug, dev(b), 1, G.Opts(ordering=G.COLOUR, colour_period=3))
-    check("sweep", host(ug))
+    # one FP64 coloured sweep: the streamed Schwarz colour of large grids, and
+    # the tiled register-light instance it replaces there
+    for stream in ("1", "0"):
+        monkeypatch.setenv("IGA2L_COLOUR_STREAM", stream)
+        ug = dev(u)
+        gp.smooth(ug, dev(b), 1, G.Opts(ordering=G.COLOUR, colour_period=3))
+        check("sweep", host(ug))
+
+
+@pytest.mark.parametrize("p,bw,m,groups", [(2, 3, 730, "40"), (5, 5, 722, None), (5, 5, 722, "40"),
+                                           (8, 7, 719, None), (8, 7, 719, "40")])
+def test_large_grid_streamed_colour(p, bw, m, groups, monkeypatch):
+    """The streamed Schwarz colour (grids of 2^19 DOFs and more, kappa = 1,
+    colour period b) for each block width against the tiled kernel, which the
+    small-grid cases and the 1024^2 golden compare with the oracle: one FP64
+    coloured sweep from a random iterate, and mixed-precision solves (whose
+    FP32 correction sweeps take the streamed colour after the first) with the
+    same cycle count.  With 7x7 blocks at p = 8 the period-b iteration
+    diverges (the oracle's too: 60 cycles at m = 40 end near 1e100), so that
+    case compares the sweep only.  With a target of 40 workgroups each strip
+    runs many chunks through its ring."""
+    G = _gpu()
+    if groups is not None:
+        monkeypatch.setenv("IGA2L_COLOUR_GROUPS", groups)
+    d = 2
+    print(f"\n[case] streamed colour p={p} b={bw} m={m} groups={groups}", flush=True)
+    gp = G.Problem(d, p, m)
+    o32 = G.Opts(coarse=G.COARSE_VCYCLE, nu1=1, nu2=1, tol=1e-10, precision=G.MIXED_FP32)
+    gp.setup(bw, o32)
+    assert gp.n >= 1 << 19
+    u = synth.initial_guess(d, p, m, seed=1)
+    b = synth.rhs_normal(d, p, m, seed=0)
+    out, sol = {}, {}
+    for stream in ("1", "0"):
+        monkeypatch.setenv("IGA2L_COLOUR_STREAM", stream)
+        ug = dev(u)
+        gp.smooth(ug, dev(b), 1, G.Opts(ordering=G.COLOUR, colour_period=bw))
+        out[stream] = host(ug)
+        if bw < 7:
+            sol[stream] = gp.solve(dev(b), opts=o32)
+    e = rel(out["1"], out["0"])
+    # the same inverses on both sides: only the residual's summation order differs
+    assert e < (1e-11 if bw == 7 else 1e-12), e
+    if bw == 7:
+        print(f"[streamed colour] sweep rel {e:.2e}", flush=True)
+        return
+    es = rel(host(sol["1"][0]), host(sol["0"][0]))
+    print(f"[streamed colour] sweep rel {e:.2e}; mixed solve cycles {sol['1'][1].iters} / {sol['0'][1].iters}, "
+          f"relres {sol['1'][1].relres:.2e}, solution difference {es:.2e}", flush=True)
+    assert sol["1"][1].relres <= 1e-10
+    assert abs(sol["1"][1].iters - sol["0"][1].iters) <= 1
+    assert es < 1e-4
 
 
 def _oracle_residual_offsets(d, p, m, kappa, u, b):
