@@ -110,10 +110,10 @@ def roofline_large(torch, G, m, p=3):
     registers): residual 24 B/DOF (u, b read, r written); restriction 8 B per
     fine DOF read + 8 B per coarse DOF written; prolongation 16 B per fine DOF
     (u read and written) + 8 B per coarse DOF; one Schwarz colour 24 B/DOF
-    (iterate read and written, right-hand side read).  Averages over many
+    (iterate read and written, right-hand side read; 12 B/DOF in FP32).  Averages over many
     launches, HIP events on the stream the library launches on."""
     prob = G.Problem(2, p, m, device=0)
-    prob.setup(0, G.Opts(coarse=G.COARSE_DIRECT))
+    prob.setup(0, G.Opts(coarse=G.COARSE_DIRECT, precision=G.MIXED_FP32))
     n, nc = prob.n, prob.nc
     gen = torch.Generator(device="cuda").manual_seed(0)
     u = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
@@ -128,8 +128,11 @@ def roofline_large(torch, G, m, p=3):
     out["k_restrict"] = _rl(8.0 * n + 8.0 * nc, t)
     t = event_time(torch, lambda: prob.prolong_add(dc, u), 20)
     out["k_prolong_add"] = _rl(16.0 * n + 8.0 * nc, t)
-    t = event_time(torch, lambda: prob.smooth(u, b, 1, G.Opts()), 5) / 9.0
-    out["k_colour"] = _rl(24.0 * n, t)
+    # one Schwarz colour (the streamed kernel at this size), timed by HIP
+    # events inside the library on its launch stream: FP64, and FP32 as in the
+    # correction cycle of the mixed solve (12 B/DOF)
+    out["k_colour"] = _rl(24.0 * n, prob.time_colour(G.FP64, 5))
+    out["k_colour_fp32"] = _rl(12.0 * n, prob.time_colour(G.MIXED_FP32, 5))
     # a plain device copy of one vector: calibrates byte counters (FETCH_SIZE /
     # WRITE_SIZE of this kernel against its known 8n bytes each way)
     v = torch.empty_like(u)

@@ -164,7 +164,11 @@ __global__ void __launch_bounds__(kCsNT)
 #pragma unroll
                     for (int k = 0; k < RY; ++k) {
                         const int oy = yy - k;
-                        if (oy >= 0 && oy < W1) acc[k] += cf[oy] * mx + cf[W1 + oy] * kx;
+                        if (oy >= 0 && oy < W1) {
+                            // two fused multiply-adds into the accumulator
+                            acc[k] += cf[oy] * mx;
+                            acc[k] += cf[W1 + oy] * kx;
+                        }
                     }
                 }
             } else {
@@ -203,31 +207,40 @@ __global__ void __launch_bounds__(kCsNT)
         }
         if (more) store_ring(c + 1);
         __syncthreads();
-        // x += (row of the block's inverse) . (the block's residuals)
+        // x += (row of the block's inverse) . (the block's residuals), per cell
+        // row: its residuals read once, then one inverse row per output
         if (col_in && gyb < y1) {
 #pragma unroll
-            for (int k = 0; k < RY; ++k) {
-                const int j = k / B, kk = k % B;  // the thread's cell row and the row in it
-                const int gy = gyb + k;
-                if (gy < 0 || gy >= y1) continue;
-                const int ccy = gyb + j * B + HB;
-                const bool covered = clx >= 0 && ccy >= 0 && ccy < n1;
-                const int cly = covered ? block_class(ccy, n1, clsL) : 0;
+            for (int j = 0; j < RY / B; ++j) {
+                const int cb = gyb + j * B;  // the cell's first row
+                const int ccy = cb + HB;
                 const T *rblk = rs + (ty * RY + j * B) * TX + cell0;
-                T delta = T(0);
-                if (covered) {
-                    const int loc = cx + B * kk;
+                T rv[BD], delta[B];
+#pragma unroll
+                for (int l = 0; l < BD; ++l) rv[l] = rblk[(l / B) * TX + l % B];
+#pragma unroll
+                for (int kk = 0; kk < B; ++kk) delta[kk] = T(0);
+                if (clx >= 0 && ccy >= 0 && ccy < n1) {
+                    const int cly = block_class(ccy, n1, clsL);
                     if (kLdsInv && clx == clsL && cly == clsL) {
-                        const T *irow = ivs + loc * BD;
+                        const T *irow = ivs + cx * BD;
 #pragma unroll
-                        for (int l = 0; l < BD; ++l) delta += irow[l] * rblk[(l / B) * TX + l % B];
+                        for (int kk = 0; kk < B; ++kk)
+#pragma unroll
+                            for (int l = 0; l < BD; ++l) delta[kk] += irow[kk * B * BD + l] * rv[l];
                     } else {
-                        const T *irow = inv + ((int64_t(clx) + int64_t(ncls1) * cly) * BD + loc) * BD;
+                        const T *irow = inv + ((int64_t(clx) + int64_t(ncls1) * cly) * BD + cx) * BD;
 #pragma unroll
-                        for (int l = 0; l < BD; ++l) delta += irow[l] * rblk[(l / B) * TX + l % B];
+                        for (int kk = 0; kk < B; ++kk)
+#pragma unroll
+                            for (int l = 0; l < BD; ++l) delta[kk] += irow[kk * B * BD + l] * rv[l];
                     }
                 }
-                x_dst[int64_t(gy) * n1 + gx] = xc[k] + delta;
+#pragma unroll
+                for (int kk = 0; kk < B; ++kk) {
+                    const int gy = cb + kk;
+                    if (gy >= 0 && gy < y1) x_dst[int64_t(gy) * n1 + gx] = xc[j * B + kk] + delta[kk];
+                }
             }
         }
         if (more) {
