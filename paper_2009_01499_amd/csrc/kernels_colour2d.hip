@@ -5,8 +5,8 @@
 // With s = b every point lies in exactly one b x b block of the colour, so a
 // colour is: r = f - A x on every point, then x += A_blk^{-1} r_blk per block.
 // A workgroup owns a strip of whole cells (63 or 60 columns) and a segment of
-// rows; it walks the segment in chunks of four thread rows of one or two cell
-// rows each (two for 3 x 3 blocks: fewer window rows per output).  The x rows of a
+// rows; it walks the segment in chunks of four thread rows of one to three
+// cell rows each (more for 3 x 3 blocks: fewer window rows per output).  The x rows of a
 // chunk's window sit in an LDS ring, the next chunk's rows (and right-hand
 // side) are loaded into registers while the current chunk computes, the
 // residual of the chunk's cells goes to LDS, and each point then applies its
@@ -28,27 +28,36 @@ namespace iga2l {
 namespace {
 
 constexpr int kCsTXT = 64, kCsTYT = 4, kCsNT = kCsTXT * kCsTYT;
-constexpr int kCsTargetGroups = 8192;
-// cell rows per thread: two for 3 x 3 blocks where the chunk window still
-// fits the 32-row ring (fewer window rows per output), one otherwise
-template <int P, int B>
-constexpr int kCellRows = (B == 3 && kCsTYT * 2 * B + 2 * P <= 32) ? 2 : 1;
-
+constexpr int kCsTargetGroups = 16384;
+// cell rows per thread: for 3 x 3 blocks two (FP64) or three (FP32, whose
+// registers are half the size) where the chunk window fits a 32- or 64-row
+// ring (fewer window rows per output), one otherwise
 template <int P, int B, class T>
-__global__ void __launch_bounds__(kCsNT)
+constexpr int kCellRows = (B != 3) ? 1
+                          : (sizeof(T) == 4 && kCsTYT * 3 * B + 2 * P <= 64) ? 3
+                          : (kCsTYT * 2 * B + 2 * P <= 32) ? 2 : 1;
+
+// ONE: every segment is a single chunk (the launch shape of large grids
+// with the default workgroup target), so no rows are prefetched and the
+// registers that would hold them go to occupancy
+template <int P, int B, class T, bool ONE>
+__global__ void __launch_bounds__(kCsNT, (ONE && B == 3) ? 5 : 1)
     k_colour2d_stream(const T *__restrict__ fac, const T *__restrict__ cf, int n1, int ulo, int uhi,
                       const T *__restrict__ inv, int clsL, int ncls1, const T *__restrict__ x_src,
                       T *__restrict__ x_dst, const T *__restrict__ rhs, int ox, int oy, int nsx, int nseg,
                       int seg_rows, const int *__restrict__ skip) {
     constexpr int TX = (kCsTXT / B) * B;  // strip columns: whole cells
-    constexpr int RY = kCellRows<P, B> * B;  // rows per thread: whole cell rows
+    constexpr int RY = kCellRows<P, B, T> * B;  // rows per thread: whole cell rows
     constexpr int CH = kCsTYT * RY;          // chunk rows
     constexpr int HX = TX + 2 * P;
     constexpr int W1 = 2 * P + 1, BD = B * B, HB = (B - 1) / 2;
-    constexpr int RING = (CH + 2 * P <= 32) ? 32 : 64;
+    // a single chunk's window exactly, else a power of two holding one
+    constexpr int RING = ONE ? CH + 2 * P : (CH + 2 * P <= 32) ? 32 : 64;
     constexpr bool kLdsInv = BD * BD * sizeof(T) <= 8192;
     static_assert(CH + 2 * P <= RING, "ring holds the window");
     __shared__ T ring[RING * HX];
+    // ring slot of window row q (the single-chunk window does not wrap)
+    auto slot = [](int q) { return ONE ? q : (q & (RING - 1)); };
     __shared__ T rs[CH * TX];
     __shared__ T ivs[kLdsInv ? BD * BD : 1];
     if (skip && *skip) return;
@@ -56,7 +65,7 @@ __global__ void __launch_bounds__(kCsNT)
     xcd_relabel(int(blockIdx.x), nsx, nsx * nseg, bx, bs);
     const int gx0 = ox + bx * TX, y0 = oy + bs * seg_rows;
     const int y1 = min(y0 + seg_rows, n1);
-    const int nch = (y1 - y0 + CH - 1) / CH;
+    const int nch = ONE ? 1 : (y1 - y0 + CH - 1) / CH;
     const int tid = int(threadIdx.x);
     const int tx = tid % kCsTXT;
     // the thread row is the wavefront's: rows and their 1-D factors are uniform
@@ -102,7 +111,7 @@ __global__ void __launch_bounds__(kCsNT)
 #pragma unroll
             for (int u = 0; u < NI; ++u) {
                 const int j = ty + kCsTYT * u, y = ybase + j;
-                ring[((q + j) & (RING - 1)) * HX + P + tx] = (col_in && y >= 0 && y < n1) ? xi[u] : T(0);
+                ring[slot(q + j) * HX + P + tx] = (col_in && y >= 0 && y < n1) ? xi[u] : T(0);
             }
         }
 #pragma unroll
@@ -110,7 +119,7 @@ __global__ void __launch_bounds__(kCsNT)
             const int t = tid + u * kCsNT, j = t % CH, hc = t / CH;
             const int gxh = halo_col(hc), y = ybase + j;
             if (t < 2 * P * CH)
-                ring[((q + j) & (RING - 1)) * HX + (hc < P ? hc : TX + hc)] =
+                ring[slot(q + j) * HX + (hc < P ? hc : TX + hc)] =
                     (gxh >= 0 && gxh < n1 && y >= 0 && y < n1) ? xh[u] : T(0);
         }
     };
@@ -153,7 +162,7 @@ __global__ void __launch_bounds__(kCsNT)
                 // the x sums pair the entries o and 2P - o
 #pragma unroll
                 for (int yy = 0; yy < RY + 2 * P; ++yy) {
-                    const T *row = ring + ((q0 + yy) & (RING - 1)) * HX + tx;
+                    const T *row = ring + slot(q0 + yy) * HX + tx;
                     T kx = cf[P] * row[P], mx = cf[W1 + P] * row[P];
 #pragma unroll
                     for (int o = 0; o < P; ++o) {
@@ -176,7 +185,7 @@ __global__ void __launch_bounds__(kCsNT)
                 // would leave the grid are zero there)
 #pragma unroll 1
                 for (int yy = 0; yy < RY + 2 * P; ++yy) {
-                    const T *row = ring + ((q0 + yy) & (RING - 1)) * HX + tx;
+                    const T *row = ring + slot(q0 + yy) * HX + tx;
                     T mx = T(0), kx = T(0);
 #pragma unroll
                     for (int o = 0; o < W1; ++o) {
@@ -195,7 +204,7 @@ __global__ void __launch_bounds__(kCsNT)
                 }
             }
 #pragma unroll
-            for (int k = 0; k < RY; ++k) xc[k] = ring[((q0 + P + k) & (RING - 1)) * HX + P + tx];
+            for (int k = 0; k < RY; ++k) xc[k] = ring[slot(q0 + P + k) * HX + P + tx];
         }
         __syncthreads();  // the ring rows and the residuals of the last chunk are read
         if (act) {
@@ -264,7 +273,7 @@ int colour2d_segment_rows(int64_t n1, int tx, int ch) {
 template <int P, int B, class T>
 void colour2d_stream_launch(const Problem &Pb, int cx, int cy, const T *x_src, T *x_dst, const T *rhs,
                             hipStream_t s) {
-    constexpr int TX = (kCsTXT / B) * B, CH = kCsTYT * kCellRows<P, B> * B, HB = (B - 1) / 2;
+    constexpr int TX = (kCsTXT / B) * B, CH = kCsTYT * kCellRows<P, B, T> * B, HB = (B - 1) / 2;
     const int n1 = Pb.fine.n1;
     // strip and segment origins: aligned with the colour's blocks, at or before 0
     int ox = cx - HB, oy = cy - HB;
@@ -272,11 +281,12 @@ void colour2d_stream_launch(const Problem &Pb, int cx, int cy, const T *x_src, T
     if (oy > 0) oy -= B;
     const int seg_rows = colour2d_segment_rows(n1, TX, CH);
     const int nsx = (n1 - ox + TX - 1) / TX, nseg = (n1 - oy + seg_rows - 1) / seg_rows;
+    auto kern = seg_rows == CH ? k_colour2d_stream<P, B, T, true> : k_colour2d_stream<P, B, T, false>;
     constexpr bool f64 = std::is_same<T, double>::value;
     const T *fac = reinterpret_cast<const T *>(f64 ? Pb.fac64.ptr : Pb.fac32.ptr);
     const T *cf = reinterpret_cast<const T *>(f64 ? Pb.cf64.ptr : Pb.cf32.ptr);
     const T *inv = reinterpret_cast<const T *>(f64 ? Pb.Inv64.ptr : Pb.Inv32.ptr);
-    hipLaunchKernelGGL((k_colour2d_stream<P, B, T>), dim3(nsx * nseg), dim3(kCsNT), 0, s, fac, cf, n1, Pb.ulo, Pb.uhi,
+    hipLaunchKernelGGL(kern, dim3(nsx * nseg), dim3(kCsNT), 0, s, fac, cf, n1, Pb.ulo, Pb.uhi,
                        inv, class_split(Pb), Pb.ncls1, x_src, x_dst, rhs, ox, oy, nsx, nseg, seg_rows, Pb.skip);
 }
 
