@@ -553,12 +553,14 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
         P.lumped_default = o.lumped != 0;
         IGA2L_HIP(hipDeviceSynchronize());
         // tile shapes of the coloured sweep, timed once per working precision
+        // (not where every colour of the sweep runs the streamed kernel)
         const int S = o.colour_period ? o.colour_period : P.bw;
-        if (P.dim == 2 && !P.tuned[0]) {
+        const bool streamed = colour2d_stream_ok(P, S);
+        if (P.dim == 2 && !P.tuned[0] && !streamed) {
             autotune_colour_tile<double>(P, S, s);
             P.tuned[0] = true;
         }
-        if (P.dim == 2 && P.fp32_ready && !P.tuned[1]) {
+        if (P.dim == 2 && P.fp32_ready && !P.tuned[1] && !streamed) {
             autotune_colour_tile<float>(P, S, s);
             P.tuned[1] = true;
         }

@@ -421,10 +421,12 @@ void launch_colour3d_sf(const Problem &P, int cx, int cy, int cz, const T *x_src
 template <class T, bool NORM>
 void launch_residual3d_sf(const Problem &P, const T *x, const T *b, T *r, double *partial, hipStream_t s);
 // 2-D kappa = 1 on large grids (kernels_colour2d.hip): one Schwarz colour with
-// colour period b, streamed along y; false (nothing launched) where it does
-// not apply
+// colour period b, streamed along y (from a zero iterate: tiles of whole
+// cells without a halo); false (nothing launched) where it does not apply.
+// colour2d_stream_ok: whether it applies to period S.
+bool colour2d_stream_ok(const Problem &P, int S);
 bool colour2d_stream(const Problem &P, int cx, int cy, int S, const void *x_src, void *x_dst, const void *rhs,
-                     bool fp64, hipStream_t s);
+                     bool x_zero, const double *r64, void *rhs_out, bool fp64, hipStream_t s);
 // 2-D bandwidth-oriented variants (kernels_2d.hip)
 template <class T>
 void launch_residual2d(const Problem &P, const T *val, const T *x, const T *b, T *r, double *partial, hipStream_t s);

@@ -259,6 +259,86 @@ __global__ void __launch_bounds__(kCsNT, (ONE && B == 3) ? 5 : 1)
     }
 }
 
+// The first colour of a sweep from a zero iterate (x_zero): the residual is
+// the right-hand side itself (or r64 / sigma, cast to T and stored to rhs_out
+// for the later colours), so a workgroup needs no halo: a tile of whole cells
+// (the strip width by four thread rows of one cell row) loads its residuals
+// to LDS and applies the block inverses, x = A_blk^{-1} r_blk.  The block
+// solve is the streamed colour's, in the same summation order.
+template <int B, class T>
+__global__ void __launch_bounds__(kCsNT)
+    k_colour2d_zero(const T *__restrict__ inv, int clsL, int ncls1, int n1, const T *__restrict__ rhs,
+                    const double *__restrict__ r64, const double *__restrict__ scal, T *__restrict__ rhs_out,
+                    T *__restrict__ x_dst, int ox, int oy, int nsx, int nty, const int *__restrict__ skip) {
+    constexpr int TX = (kCsTXT / B) * B, CH = kCsTYT * B, BD = B * B, HB = (B - 1) / 2;
+    constexpr bool kLdsInv = BD * BD * sizeof(T) <= 8192;
+    __shared__ T rs[CH * TX];
+    __shared__ T ivs[kLdsInv ? BD * BD : 1];
+    if (skip && *skip) return;
+    int bx, by;
+    xcd_relabel(int(blockIdx.x), nsx, nsx * nty, bx, by);
+    const int gx0 = ox + bx * TX;
+    const int tid = int(threadIdx.x), tx = tid % kCsTXT;
+    const int ty = __builtin_amdgcn_readfirstlane(tid / kCsTXT);
+    const int gyb = oy + by * CH + ty * B;  // the thread's cell row
+    const bool act = tx < TX;
+    const int gx = gx0 + tx;
+    const bool col_in = act && gx >= 0 && gx < n1;
+    if constexpr (kLdsInv) {
+        const int64_t islot = int64_t(clsL) + int64_t(ncls1) * clsL;
+        for (int h = tid; h < BD * BD; h += kCsNT) ivs[h] = inv[islot * BD * BD + h];
+    }
+    if (act) {
+        const double inv_sigma = r64 ? scal[kScalInvSigma] : 1.0;
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int gy = gyb + k;
+            T v = T(0);
+            if (col_in && gy >= 0 && gy < n1) {
+                const int64_t gi = int64_t(gy) * n1 + gx;
+                if (r64) {
+                    v = T(r64[gi] * inv_sigma);
+                    rhs_out[gi] = v;
+                } else {
+                    v = rhs[gi];
+                }
+            }
+            rs[(ty * B + k) * TX + tx] = v;
+        }
+    }
+    __syncthreads();
+    if (!col_in || gyb >= n1) return;
+    const int cx = tx % B, cell0 = (tx / B) * B;
+    const int ccx = gx0 + cell0 + HB, ccy = gyb + HB;
+    const T *rblk = rs + ty * B * TX + cell0;
+    T rv[BD], delta[B];
+#pragma unroll
+    for (int l = 0; l < BD; ++l) rv[l] = rblk[(l / B) * TX + l % B];
+#pragma unroll
+    for (int kk = 0; kk < B; ++kk) delta[kk] = T(0);
+    if (ccx >= 0 && ccx < n1 && ccy >= 0 && ccy < n1) {
+        const int clx = block_class(ccx, n1, clsL), cly = block_class(ccy, n1, clsL);
+        if (kLdsInv && clx == clsL && cly == clsL) {
+            const T *irow = ivs + cx * BD;
+#pragma unroll
+            for (int kk = 0; kk < B; ++kk)
+#pragma unroll
+                for (int l = 0; l < BD; ++l) delta[kk] += irow[kk * B * BD + l] * rv[l];
+        } else {
+            const T *irow = inv + ((int64_t(clx) + int64_t(ncls1) * cly) * BD + cx) * BD;
+#pragma unroll
+            for (int kk = 0; kk < B; ++kk)
+#pragma unroll
+                for (int l = 0; l < BD; ++l) delta[kk] += irow[kk * B * BD + l] * rv[l];
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < B; ++kk) {
+        const int gy = gyb + kk;
+        if (gy >= 0 && gy < n1) x_dst[int64_t(gy) * n1 + gx] = delta[kk];
+    }
+}
+
 int colour2d_segment_rows(int64_t n1, int tx, int ch) {
     int64_t target = kCsTargetGroups;
     // IGA2L_COLOUR_GROUPS sets another workgroup target (tests use a small one
@@ -290,6 +370,31 @@ void colour2d_stream_launch(const Problem &Pb, int cx, int cy, const T *x_src, T
                        inv, class_split(Pb), Pb.ncls1, x_src, x_dst, rhs, ox, oy, nsx, nseg, seg_rows, Pb.skip);
 }
 
+template <int B, class T>
+void colour2d_zero_launch(const Problem &Pb, int cx, int cy, const T *rhs, const double *r64, T *rhs_out, T *x_dst,
+                          hipStream_t s) {
+    constexpr int TX = (kCsTXT / B) * B, CH = kCsTYT * B, HB = (B - 1) / 2;
+    const int n1 = Pb.fine.n1;
+    int ox = cx - HB, oy = cy - HB;
+    if (ox > 0) ox -= B;
+    if (oy > 0) oy -= B;
+    const int nsx = (n1 - ox + TX - 1) / TX, nty = (n1 - oy + CH - 1) / CH;
+    constexpr bool f64 = std::is_same<T, double>::value;
+    const T *inv = reinterpret_cast<const T *>(f64 ? Pb.Inv64.ptr : Pb.Inv32.ptr);
+    hipLaunchKernelGGL((k_colour2d_zero<B, T>), dim3(nsx * nty), dim3(kCsNT), 0, s, inv, class_split(Pb), Pb.ncls1, n1,
+                       rhs, r64, Pb.scal.as<double>(), rhs_out, x_dst, ox, oy, nsx, nty, Pb.skip);
+}
+
+template <class T>
+void colour2d_zero_b(const Problem &Pb, int cx, int cy, const T *rhs, const double *r64, T *rhs_out, T *x_dst,
+                     hipStream_t s) {
+    switch (Pb.bw) {
+        case 3: colour2d_zero_launch<3, T>(Pb, cx, cy, rhs, r64, rhs_out, x_dst, s); break;
+        case 5: colour2d_zero_launch<5, T>(Pb, cx, cy, rhs, r64, rhs_out, x_dst, s); break;
+        default: colour2d_zero_launch<7, T>(Pb, cx, cy, rhs, r64, rhs_out, x_dst, s); break;
+    }
+}
+
 template <int P, class T>
 void colour2d_stream_b(const Problem &Pb, int cx, int cy, const T *x_src, T *x_dst, const T *rhs, hipStream_t s) {
     switch (Pb.bw) {
@@ -315,8 +420,7 @@ void colour2d_stream_p(const Problem &Pb, int cx, int cy, const T *x_src, T *x_d
 
 }  // namespace
 
-bool colour2d_stream(const Problem &P, int cx, int cy, int S, const void *x_src, void *x_dst, const void *rhs,
-                     bool fp64, hipStream_t s) {
+bool colour2d_stream_ok(const Problem &P, int S) {
     // IGA2L_COLOUR_STREAM=0 in the environment keeps the tiled kernel (read at
     // every launch, so that tests can compare the two in one process)
     const char *v = std::getenv("IGA2L_COLOUR_STREAM");
@@ -328,6 +432,22 @@ bool colour2d_stream(const Problem &P, int cx, int cy, int S, const void *x_src,
     const size_t ic = size_t(P.fine.n1 / 2) * w1;
     for (int o = 0; o < P.p; ++o)
         if (P.K1[ic + o] != P.K1[ic + 2 * P.p - o] || P.M1[ic + o] != P.M1[ic + 2 * P.p - o]) return false;
+    return true;
+}
+
+bool colour2d_stream(const Problem &P, int cx, int cy, int S, const void *x_src, void *x_dst, const void *rhs,
+                     bool x_zero, const double *r64, void *rhs_out, bool fp64, hipStream_t s) {
+    if (!colour2d_stream_ok(P, S)) return false;
+    if (x_zero) {
+        if (fp64)
+            colour2d_zero_b<double>(P, cx, cy, static_cast<const double *>(rhs), r64, static_cast<double *>(rhs_out),
+                                    static_cast<double *>(x_dst), s);
+        else
+            colour2d_zero_b<float>(P, cx, cy, static_cast<const float *>(rhs), r64, static_cast<float *>(rhs_out),
+                                   static_cast<float *>(x_dst), s);
+        return true;
+    }
+    if (r64) return false;
     if (fp64)
         colour2d_stream_p<double>(P, cx, cy, static_cast<const double *>(x_src), static_cast<double *>(x_dst),
                                   static_cast<const double *>(rhs), s);

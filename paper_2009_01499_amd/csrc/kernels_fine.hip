@@ -999,11 +999,11 @@ void defect_dp(const Problem &Pb, const T *e, const T *rhs, T *d, hipStream_t s)
 template <int D, int P, int B, class T>
 void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_src, T *x_dst, const T *rhs,
                    bool x_zero, const double *r64, T *rhs_out, hipStream_t s, int tile_nbx = 0, int tile_nby = 0) {
-    // 2-D kappa = 1 on large grids, colour period b, from a given iterate:
-    // streamed (the tile shapes the autotuner times are for this kernel)
+    // 2-D kappa = 1 on large grids, colour period b: streamed (explicit tile
+    // shapes ask for this kernel)
     if constexpr (D == 2)
-        if (!x_zero && !r64 && tile_nbx == 0 && tile_nby == 0 &&
-            colour2d_stream(Pb, cx, cy, S, x_src, x_dst, rhs, std::is_same<T, double>::value, s))
+        if (tile_nbx == 0 && tile_nby == 0 &&
+            colour2d_stream(Pb, cx, cy, S, x_src, x_dst, rhs, x_zero, r64, rhs_out, std::is_same<T, double>::value, s))
             return;
     if constexpr (D == 3 && B == 3) if (colour3d_sf_ok(Pb, S)) {
         // kappa = 1, colour period 3: sum-factorised residual, shared inverse on MFMA

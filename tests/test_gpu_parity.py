@@ -466,14 +466,17 @@ def test_large_grid_kernels_sampled(groups, monkeypatch):
 
 
 @pytest.mark.parametrize("p,bw,m,groups", [(2, 3, 730, "40"), (5, 5, 722, None), (5, 5, 722, "40"),
-                                           (8, 7, 719, None), (8, 7, 719, "40")])
+                                           (8, 7, 719, None), (8, 7, 719, "40"), (5, 3, 722, None),
+                                           (3, 7, 1024, None)])
 def test_large_grid_streamed_colour(p, bw, m, groups, monkeypatch):
     """The streamed Schwarz colour (grids of 2^19 DOFs and more, kappa = 1,
     colour period b) for each block width against the tiled kernel, which the
     small-grid cases and the 1024^2 golden compare with the oracle: one FP64
     coloured sweep from a random iterate, and mixed-precision solves (whose
-    FP32 correction sweeps take the streamed colour after the first) with the
-    same cycle count.  With 7x7 blocks at p = 8 the period-b iteration
+    FP32 correction sweeps start with the zero-iterate colour, which takes
+    its residual from the cast FP64 residual without a halo) with the same
+    cycle count.  Block widths other than the default (3x3 at p = 5, 7x7 at
+    p = 3) run the instances with one cell row per thread.  With 7x7 blocks at p = 8 the period-b iteration
     diverges (the oracle's too: 60 cycles at m = 40 end near 1e100), so that
     case compares the sweep only.  With a target of 40 workgroups each strip
     runs many chunks through its ring."""
