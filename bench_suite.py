@@ -8,6 +8,8 @@ as one JSON line each (the headline line of bench.py stays the first line).
   C5  2-D p=4 256x256 GRF kappa: forward mixed solve + adjoint gradient
   AGG 2-D 256x256, p = 2..5, the paper's timed configuration: aggressive
       coarsening (degree 1 on 2h) with one V(1,1) cycle there
+  LARGE 2-D p=3 at 2048^2 and 4096^2 (4.2 M and 16.8 M DOFs), V(2,2) coarse, FP64
+      and mixed: the bandwidth regime (streamed kernels) on the whole solve
   ANN quarter annulus (NURBS, Section 5.2), 32^2 .. 256^2, p = 3..8, degree-2
       coarse space solved exactly, coloured Schwarz with period b+2 (the
       shortest period that converges like non-interacting colours on the
@@ -132,6 +134,16 @@ def run(torch, G, steps=5, only=None):
                                {"fp64": G.Opts(**v11a), "mixed": G.Opts(precision=G.MIXED_FP32, **v11a)}, steps,
                                oracle_ref=_oracle_c2(2, p, 256, (1, 1), aggressive=True))
             line["paper_table4_iterations_1e-8_context"] = {2: 6, 3: 6, 4: 7, 5: 5}[p]
+            lines.append(line)
+    if want("LARGE"):
+        for m in (2048, 4096):
+            line = _solve_line(torch, G, "LARGE", 2, 3, m,
+                               {"fp64": G.Opts(**v22), "mixed": G.Opts(precision=G.MIXED_FP32, **v22)},
+                               max(2, steps // 4),
+                               oracle_ref=lambda b_np, sols: {"mixed_vs_fp64": _error_vs(sols["fp64"], sols["mixed"])})
+            # no oracle solution at this size (its set-up alone takes minutes): the
+            # mixed solution against the FP64 one instead
+            line["difference"] = line.pop("error_vs_oracle")
             lines.append(line)
     if want("ANN"):
         lines.extend(_annulus(torch, G, steps))
