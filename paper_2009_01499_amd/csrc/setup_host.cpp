@@ -847,7 +847,13 @@ void host_build_levels(Problem &P) {
         IGA2L_HIP(hipMemcpy(L.invd64.ptr, inv.data(), n * sizeof(double), hipMemcpyHostToDevice));
         IGA2L_HIP(hipMemcpy(L.invd32.ptr, inv32.data(), n * sizeof(float), hipMemcpyHostToDevice));
         // translation invariance: every row carries the centre row's coefficients
-        // on all of its in-grid neighbours (rows are truncated at the boundary)
+        // on all of its in-grid neighbours (rows are truncated at the boundary),
+        // to 1e-12 of the largest: the element matrices next to the boundary are
+        // computed on their own, and their rounding grows with m (the centre
+        // coefficient of the last row of the degree-1 operator is 2.6666666666668792
+        // against 2.6666666666666679 at m = 4096); the smoother then reads no
+        // stored stencil on such a level
+        constexpr double kCstTol = 1e-12;
         L.cst = false;
         double ref[27] = {0};
         if (n1 >= 3) {
@@ -869,11 +875,19 @@ void host_build_levels(Problem &P) {
                         int j = ix[k] + o[k] - 1;
                         if (j < 0 || j >= n1) in = false;
                     }
-                    if (in && std::fabs(S[size_t(w) * n + i] - ref[w]) > 1e-14 * scale) same = false;
+                    if (in && std::fabs(S[size_t(w) * n + i] - ref[w]) > kCstTol * scale) {
+                        same = false;
+                        if (tune_log())
+                            std::fprintf(stderr, "[iga2l setup] level %zu row %lld offset %d: %.17g against %.17g\n",
+                                         l, (long long)i, w, S[size_t(w) * n + i], ref[w]);
+                    }
                 }
             }
             L.cst = same;
         }
+        if (tune_log())
+            std::fprintf(stderr, "[iga2l setup] V-cycle level %zu: n1=%d, %s stencil\n", l, n1,
+                         L.cst ? "constant" : "stored");
         const size_t nb = size_t(n) * sizeof(double);
         L.e[0].alloc(nb);
         L.e[1].alloc(nb);
