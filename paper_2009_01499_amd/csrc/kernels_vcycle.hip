@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 
 #include "internal.h"
@@ -205,14 +206,25 @@ __global__ void __launch_bounds__(256) k_rb_step(LevelDev<T> L, const T *__restr
 // ring's half steps then need one pass), launches with many tiles take 256
 // (two instantiations, each compiled for its own register budget)
 inline bool rb_wide(int64_t tiles) { return tiles < 1024; }
+// levels with at least this many points per direction take 64 x 16 tiles
+// (512 threads): the halo ring of a fused step costs about half as much per
+// point, and such levels still give thousands of workgroups.  The result of
+// every point is the same bits for any tile shape.
+constexpr int kRbBigN1 = 1024;
+// IGA2L_RB_BIG_N1 in the environment sets another threshold (read at every
+// launch: tests send small levels through the large tiles)
+inline int rb_big_n1() {
+    const char *v = std::getenv("IGA2L_RB_BIG_N1");
+    return v ? std::max(1, std::atoi(v)) : kRbBigN1;
+}
 
 // The body serves the single-problem kernel and the batched one (tile bx, by).
-template <class T, int NU, bool RESTRICT>
+template <class T, int NU, bool RESTRICT, int TX = 32, int TY = 8>
 __device__ __forceinline__ void rb_multi2_body(const LevelDev<T> &L, const T *__restrict__ e_src, int zero_src,
                                                const T *__restrict__ ec, int n1c_interp, const T *__restrict__ rhs,
                                                T *__restrict__ e_dst, T *__restrict__ rc, int n1c,
                                                const int *__restrict__ skip, int bx, int by) {
-    constexpr int TX = 32, TY = 8;
+    static_assert(TX % 2 == 0 && TY % 2 == 0, "whole coarse cells per tile");
     constexpr int H = 2 * NU + (RESTRICT ? 2 : 0);
     constexpr int HX = TX + 2 * H, HY = TY + 2 * H, NH = HX * HY;
     __shared__ T buf[2][NH];
@@ -304,14 +316,14 @@ __device__ __forceinline__ void rb_multi2_body(const LevelDev<T> &L, const T *__
     }
 }
 
-template <class T, int NU, bool RESTRICT, int NT>
+template <class T, int NU, bool RESTRICT, int NT, int TX = 32, int TY = 8>
 __global__ void __launch_bounds__(NT) k_rb_multi2(LevelDev<T> L, const T *__restrict__ e_src, int zero_src,
                                                    const T *__restrict__ ec, int n1c_interp,
                                                    const T *__restrict__ rhs, T *__restrict__ e_dst,
                                                    T *__restrict__ rc, int n1c, const int *__restrict__ skip) {
     int bx, by;
     xcd_tile_2d(bx, by);
-    rb_multi2_body<T, NU, RESTRICT>(L, e_src, zero_src, ec, n1c_interp, rhs, e_dst, rc, n1c, skip, bx, by);
+    rb_multi2_body<T, NU, RESTRICT, TX, TY>(L, e_src, zero_src, ec, n1c_interp, rhs, e_dst, rc, n1c, skip, bx, by);
 }
 
 // batched: pre-smoothing + residual restriction (RESTRICT) or prolongation +
@@ -769,6 +781,14 @@ void vcycle_top(Problem &P, size_t l, const T *rhs, T *e_out, int nu1, int nu2, 
 template <class T, int NU, bool RESTRICT>
 void launch_rb_multi2(const Problem &P, const LevelDev<T> &Ld, const T *e_src, bool zero_src, const T *ec,
                       int n1c_interp, const T *rhs, T *e_dst, T *rc, int n1c, hipStream_t s) {
+    if constexpr (NU <= 2) if (Ld.n1 >= rb_big_n1()) {
+        // large levels: 64 x 16 tiles, about half the halo work per point of 32 x 8
+        // (up to two steps: the LDS of the tile and its halo stays under 64 KB)
+        const dim3 grid(nblk(Ld.n1, 64), nblk(Ld.n1, 16), 1);
+        hipLaunchKernelGGL((k_rb_multi2<T, NU, RESTRICT, 512, 64, 16>), grid, dim3(512), 0, s, Ld, e_src,
+                           zero_src ? 1 : 0, ec, n1c_interp, rhs, e_dst, rc, n1c, P.skip);
+        return;
+    }
     const dim3 grid(nblk(Ld.n1, 32), nblk(Ld.n1, 8), 1);
     if (rb_wide(grid.x * grid.y))
         hipLaunchKernelGGL((k_rb_multi2<T, NU, RESTRICT, 1024>), grid, dim3(1024), 0, s, Ld, e_src, zero_src ? 1 : 0,

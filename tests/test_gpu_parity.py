@@ -150,6 +150,30 @@ def test_vcycle_parity(d, m, kap, nu):
     assert e < 1e-12, e
 
 
+@pytest.mark.parametrize("m,kap", [(64, None), (33, "grf"), (128, "grf")])
+def test_vcycle_large_level_tiles(m, kap, monkeypatch):
+    """The fused red-black launches of levels with at least 1024 points per
+    direction take 64 x 16 tiles instead of 32 x 8; every point's arithmetic
+    is the same, so the V-cycle gives the same bits.  The threshold is moved
+    down here so that these small levels take the large tiles (m = 33 leaves
+    partial tiles on every edge): against the oracle at 1e-12 and bit for bit
+    against the default tiles, for V(1,1) and V(2,2)."""
+    kappa = synth.kappa_grf(2, m, 1.0, 0.1, seed=9) if kap else None
+    G, orc, gp = _pair(2, 2, m, kappa, vcycle=True, direct=False)
+    dc = synth.rhs_normal(2, 1, m, seed=2)
+    for nu in ((1, 1), (2, 2)):
+        o = G.Opts(coarse=G.COARSE_VCYCLE, nu1=nu[0], nu2=nu[1])
+        monkeypatch.delenv("IGA2L_RB_BIG_N1", raising=False)
+        ref = host(gp.coarse_solve(dev(dc), opts=o))
+        monkeypatch.setenv("IGA2L_RB_BIG_N1", "8")
+        big = host(gp.coarse_solve(dev(dc), opts=o))
+        e = rel(big, orc.coarse_vcycle(dc, *nu))
+        print(f"[V-cycle big tiles] m={m} nu={nu}: against the oracle {e:.2e}, "
+              f"bitwise equal {np.array_equal(big, ref)}", flush=True)
+        assert e < 1e-12, e
+        assert np.array_equal(big, ref)
+
+
 @pytest.mark.parametrize("d,m", [(2, 32), (2, 17), (3, 6)])
 def test_direct_coarse_parity(d, m):
     G, orc, gp = _pair(d, 3 if d == 2 else 2, m, vcycle=False, direct=True)
