@@ -56,7 +56,11 @@ typedef struct {
     int max_cycles;      /* upper bound on two-level cycles */
     int ordering;        /* IGA2L_LEX (one block at a time, lexicographic) or IGA2L_COLOUR */
     int colour_period;   /* COLOUR only: period s >= block width; 0 selects s = block width */
-    int coarse;          /* IGA2L_COARSE_DIRECT (kappa = 1 only) or IGA2L_COARSE_VCYCLE */
+    int coarse;          /* IGA2L_COARSE_DIRECT or IGA2L_COARSE_VCYCLE.  DIRECT solves the coarse
+                            space exactly: kappa = 1 by the DST-I (fast diagonalisation for
+                            plow = 2); variable kappa (plow = 1, at most 4096 coarse unknowns,
+                            else EUNSUPPORTED at set-up) by a banded Cholesky factorisation of
+                            A_1 at set-up, whose inverse the solve applies */
     int nu1, nu2;        /* pre-/post-smoothing steps of the coarse V-cycle (paper: 1, 1) */
     int precision;       /* IGA2L_FP64, or IGA2L_MIXED_FP32: FP64 residual and accumulation,
                             FP32 smoother, defect, transfers and V-cycle */

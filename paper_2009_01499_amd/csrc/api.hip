@@ -542,8 +542,8 @@ int iga2l_setup_blocks(iga2l_problem *prob, int block_width, const iga2l_opts *o
                           "unknowns)");
             if (o.coarse == IGA2L_COARSE_DIRECT && !P.agg_direct_ready) host_build_agg_direct(P);
         } else if (o.coarse == IGA2L_COARSE_DIRECT && !P.direct_ready) {
-            IGA2L_REQUIRE(P.kappa_one || P.geometry == kGeomAnnulus, IGA2L_EUNSUPPORTED,
-                          "the exact coarse solve needs kappa = 1; use the V-cycle for variable kappa");
+            IGA2L_REQUIRE(P.kappa_one || P.geometry == kGeomAnnulus || P.plow == 1, IGA2L_EUNSUPPORTED,
+                          "the exact coarse solve with variable kappa needs the degree-1 coarse space");
             host_build_dst(P);
         }
         if (!o.lumped && !P.mass_ready) {

@@ -162,6 +162,7 @@ struct Problem {
     size_t vc_bottom64 = 0, vc_bottom32 = 0;  // first level run by the one-workgroup kernel
     bool vcycle_ready = false;
     DevBuf dst_S, dst_mu;         // DST-I matrix [n1c][n1c], eigenvalues [n_c]
+    DevBuf coarse_inv64;          // variable kappa: A_1^{-1} [n_c][n_c] (exact coarse solve), else empty
     bool direct_ready = false;
     // exact (not lumped) transfers: the degree-1 mass matrix M_1 is diagonalised
     // by the same DST-I; dstM_mu holds its eigenvalues (products of the 1-D
@@ -370,7 +371,9 @@ void solve_batch_fused(Problem *const *probs, int nprob, const double *const *b,
 enum { kGeomSquare = 0, kGeomAnnulus = 1 };
 void host_assemble(Problem &P);                 // 1-D factors, DIA, transfers, kappa
 void host_build_levels(Problem &P);             // V-cycle hierarchy (Galerkin)
-void host_build_dst(Problem &P);                // exact coarse solver (kappa = 1)
+void host_build_dst(Problem &P);                // exact coarse solver
+// largest coarse space with variable kappa solved exactly (dense inverse)
+constexpr int64_t kCoarseInvMax = 4096;
 void host_build_mass(Problem &P);               // exact M_low^{-1} transfers (DST-I / fast diagonalisation)
 void host_transfer_factors(Problem &P, int plow);  // 1-D transfer factors, coarse grid of degree plow
 void host_coarse_workspaces(Problem &P);        // coarse vectors sized by the coarse grid

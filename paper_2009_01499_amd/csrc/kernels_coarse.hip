@@ -421,8 +421,30 @@ void dst_apply_2h(Problem &P, const double *d, double *e, double *t1, hipStream_
     dst_apply(P.dst2_S.as<double>(), P.dst2_mu.as<double>(), P.levels[1].g.n1, P.dim, d, e, t1, P.skip, s);
 }
 
+// e = Z d for a dense n x n matrix Z (row-major): one wavefront per row
+__global__ void __launch_bounds__(256) k_dense_apply(const double *__restrict__ Z, int64_t n,
+                                                     const double *__restrict__ d, double *__restrict__ e,
+                                                     const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t row = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    if (row >= n) return;  // whole wavefronts
+    const double *z = Z + row * n;
+    double acc = 0.0;
+    for (int64_t j = lane; j < n; j += 64) acc += z[j] * d[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) e[row] = acc;
+}
+
 void launch_dst_solve(Problem &P, const double *d, double *e, hipStream_t s) {
     IGA2L_REQUIRE(P.direct_ready, IGA2L_EINVAL, "exact coarse solver not set up");
+    if (P.plow == 1 && P.coarse_inv64.ptr) {
+        // variable kappa: the inverse formed from the banded Cholesky factor
+        const int64_t n = P.coarse.n;
+        hipLaunchKernelGGL(k_dense_apply, dim3(unsigned((n + 3) / 4)), dim3(256), 0, s, P.coarse_inv64.as<double>(),
+                           n, d, e, P.skip);
+        return;
+    }
     if (P.plow == 2)
         dst_apply(P.fdm_Vt.as<double>(), P.dst_mu.as<double>(), P.coarse.n1, P.dim, d, e, P.ctmp.as<double>(), P.skip,
                   s, P.fdm_V.as<double>(), P.fdm_axis_stride);

@@ -605,6 +605,7 @@ void host_set_coarse_degree(Problem &P, int plow) {
     }
     host_coarse_workspaces(P);
     P.vcycle_ready = P.direct_ready = P.mass_ready = P.agg_direct_ready = false;
+    P.coarse_inv64.free();
     P.levels.clear();
     P.levhost64.clear();
     P.levhost32.clear();
@@ -780,6 +781,29 @@ void host_build_fdm(Problem &P) {
 // stencil.  Coarser levels: coarse nodes are the odd-indexed interior nodes
 // (0-based) of the finer level, P = linear interpolation, A_c = P^T A P,
 // down to a single node per direction.
+// The degree-1 operator on the fine knots with the element coefficients
+// kappa, [3^d][(m-1)^d], assembled on the device.
+static DevBuf assemble_degree1(Problem &P) {
+    const int d = P.dim, m = P.m;
+    // degree-1 element matrices: K = (1/h)[1 -1; -1 1], M = (h/6)[2 1; 1 2]
+    std::vector<std::vector<double>> Kc, Mc;
+    element_matrices(1, m, Kc, Mc);
+    std::vector<double> km1(size_t(m) * 8);
+    for (int el = 0; el < m; ++el)
+        for (int k = 0; k < 4; ++k) {
+            km1[(size_t(el) * 2 + 0) * 4 + k] = Kc[el][k];
+            km1[(size_t(el) * 2 + 1) * 4 + k] = Mc[el][k];
+        }
+    DevBuf km1_d;
+    km1_d.alloc(km1.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(km1_d.ptr, km1.data(), km1.size() * sizeof(double), hipMemcpyHostToDevice));
+    DevBuf S0;
+    S0.alloc(size_t(ipow(3, d)) * ipow(m - 1, d) * sizeof(double));
+    launch_assemble_q1(d, km1_d.as<double>(), P.kappa_d.as<double>(), m, S0.as<double>(), nullptr);
+    IGA2L_HIP(hipDeviceSynchronize());
+    return S0;
+}
+
 void host_build_levels(Problem &P) {
     const int d = P.dim, m = P.m;
     const int W3 = int(ipow(3, d));
@@ -788,26 +812,8 @@ void host_build_levels(Problem &P) {
     // most kCoarsestMax unknowns; host copies for the per-level book-keeping
     std::vector<DevBuf> dops;
     std::vector<int> sizes;
-    DevBuf km1_d;
-    {
-        // degree-1 element matrices: K = (1/h)[1 -1; -1 1], M = (h/6)[2 1; 1 2]
-        std::vector<std::vector<double>> Kc, Mc;
-        element_matrices(1, m, Kc, Mc);
-        std::vector<double> km1(size_t(m) * 8);
-        for (int el = 0; el < m; ++el)
-            for (int k = 0; k < 4; ++k) {
-                km1[(size_t(el) * 2 + 0) * 4 + k] = Kc[el][k];
-                km1[(size_t(el) * 2 + 1) * 4 + k] = Mc[el][k];
-            }
-        km1_d.alloc(km1.size() * sizeof(double));
-        IGA2L_HIP(hipMemcpy(km1_d.ptr, km1.data(), km1.size() * sizeof(double), hipMemcpyHostToDevice));
-        const int n1 = m - 1;
-        DevBuf S0;
-        S0.alloc(size_t(W3) * ipow(n1, d) * sizeof(double));
-        launch_assemble_q1(d, km1_d.as<double>(), P.kappa_d.as<double>(), m, S0.as<double>(), nullptr);
-        dops.push_back(std::move(S0));
-        sizes.push_back(n1);
-    }
+    dops.push_back(assemble_degree1(P));
+    sizes.push_back(m - 1);
     while (ipow(sizes.back(), d) > kCoarsestMax) {
         const int nf1 = sizes.back(), nc1 = nf1 / 2;
         DevBuf Sc;
@@ -1032,9 +1038,83 @@ static void dst_tables(int m, int d, bool stiffness, DevBuf &Sd, DevBuf &mud) {
     IGA2L_HIP(hipMemcpy(mud.ptr, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice));
 }
 
+// Variable kappa, degree-1 coarse space: A_1 (the degree-1 operator with the
+// element coefficients) factored by banded Cholesky, L L^T with L(i, i-k) for
+// k <= bw = the largest stencil offset; then A_1^{-1} column by column (one
+// banded forward and one backward solve each), uploaded as a dense matrix
+// that the exact coarse solve applies on the device.  O(n bw^2) for the
+// factor and O(n^2 bw) for the inverse: bounded by kCoarseInvMax unknowns.
+static void host_build_coarse_inverse(Problem &P) {
+    const int d = P.dim, n1 = P.m - 1;
+    const int W3 = int(ipow(3, d));
+    const int64_t n = ipow(n1, d);
+    IGA2L_REQUIRE(n <= kCoarseInvMax, IGA2L_EUNSUPPORTED,
+                  "the exact coarse solve with variable kappa is limited to 4096 coarse unknowns; use the V-cycle");
+    DevBuf S0 = assemble_degree1(P);
+    std::vector<double> S(size_t(W3) * n);
+    IGA2L_HIP(hipMemcpy(S.data(), S0.ptr, S.size() * sizeof(double), hipMemcpyDeviceToHost));
+    int64_t bw = 0;  // offset of the (+1, +1, +1) neighbour
+    for (int k = 0; k < d; ++k) bw = bw * n1 + 1;
+    const int64_t w1 = bw + 1;
+    // A(i, i-k) for 0 <= k <= bw, row i: from the stencil entries of row i
+    std::vector<double> Lb(size_t(n) * w1, 0.0);
+    int ix[kMaxDim] = {0, 0, 0}, o[kMaxDim] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        split(i, d, n1, ix);
+        for (int w = 0; w < W3; ++w) {
+            split(w, d, 3, o);
+            bool in = true;
+            int64_t j = 0;
+            for (int k = d - 1; k >= 0; --k) {
+                const int jk = ix[k] + o[k] - 1;
+                if (jk < 0 || jk >= n1) in = false;
+                j = j * n1 + jk;
+            }
+            if (in && j <= i) Lb[size_t(i) * w1 + (i - j)] = S[size_t(w) * n + i];
+        }
+    }
+    auto L = [&](int64_t i, int64_t j) -> double & { return Lb[size_t(i) * w1 + (i - j)]; };
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t j0 = std::max<int64_t>(0, i - bw);
+        for (int64_t j = j0; j <= i; ++j) {
+            double t = L(i, j);
+            for (int64_t k = std::max(j0, j - bw); k < j; ++k) t -= L(i, k) * L(j, k);
+            if (j == i) {
+                IGA2L_REQUIRE(t > 0.0, IGA2L_ENUMERIC, "coarse operator is not positive definite");
+                L(i, i) = std::sqrt(t);
+            } else {
+                L(i, j) = t / L(j, j);
+            }
+        }
+    }
+    std::vector<double> Zi(size_t(n) * n), col(n);
+    for (int64_t c = 0; c < n; ++c) {
+        std::fill(col.begin(), col.end(), 0.0);
+        col[c] = 1.0;
+        for (int64_t i = c; i < n; ++i) {
+            double t = col[i];
+            for (int64_t k = std::max(c, i - bw); k < i; ++k) t -= L(i, k) * col[k];
+            col[i] = t / L(i, i);
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double t = col[i];
+            for (int64_t k = i + 1; k <= std::min(n - 1, i + bw); ++k) t -= L(k, i) * col[k];
+            col[i] = t / L(i, i);
+        }
+        for (int64_t i = 0; i < n; ++i) Zi[size_t(i) * n + c] = col[i];
+    }
+    P.coarse_inv64.alloc(Zi.size() * sizeof(double));
+    IGA2L_HIP(hipMemcpy(P.coarse_inv64.ptr, Zi.data(), Zi.size() * sizeof(double), hipMemcpyHostToDevice));
+    P.direct_ready = true;
+}
+
 void host_build_dst(Problem &P) {
     if (P.plow == 2) {
         host_build_fdm(P);
+        return;
+    }
+    if (!P.kappa_one && P.geometry == kGeomSquare) {
+        host_build_coarse_inverse(P);
         return;
     }
     dst_tables(P.m, P.dim, true, P.dst_S, P.dst_mu);

@@ -48,7 +48,8 @@ def _pair(d, p, m, kappa=None, bw=0, vcycle=True, direct=True, mixed=False, lump
     extra = dict(precision=G.MIXED_FP32 if mixed else G.FP64, lumped=lumped, aggressive=aggressive, plow=plow)
     if vcycle:
         gp.setup(bw, G.Opts(coarse=G.COARSE_VCYCLE, **extra))
-    if direct and kappa is None:
+    # the exact coarse solve takes variable kappa up to 4096 coarse unknowns
+    if direct and (kappa is None or (m - 1) ** d <= 4096):
         gp.setup(bw, G.Opts(coarse=G.COARSE_DIRECT, **extra))
     if not vcycle and not direct:
         gp.setup(bw, G.Opts(**extra))
@@ -174,9 +175,14 @@ def test_vcycle_large_level_tiles(m, kap, monkeypatch):
         assert np.array_equal(big, ref)
 
 
-@pytest.mark.parametrize("d,m", [(2, 32), (2, 17), (3, 6)])
-def test_direct_coarse_parity(d, m):
-    G, orc, gp = _pair(d, 3 if d == 2 else 2, m, vcycle=False, direct=True)
+@pytest.mark.parametrize("d,m,kap", [(2, 32, None), (2, 17, None), (3, 6, None), (2, 32, "grf"), (2, 17, "grf"),
+                                     (3, 9, "grf"), (2, 65, "grf")])
+def test_direct_coarse_parity(d, m, kap):
+    """Exact coarse solve against the oracle's banded Cholesky: the DST-I for
+    kappa = 1; for kappa = exp(GRF) the inverse that the set-up forms from a
+    banded Cholesky factor of A_1 (m = 65: 4096 coarse unknowns, the limit)."""
+    kappa = synth.kappa_grf(d, m, 1.0, 0.1, seed=9) if kap else None
+    G, orc, gp = _pair(d, 3 if d == 2 else 2, m, kappa, vcycle=False, direct=True)
     dc = synth.rhs_normal(d, 1, m, seed=2)
     ec = host(gp.coarse_solve(dev(dc), opts=G.Opts(coarse=G.COARSE_DIRECT)))
     e = rel(ec, orc.coarse_direct(dc))
@@ -347,6 +353,9 @@ def test_mixed_precision_variants_reach_tolerance(aggr, lumped):
     ("3d-interior-vcycle22", 3, 3, 12, None, "colour", 0, "vcycle", (2, 2)),
     ("3d-interior-direct", 3, 2, 10, None, "colour", 0, "direct", (1, 1)),
     ("3d-interior-b+p", 3, 3, 16, None, "colour", 6, "vcycle", (1, 1)),
+    ("grf-direct", 2, 3, 24, "grf", "colour", 0, "direct", (1, 1)),
+    ("C1-grf-lex-direct", 2, 3, 32, "grf", "lex", 0, "direct", (1, 1)),
+    ("3d-grf-direct", 3, 2, 8, "grf", "colour", 0, "direct", (1, 1)),
 ])
 def test_cycle_iterates_parity(name, d, p, m, kap, ordering, period, coarse, nu):
     kappa = synth.kappa_grf(d, m, 1.0, 0.1, seed=5) if kap else None
