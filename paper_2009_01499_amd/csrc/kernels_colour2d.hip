@@ -259,10 +259,15 @@ __global__ void __launch_bounds__(kCsNT, (ONE && B == 3) ? 5 : 1)
     }
 }
 
+// cell rows per thread of the zero-start colour: two for 3 x 3 blocks (more
+// loads in flight per thread), one otherwise
+template <int B>
+constexpr int kZeroCellRows = (B == 3) ? 2 : 1;
+
 // The first colour of a sweep from a zero iterate (x_zero): the residual is
 // the right-hand side itself (or r64 / sigma, cast to T and stored to rhs_out
 // for the later colours), so a workgroup needs no halo: a tile of whole cells
-// (the strip width by four thread rows of one cell row) loads its residuals
+// (the strip width by four thread rows of whole cell rows) loads its residuals
 // to LDS and applies the block inverses, x = A_blk^{-1} r_blk.  The block
 // solve is the streamed colour's, in the same summation order.
 template <int B, class T>
@@ -270,7 +275,7 @@ __global__ void __launch_bounds__(kCsNT)
     k_colour2d_zero(const T *__restrict__ inv, int clsL, int ncls1, int n1, const T *__restrict__ rhs,
                     const double *__restrict__ r64, const double *__restrict__ scal, T *__restrict__ rhs_out,
                     T *__restrict__ x_dst, int ox, int oy, int nsx, int nty, const int *__restrict__ skip) {
-    constexpr int TX = (kCsTXT / B) * B, CH = kCsTYT * B, BD = B * B, HB = (B - 1) / 2;
+    constexpr int TX = (kCsTXT / B) * B, RY = kZeroCellRows<B> * B, CH = kCsTYT * RY, BD = B * B, HB = (B - 1) / 2;
     constexpr bool kLdsInv = BD * BD * sizeof(T) <= 8192;
     __shared__ T rs[CH * TX];
     __shared__ T ivs[kLdsInv ? BD * BD : 1];
@@ -280,7 +285,7 @@ __global__ void __launch_bounds__(kCsNT)
     const int gx0 = ox + bx * TX;
     const int tid = int(threadIdx.x), tx = tid % kCsTXT;
     const int ty = __builtin_amdgcn_readfirstlane(tid / kCsTXT);
-    const int gyb = oy + by * CH + ty * B;  // the thread's cell row
+    const int gyb = oy + by * CH + ty * RY;  // the thread's first cell row
     const bool act = tx < TX;
     const int gx = gx0 + tx;
     const bool col_in = act && gx >= 0 && gx < n1;
@@ -291,7 +296,7 @@ __global__ void __launch_bounds__(kCsNT)
     if (act) {
         const double inv_sigma = r64 ? scal[kScalInvSigma] : 1.0;
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
+        for (int k = 0; k < RY; ++k) {
             const int gy = gyb + k;
             T v = T(0);
             if (col_in && gy >= 0 && gy < n1) {
@@ -303,39 +308,43 @@ __global__ void __launch_bounds__(kCsNT)
                     v = rhs[gi];
                 }
             }
-            rs[(ty * B + k) * TX + tx] = v;
+            rs[(ty * RY + k) * TX + tx] = v;
         }
     }
     __syncthreads();
     if (!col_in || gyb >= n1) return;
     const int cx = tx % B, cell0 = (tx / B) * B;
-    const int ccx = gx0 + cell0 + HB, ccy = gyb + HB;
-    const T *rblk = rs + ty * B * TX + cell0;
-    T rv[BD], delta[B];
+    const int ccx = gx0 + cell0 + HB;
 #pragma unroll
-    for (int l = 0; l < BD; ++l) rv[l] = rblk[(l / B) * TX + l % B];
+    for (int j = 0; j < RY / B; ++j) {
+        const int cb = gyb + j * B, ccy = cb + HB;  // the cell's first row and centre
+        const T *rblk = rs + (ty * RY + j * B) * TX + cell0;
+        T rv[BD], delta[B];
 #pragma unroll
-    for (int kk = 0; kk < B; ++kk) delta[kk] = T(0);
-    if (ccx >= 0 && ccx < n1 && ccy >= 0 && ccy < n1) {
-        const int clx = block_class(ccx, n1, clsL), cly = block_class(ccy, n1, clsL);
-        if (kLdsInv && clx == clsL && cly == clsL) {
-            const T *irow = ivs + cx * BD;
+        for (int l = 0; l < BD; ++l) rv[l] = rblk[(l / B) * TX + l % B];
 #pragma unroll
-            for (int kk = 0; kk < B; ++kk)
+        for (int kk = 0; kk < B; ++kk) delta[kk] = T(0);
+        if (ccx >= 0 && ccx < n1 && ccy >= 0 && ccy < n1) {
+            const int clx = block_class(ccx, n1, clsL), cly = block_class(ccy, n1, clsL);
+            if (kLdsInv && clx == clsL && cly == clsL) {
+                const T *irow = ivs + cx * BD;
 #pragma unroll
-                for (int l = 0; l < BD; ++l) delta[kk] += irow[kk * B * BD + l] * rv[l];
-        } else {
-            const T *irow = inv + ((int64_t(clx) + int64_t(ncls1) * cly) * BD + cx) * BD;
+                for (int kk = 0; kk < B; ++kk)
 #pragma unroll
-            for (int kk = 0; kk < B; ++kk)
+                    for (int l = 0; l < BD; ++l) delta[kk] += irow[kk * B * BD + l] * rv[l];
+            } else {
+                const T *irow = inv + ((int64_t(clx) + int64_t(ncls1) * cly) * BD + cx) * BD;
 #pragma unroll
-                for (int l = 0; l < BD; ++l) delta[kk] += irow[kk * B * BD + l] * rv[l];
+                for (int kk = 0; kk < B; ++kk)
+#pragma unroll
+                    for (int l = 0; l < BD; ++l) delta[kk] += irow[kk * B * BD + l] * rv[l];
+            }
         }
-    }
 #pragma unroll
-    for (int kk = 0; kk < B; ++kk) {
-        const int gy = gyb + kk;
-        if (gy >= 0 && gy < n1) x_dst[int64_t(gy) * n1 + gx] = delta[kk];
+        for (int kk = 0; kk < B; ++kk) {
+            const int gy = cb + kk;
+            if (gy >= 0 && gy < n1) x_dst[int64_t(gy) * n1 + gx] = delta[kk];
+        }
     }
 }
 
@@ -373,7 +382,7 @@ void colour2d_stream_launch(const Problem &Pb, int cx, int cy, const T *x_src, T
 template <int B, class T>
 void colour2d_zero_launch(const Problem &Pb, int cx, int cy, const T *rhs, const double *r64, T *rhs_out, T *x_dst,
                           hipStream_t s) {
-    constexpr int TX = (kCsTXT / B) * B, CH = kCsTYT * B, HB = (B - 1) / 2;
+    constexpr int TX = (kCsTXT / B) * B, CH = kCsTYT * kZeroCellRows<B> * B, HB = (B - 1) / 2;
     const int n1 = Pb.fine.n1;
     int ox = cx - HB, oy = cy - HB;
     if (ox > 0) ox -= B;
