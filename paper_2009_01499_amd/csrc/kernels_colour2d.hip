@@ -6,15 +6,20 @@
 // colour is: r = f - A x on every point, then x += A_blk^{-1} r_blk per block.
 // A workgroup owns a strip of whole cells (63 or 60 columns) and a segment of
 // rows; it walks the segment in chunks of four thread rows of one to three
-// cell rows each (more for 3 x 3 blocks: fewer window rows per output).  The x rows of a
-// chunk's window sit in an LDS ring, the next chunk's rows (and right-hand
-// side) are loaded into registers while the current chunk computes, the
-// residual of the chunk's cells goes to LDS, and each point then applies its
-// row of its block's inverse.  Interior rows apply A = K1 (x) M1 + M1 (x) K1
-// by sum factorisation from the interior 1-D rows (symmetric: the x sums add
-// the two entries that share a weight first); wavefronts that touch the
-// frame of points within ulo of the boundary take every 1-D row from the
-// factors.  The interior blocks' shared inverse is staged in LDS (b <= 5).
+// cell rows each (more for 3 x 3 blocks: fewer window rows per output).  The
+// x rows of a chunk's window sit in an LDS ring, the next chunk's rows (and
+// right-hand side) are loaded into registers while the current chunk
+// computes, the residual of the chunk's cells goes to LDS, and each point
+// then applies its row of its block's inverse.  Interior rows apply
+// A = K1 (x) M1 + M1 (x) K1 by sum factorisation from the interior 1-D rows
+// (symmetric: the x sums add the two entries that share a weight first);
+// wavefronts that touch the frame of points within ulo of the boundary take
+// every 1-D row from the factors.  The interior blocks' shared inverse is
+// staged in LDS (b <= 5).  With the default workgroup target every segment
+// is one chunk on large grids (more workgroups in flight measured faster
+// than longer streams), which an instance without the prefetch registers
+// serves; the first colour of a sweep from a zero iterate has a kernel of
+// its own (no halo).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
