@@ -187,8 +187,8 @@ def event_time(torch, fn, reps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): sharding the path over "
+              "several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
 
