@@ -257,6 +257,8 @@ std::unique_ptr<Plan> build_plan(const std::vector<Problem *> &probs, const iga2
         q.inv[1] = P.Inv32.ptr;
         q.cs[0] = P.cs64.ptr;
         q.cs[1] = P.cs32.ptr;
+        q.fac[0] = colour_factor_rows(P, true);
+        q.fac[1] = colour_factor_rows(P, false);
         q.R1[0] = P.R1d64.ptr;
         q.R1[1] = P.R1d32.ptr;
         q.cls = P.cls_d.as<int>();

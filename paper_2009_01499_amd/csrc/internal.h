@@ -196,7 +196,7 @@ struct Problem {
     DevBuf cs64, cs32;            // interior stencil of kappa = 1 rows, (2p+1)^d (empty otherwise)
     DevBuf kron64, kron32;        // kappa = 1, 3-D: K1 then M1, [n1][2p+1] each (empty otherwise)
     DevBuf cf64, cf32;            // kappa = 1: interior row of K1 then of M1, 2 (2p+1) (empty otherwise)
-    DevBuf fac64, fac32;          // kappa = 1, 2-D: K1 then M1, [n1][2p+1] each (empty otherwise)
+    DevBuf fac64, fac32;          // kappa = 1, 2-D: K1, M1, K1, M1, [n1][2p+1] each (empty otherwise)
     DevBuf fac2d64, fac2d32;      // annulus: rows of K1, M1, K1y, M1y, [n1][2p+1] each (empty otherwise)
     int ulo = 1, uhi = 0;         // rows with all coordinates in [ulo, uhi] carry that stencil
     DevBuf scal;                  // status block: kScalCount doubles, kFlagCount ints, hist_cap doubles
@@ -294,6 +294,7 @@ enum VecRole { kVecU, kVecB, kVecR64, kVecE0, kVecE1, kVecRhsW, kVecDFine, kVecD
 
 struct BatchProb {
     const void *val[2], *inv[2], *cs[2], *R1[2];   // [0] FP64, [1] FP32 (null if not set up)
+    const void *fac[2];                            // the Schwarz colour's 1-D factor rows (colour_factor_rows)
     const int *cls;
     int clsL;                                      // block classes: L of shared inverses, -1 = one per position
     int64_t npad;
@@ -355,7 +356,12 @@ void launch_rb_multi2_batch(const BatchLevel<T> *bl, const int2 *map, int nwg, i
                             hipStream_t s);
 template <class T>
 void launch_vcycle_bottom_batch(const BatchBottom<T> *bb, int nprob, size_t shm, int nu1, int nu2, hipStream_t s);
-size_t colour_lds(int p, int S, int nbx, int nby, size_t elem);
+size_t colour_lds(int p, int S, int nbx, int nby, size_t elem, bool factor_rows);
+// the 1-D factor rows from which the 2-D Schwarz colour forms every operator
+// row (rows of Kx, Mx, Ky, My, [n1][2p+1] each): the quarter annulus's, and a
+// kappa = 1 square's on grids below the streamed sizes; null: the stencil and
+// the stored diagonals
+const void *colour_factor_rows(const Problem &P, bool fp64);
 void colour_tile_clamp(int S, int &nbx, int &nby);
 
 // grows the status block so that it holds cap cycles of history

@@ -1031,7 +1031,8 @@ void colour_launch(const Problem &Pb, int cx, int cy, int cz, int S, const T *x_
     if (oz > 0) oz -= S;
     dim3 grid((n1 - ox + TX - 1) / TX, (n1 - oy + TY - 1) / TY, D == 3 ? (n1 - oz + TZ - 1) / TZ : 1);
     const int threads = ((TX * TY * TZ + kWave - 1) / kWave) * kWave;
-    const T *fac2 = kron_factors<T>(Pb);
+    const T *fac2 = (D == 2) ? static_cast<const T *>(colour_factor_rows(Pb, std::is_same<T, double>::value))
+                             : kron_factors<T>(Pb);
     const size_t sf2_lds = (D == 2 && fac2) ? 2 * size_t(TY + 2 * Pb.p) * TX : 0;
     const size_t shm = (size_t(TX + 2 * Pb.p) * (TY + 2 * Pb.p) * (D == 3 ? TZ + 2 * Pb.p : 1) + size_t(TX) * TY * TZ +
                         size_t(cpow(2 * P + 1, D)) + sf2_lds) *
@@ -1185,7 +1186,8 @@ __global__ void __launch_bounds__(kColourThreads) kb_colour(const BatchProb *__r
                             0, S, nbx, nby, 1, static_cast<const T *>(q.cs[pr]), q.ulo, q.uhi,
                             use_skip ? q.flags : nullptr,
                             fuse ? static_cast<const double *>(q.vec[kVecR64]) : nullptr, q.scal,
-                            fuse ? static_cast<T *>(q.vec[kVecRhsW]) : nullptr, bx, by, 0, smem_raw);
+                            fuse ? static_cast<T *>(q.vec[kVecRhsW]) : nullptr, bx, by, 0, smem_raw,
+                            static_cast<const T *>(q.fac[pr]));
 }
 
 }  // namespace
@@ -1315,9 +1317,20 @@ void colour_tile_clamp(int S, int &nbx, int &nby) {
     }
 }
 
-size_t colour_lds(int p, int S, int nbx, int nby, size_t elem) {
+size_t colour_lds(int p, int S, int nbx, int nby, size_t elem, bool factor_rows) {
     const size_t TX = size_t(nbx) * S, TY = size_t(nby) * S, W = size_t(2 * p + 1) * (2 * p + 1);
-    return ((TX + 2 * p) * (TY + 2 * p) + TX * TY + W) * elem;
+    const size_t sf2 = factor_rows ? 2 * (TY + 2 * p) * TX : 0;
+    return ((TX + 2 * p) * (TY + 2 * p) + TX * TY + W + sf2) * elem;
+}
+
+const void *colour_factor_rows(const Problem &P, bool fp64) {
+    if (P.dim != 2) return nullptr;
+    if (P.geometry == kGeomAnnulus) return fp64 ? P.fac2d64.ptr : P.fac2d32.ptr;
+    // kappa = 1 square: measured faster than the stencil and stored diagonals
+    // on the latency-bound grids (the wavefronts next to the boundary no
+    // longer read (2p+1)^2 diagonals); the large tiled instance keeps them
+    if (P.fine.n >= kColourPreMaxN) return nullptr;
+    return fp64 ? P.fac64.ptr : P.fac32.ptr;
 }
 
 template <int P, class T, bool NORM>
@@ -1368,7 +1381,8 @@ void launch_colour_batch(const BatchProb *bp, const int2 *map, int nwg, int p, i
                          int cy, int S, int role_src, int role_dst, int role_rhs, bool x_zero, bool fuse,
                          hipStream_t s, bool use_skip) {
     const int threads = ((nbx * S * nby * S + kWave - 1) / kWave) * kWave;
-    const size_t shm = colour_lds(p, S, nbx, nby, sizeof(T));
+    // (room for the factor rows' x sums: some problems of the table may use them)
+    const size_t shm = colour_lds(p, S, nbx, nby, sizeof(T), true);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(nwg), dim3(threads), shm, s, bp, map, nbx, nby, cx, cy, S, role_src, role_dst,
                            role_rhs, x_zero ? 1 : 0, fuse ? 1 : 0, use_skip ? 1 : 0);

@@ -492,8 +492,12 @@ void host_assemble(Problem &P) {
         IGA2L_HIP(hipMemcpy(P.cf64.ptr, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice));
         IGA2L_HIP(hipMemcpy(P.cf32.ptr, cf32.data(), cf32.size() * sizeof(float), hipMemcpyHostToDevice));
         if (d == 2) {
-            // every row of both factors, for the rows next to the boundary
+            // every row of both factors, for the rows next to the boundary,
+            // then again as the y factors: A = K1 (x) M1 + M1 (x) K1 in the
+            // layout of the direction-dependent factors of the annulus
             std::vector<double> fac(P.K1);
+            fac.insert(fac.end(), P.M1.begin(), P.M1.end());
+            fac.insert(fac.end(), P.K1.begin(), P.K1.end());
             fac.insert(fac.end(), P.M1.begin(), P.M1.end());
             std::vector<float> fac32(fac.begin(), fac.end());
             P.fac64.alloc(fac.size() * sizeof(double));
