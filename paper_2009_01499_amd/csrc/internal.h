@@ -358,7 +358,8 @@ template <class T>
 void launch_vcycle_bottom_batch(const BatchBottom<T> *bb, int nprob, size_t shm, int nu1, int nu2, hipStream_t s);
 size_t colour_lds(int p, int S, int nbx, int nby, size_t elem, bool factor_rows);
 // the 1-D factor rows from which the 2-D Schwarz colour forms every operator
-// row (rows of Kx, Mx, Ky, My, [n1][2p+1] each): the quarter annulus's, and a
+// row, and the tiled residual the rows of its wavefronts next to the boundary
+// (rows of Kx, Mx, Ky, My, [n1][2p+1] each): the quarter annulus's, and a
 // kappa = 1 square's on grids below the streamed sizes; null: the stencil and
 // the stored diagonals
 const void *colour_factor_rows(const Problem &P, bool fp64);

@@ -946,7 +946,9 @@ void residual_launch(const Problem &Pb, const T *val, const T *x, const T *b, T 
     nblocks = int(grid.x * grid.y * grid.z);
     hipLaunchKernelGGL((k_residual<D, P, T, NORM>), grid, dim3(TS::TX * TS::TY * TS::TZ), shm, s, val, Pb.A.npad,
                        Pb.A.pitch[1], Pb.A.pitch[2], n1, TS::TX, TS::TY, TS::TZ, x, b, r, partial,
-                       uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip, kron_factors<T>(Pb));
+                       uniform_stencil<T>(Pb), Pb.ulo, Pb.uhi, Pb.skip,
+                       (D == 2) ? static_cast<const T *>(colour_factor_rows(Pb, std::is_same<T, double>::value))
+                                : kron_factors<T>(Pb));
     if (NORM)
         hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, Pb.partial.as<double>(), nblocks,
                            Pb.scal.as<double>(), scale_fp32 ? 1 : 0, book ? dev_flags(Pb) : nullptr, dev_hist(Pb),
@@ -1151,7 +1153,7 @@ __global__ void __launch_bounds__(256) kb_residual(const BatchProb *__restrict__
                                  static_cast<const T *>(q.vec[role_x]), static_cast<const T *>(q.vec[role_b]),
                                  static_cast<T *>(q.vec[role_r]), NORM ? q.partial + m.y : nullptr,
                                  static_cast<const T *>(q.cs[pr]), q.ulo, q.uhi, use_skip ? q.flags : nullptr, bx,
-                                 by, 0, reinterpret_cast<T *>(smem_raw));
+                                 by, 0, reinterpret_cast<T *>(smem_raw), static_cast<const T *>(q.fac[pr]));
 }
 
 __global__ void __launch_bounds__(256) kb_norm_finalize(const BatchProb *__restrict__ bp, int scale_fp32, int book) {
