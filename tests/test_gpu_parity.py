@@ -70,7 +70,10 @@ def sweep_tolerance(orc):
     return 1e-12 if orc.block_width <= 5 else 5e-11
 
 
-CASES_2D = [(2, 3, 32, None), (2, 2, 33, None), (2, 5, 20, None), (2, 4, 24, "grf"), (2, 7, 14, None)]
+# (kappa = 1 with n1 >= 4p-1: the operator rows are formed from the 1-D factor
+# rows on these latency-bound sizes; p = 6 and 8 bring 5x5 and 7x7 blocks)
+CASES_2D = [(2, 3, 32, None), (2, 2, 33, None), (2, 5, 20, None), (2, 4, 24, "grf"), (2, 7, 14, None),
+            (2, 6, 24, None), (2, 8, 28, None)]
 
 
 # 3-D, kappa = 1: grids with n1 = m+p-2 >= 4p-1 contain rows whose coordinates all
